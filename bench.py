@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Throughput of Bluebild standard synthesis on one MI355X.
+
+Workload (default): the LOFAR-like single-channel configuration -- 512
+stations over 50 km, 100 epochs over 6 h of Earth rotation, 1024 x 1024
+pixels over 10 degrees, all 512 eigenpairs in 8 positive + 1 negative
+k-means levels, complex64 contraction with FP64 phase arguments.  Inputs are
+synthetic (seeded sims), built on the host; the eigenpairs come from the
+library's own FP64 GPU pre-step before the timed region.
+
+A step is one pass of the synthesis hot path over the whole job (staging of
+every epoch plus one batched synthesis launch over all 100 epochs), with all
+inputs resident in HBM.  Prints one JSON line on stdout; progress goes to
+stderr.
+
+    python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x3]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+FP32_PEAK_TFLOPS = 157.3      # MI355X dense FP32 matrix
+BF16_PEAK_TFLOPS = 2516.6     # MI355X dense BF16 matrix
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def build_inputs(args, torch, dev):
+    from paper_2310_09200_amd import StandardSynthesis, Context
+    from sims import configs
+    from sims.levels import kmeans1d_intervals
+
+    w = configs.c2(n_steps=args.epochs, n_side=args.n_side)
+    ctx = Context(0)
+    t0 = time.time()
+    insts = [w.instance(i) for i in range(args.epochs)]
+    log(f"simulated {len(insts)} visibility matrices in {time.time() - t0:.1f}s")
+    probe = StandardSynthesis(ctx, w.pix[:1], 1, 1, 512, 512)
+    _, lam0, _, _ = probe.prestep(insts[0].x, insts[0].wl, insts[0].V, 512, np.array([[-np.inf, np.inf]]))
+    intervals = kmeans1d_intervals(lam0.cpu().numpy(), 8, negative_level=True)
+    probe.close()
+    pre = StandardSynthesis(ctx, w.pix[:1], intervals.shape[0], 1, 512, 512)
+    items = []
+    t0 = time.time()
+    for i, inst in enumerate(insts):
+        W, lam, d, lev = pre.prestep(inst.x, inst.wl, inst.V, 512, intervals)
+        items.append((0, inst.x, inst.wl, W.clone(), d.clone(), lev.clone()))
+    torch.cuda.synchronize()
+    log(f"GPU FP64 pre-step (Gram + zhegvd) for {len(items)} epochs in {time.time() - t0:.1f}s")
+    pre.close()
+    return ctx, w, intervals, items, insts
+
+
+def time_mode(args, torch, ctx, w, items, precision, n_levels):
+    from paper_2310_09200_amd import Batch, StandardSynthesis
+    s = StandardSynthesis(ctx, w.pix, n_levels, 1, 512, 512, precision)
+    batch = Batch(items, ctx.device)
+    for _ in range(args.warmup):
+        s.collect_eig_batched(batch)
+    torch.cuda.synchronize()
+    kern_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.collect_eig_batched(batch)
+        kern_ms.append(s.timings())       # waits for this step's events (same stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.sync()
+    ms_step = (t1 - t0) * 1000.0 / args.steps
+    stage_ms = float(np.mean([k[1] for k in kern_ms]))
+    synth_ms = float(np.mean([k[2] for k in kern_ms]))
+    log(f"{precision}: {ms_step:.1f} ms/step, synthesis kernel {synth_ms:.1f} ms, staging {stage_ms:.2f} ms")
+    s.close()
+    return ms_step, synth_ms, stage_ms, batch.products
+
+
+def spot_error(args, torch, ctx, w, items, precision, n_levels, sel, ref_img):
+    """Per-level max error (peak-normalised) of one epoch on the oracle's sample pixels."""
+    from paper_2310_09200_amd import StandardSynthesis
+    s = StandardSynthesis(ctx, w.pix, n_levels, 1, 512, 512, precision)
+    _, x, wl, W, d, lev = items[0]
+    s.collect_eig(0, x, wl, W, d, lev)
+    s.sync()
+    got = s.images[0][:, torch.as_tensor(sel, device=ctx.device)].double().cpu().numpy()
+    s.close()
+    errs = []
+    for a, b in zip(got, ref_img):
+        if np.max(np.abs(b)) > 0:
+            errs.append(float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
+    return max(errs)
+
+
+def cpu_baseline(args, w, items, n_levels):
+    """The FP64 oracle (numpy/BLAS, all host threads) on a bounded sample of epoch 0."""
+    import oracle as ref
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+    _, x, wl, W, d, lev = items[0]
+    Wn = W.cpu().numpy().astype(np.complex128)
+    dn = d.cpu().numpy().astype(np.float64)
+    member = ref.membership_from_level_of(lev.cpu().numpy(), n_levels)
+    sel = np.arange(0, w.n_pix, args.cpu_stride)
+    t0 = time.perf_counter()
+    img = ref.synthesize_blas(Wn, dn, member, x, w.pix[sel], wl)
+    dt = time.perf_counter() - t0
+    prods = sel.size * Wn.shape[0] * Wn.shape[1]
+    log(f"oracle: {sel.size} pixels x 1 epoch in {dt:.1f}s -> {prods / dt:.3e} products/s on {threads} threads")
+    return {"value": prods / dt, "unit": "products/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"epoch 0 of the workload, every {args.cpu_stride}th pixel ({sel.size} pixels), "
+                      f"L=512, K=512, FP64 numpy/BLAS, {dt:.1f} s"}, sel, img
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--epochs", type=int, default=100)
+    ap.add_argument("--n-side", type=int, default=1024)
+    ap.add_argument("--cpu-stride", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the other precision")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (instances or pixel tiles would be "
+              "sharded across GPUs with one final all-reduce of the images). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda", 0)
+
+    ctx, w, intervals, items, insts = build_inputs(args, torch, dev)
+    n_levels = intervals.shape[0]
+    other = "bf16x3" if args.precision == "fp32" else "fp32"
+
+    ms, kern, stage, products = time_mode(args, torch, ctx, w, items, args.precision, n_levels)
+    value = products * w.n_pix / (ms / 1000.0)
+    res = {}
+    if not args.no_compare:
+        ms_o, kern_o, stage_o, _ = time_mode(args, torch, ctx, w, items, other, n_levels)
+        res[other] = (ms_o, kern_o)
+
+    cpu, sel, ref_img = (None, None, None)
+    if not args.no_cpu_baseline:
+        cpu, sel, ref_img = cpu_baseline(args, w, items, n_levels)
+
+    flops = 8.0 * products * w.n_pix
+    if args.precision == "fp32":
+        achieved = flops / (kern / 1000.0) / 1e12
+        peak = FP32_PEAK_TFLOPS
+    else:
+        achieved = 3 * flops / (kern / 1000.0) / 1e12
+        peak = BF16_PEAK_TFLOPS
+    out = {
+        "metric": "pixel*antenna*eigvec products/s for standard synthesis; compensated vs plain FP32 at 1e-4",
+        "value": value,
+        "unit": "products/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": f"LOFAR-like single channel: L=512 stations (50 km), K=512 eigenpairs, "
+                               f"{w.n_side}x{w.n_side} pixels over 10 deg, {args.epochs} epochs over 6 h, "
+                               f"{n_levels - 1}+1 k-means levels, FP64 phase arguments",
+                   "n_ant": 512, "n_eig": 512, "n_pix": w.n_pix, "n_instances": args.epochs,
+                   "n_levels": n_levels, "precision": args.precision, "launch": "batched (one synthesis launch "
+                   "over all epochs per step)"},
+        "fp32_equivalent_mfma_fraction": 8.0 * value / (FP32_PEAK_TFLOPS * 1e12),
+        "kernel_ms_per_step": kern,
+        "staging_ms_per_step": stage,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "synth_fwd_kernel", "flops_per_launch": flops * (3 if args.precision != "fp32" else 1)},
+    }
+    if res:
+        ms_o, kern_o = res[other]
+        v_o = products * w.n_pix / (ms_o / 1000.0)
+        t_fp32 = ms if args.precision == "fp32" else ms_o
+        t_bf = ms_o if args.precision == "fp32" else ms
+        out["compensated_vs_fp32"] = {"other_precision": other, "other_value": v_o, "other_ms_per_step": ms_o,
+                                      "other_kernel_ms": kern_o, "speedup_bf16x3_over_fp32": t_fp32 / t_bf}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+        errs = {args.precision: spot_error(args, torch, ctx, w, items, args.precision, n_levels, sel, ref_img)}
+        if res:
+            errs[other] = spot_error(args, torch, ctx, w, items, other, n_levels, sel, ref_img)
+        out["max_level_error_vs_oracle"] = errs
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * bluebild.h -- C ABI of the MI355X (gfx950) Bluebild standard-synthesis library.
+ *
+ * What it computes (Tolley et al., "BIPP: An efficient HPC implementation of
+ * the Bluebild algorithm for radio astronomy"):
+ *
+ *   For one (time step, channel) instance with L antennas at positions x_l,
+ *   visibility matrix V (L x L) and pixel directions p (unit vectors):
+ *     G_pq  = sinc(2 ||x_p - x_q|| / lambda_w)              Section 2.2, Eq. gram
+ *     V a   = lambda G a,  a^H G a = 1                      Section 2.3, Eq. eigenvaleq
+ *     keep the K largest eigenpairs (by signed value)       Section 2.6, Algorithm 1
+ *     B_lp  = exp(+j 2 pi <x_l, p> / lambda_w)              Section 2.1 (Psi*, g = 1)
+ *     E     = W^H B   (W = kept eigenvectors, L x K)        Section 2.4, Eq. standard_synthesis
+ *     I_l(p) += sum_{k in level l} d_k |E_kp|^2             Section 2.6 level equation; Algorithm 1
+ *   with d_k = lambda_k (least-squares filter) or d_k = 1 (standardized
+ *   filter), and images summed over instances (Section 2.3).
+ *
+ * Sign convention: V_pq = sum_s I_s exp(+j 2 pi <x_p - x_q, r_s> / lambda_w).
+ * Visibilities in the usual radio convention must be passed conjugated.
+ * Scale convention: G_pp = 1 exactly (the continuous Gram of Eq. gram).
+ *
+ * Conventions for every call:
+ *  - Device pointers are HIP device memory on the context's device; "host"
+ *    marks the few host pointers.  All matrices are column-major (Table 1).
+ *  - The caller owns every buffer, including the images and the workspace.
+ *    The library keeps the pixel, image and workspace pointers given to
+ *    bb_synth_create until bb_synth_destroy; it keeps no other pointer.
+ *  - Work is enqueued on the context's HIP stream, in call order.  Inputs
+ *    must stay valid and unmodified until the stream has reached the work;
+ *    inputs are never written.  bb_synth_sync waits for the stream.
+ *  - Arguments are validated on the host before anything is enqueued; a call
+ *    that returns an error has enqueued nothing and left the images as they
+ *    were.  Asynchronous device faults surface as BB_ERR_DEVICE from
+ *    bb_synth_sync.  No C++ exception crosses this interface.
+ *  - Calls on one handle, or on handles sharing a context, must not be made
+ *    concurrently from several host threads.
+ */
+#ifndef BLUEBILD_H
+#define BLUEBILD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BB_OK = 0,
+  BB_ERR_INVALID_ARG = 1, /* null pointer, bad size, NaN input, bad interval, bad level id */
+  BB_ERR_SHAPE = 2,       /* size beyond the maxima fixed at handle creation */
+  BB_ERR_NOT_POSDEF = 3,  /* Cholesky of G failed (e.g. coincident antennas) */
+  BB_ERR_EIGEN = 4,       /* eigensolver did not converge */
+  BB_ERR_WORKSPACE = 5,   /* workspace smaller than bb_workspace_size() */
+  BB_ERR_DEVICE = 6,      /* HIP runtime / library error */
+  BB_ERR_STATE = 7        /* wrong object state (e.g. destroying a context with live handles) */
+} bb_status;
+
+typedef enum { BB_PREC_FP32 = 0, BB_PREC_BF16X3 = 1 } bb_precision;
+typedef enum { BB_FILTER_LSQ = 0, BB_FILTER_STD = 1 } bb_filter;
+
+typedef struct bb_context_* bb_context;
+typedef struct bb_synth_* bb_synth;
+
+/* Options fixed when a synthesis handle is created.
+ *  n_levels   number of energy levels (images per slot), 1..16
+ *  n_slots    number of image slots (e.g. channels), >= 1
+ *  n_ant_max  largest antenna count of any instance, 1..1024
+ *  k_max      largest number of kept eigenpairs, 1..1024, <= n_ant_max for bb_synth_collect
+ *  precision  bb_precision: contraction in FP32 MFMA, or BF16 hi/lo split with three
+ *             products accumulated in FP32
+ *  filter     bb_filter applied by bb_synth_collect (collect_eig takes weights directly) */
+typedef struct {
+  int32_t n_levels;
+  int32_t n_slots;
+  int32_t n_ant_max;
+  int32_t k_max;
+  int32_t precision;
+  int32_t filter;
+  int32_t reserved[2];
+} bb_options;
+
+/* One instance of a batched call.  Offsets index the packed arrays passed to
+ * bb_synth_collect_eig_batched:
+ *  ant_off  first row of this instance in ant_xyz_packed (n_ant rows)
+ *  w_off    first element of this instance's W block (n_ant x n_eig, column-major,
+ *           leading dimension n_ant) in W_packed
+ *  eig_off  first element of this instance's n_eig weights / level ids */
+typedef struct {
+  int32_t n_ant;
+  int32_t n_eig;
+  int32_t slot;
+  int32_t reserved;
+  double wavelength_m;
+  int64_t ant_off;
+  int64_t w_off;
+  int64_t eig_off;
+} bb_instance;
+
+/* ---- context -------------------------------------------------------------
+ * A context binds a HIP device and stream and holds the eigensolver library
+ * handle (Section 3.1 "Context").  hip_stream may be NULL (default stream). */
+bb_status bb_context_create(int device, void* hip_stream, bb_context* out);
+bb_status bb_context_set_stream(bb_context ctx, void* hip_stream);
+/* BB_ERR_STATE if synthesis handles created on it are still alive. */
+bb_status bb_context_destroy(bb_context ctx);
+const char* bb_status_string(bb_status s);
+/* Message of the last failed call on this context; valid until the next call. */
+const char* bb_last_error(bb_context ctx);
+
+/* ---- synthesis handle ----------------------------------------------------
+ * Bytes of device workspace a handle needs for these options and pixel count
+ * (staging of one instance plus the FP64 pre-step of one instance). */
+bb_status bb_workspace_size(bb_context ctx, const bb_options* opt, int64_t n_pix, size_t* bytes);
+
+/* Create a StandardSynthesis handle (Section 3.1).
+ *  pix_xyz    device, n_pix x 3 float64, column-major, unit vectors (X_pix of Table 1)
+ *  images     device, float32 [n_slots][n_levels][n_pix]; accumulated into, never cleared
+ *             except by bb_synth_reset
+ *  workspace  device, ws_bytes >= bb_workspace_size(...) */
+bb_status bb_synth_create(bb_context ctx, const bb_options* opt, int64_t n_pix, const double* pix_xyz,
+                          float* images, void* workspace, size_t ws_bytes, bb_synth* out);
+
+/* Full step of Algorithm 1 for one instance: Gram (FP64), generalized
+ * eigensolve (FP64), selection of the n_eig largest eigenpairs, filter,
+ * levels from intervals, synthesis, accumulation into images[slot].
+ *  ant_xyz    device, n_ant x 3 float64 column-major, metres (P_icrs of Table 1)
+ *  vis        device, complex128 n_ant x n_ant column-major, Hermitian (S of Table 1)
+ *  n_eig      1..min(n_ant, k_max)
+ *  intervals  host, n_levels x 2 float64 column-major [min, max] (I of Table 1),
+ *             closed, min <= max, +-inf allowed; intervals may share an endpoint but
+ *             must not overlap on more than that (a value on a shared endpoint
+ *             goes to the lower-numbered level)
+ * Returns BB_ERR_NOT_POSDEF if the Cholesky factorisation of G fails and
+ * BB_ERR_EIGEN if the eigensolver fails; this status is read back from the
+ * device, so the call waits for its own pre-step.  On those errors the images
+ * are unchanged. */
+bb_status bb_synth_collect(bb_synth h, int32_t slot, int32_t n_ant, double wavelength_m,
+                           const double* ant_xyz, const double* vis, int32_t n_eig,
+                           const double* intervals);
+
+/* The FP64 pre-step of bb_synth_collect alone (Algorithm 1 up to the
+ * synthesis call), for callers that keep the eigenpairs, e.g. to image them
+ * again or to differentiate the synthesis with respect to them.  Arguments as
+ * for bb_synth_collect; outputs (device, overwritten):
+ *  W_out      complex64 n_ant x n_eig column-major, kept eigenvectors (a^H G a = 1),
+ *             in descending eigenvalue order
+ *  lam_out    float64 n_eig eigenvalues, descending
+ *  d_out      float32 n_eig filter weights of the handle's filter
+ *  level_out  int32 n_eig level ids from the intervals (-1 = in none)
+ * Waits for the eigensolver status like bb_synth_collect; images untouched. */
+bb_status bb_synth_prestep(bb_synth h, int32_t n_ant, double wavelength_m, const double* ant_xyz,
+                           const double* vis, int32_t n_eig, const double* intervals, void* W_out,
+                           double* lam_out, float* d_out, int32_t* level_out);
+
+/* Hot path only (Section 2.4 and Algorithm 2, given the eigenpairs):
+ *  W          device, complex64 n_ant x n_eig column-major (interleaved re, im float32)
+ *  d          device, float32 n_eig filter weights (lambda_k for the LSQ filter)
+ *  level_of   device, int32 n_eig level ids in [0, n_levels) or -1 (eigenpair unused)
+ * Accumulates images[slot][l] += sum_{k: level_of[k] = l} d_k |(W^H B)_kp|^2. */
+bb_status bb_synth_collect_eig(bb_synth h, int32_t slot, int32_t n_ant, int32_t n_eig, double wavelength_m,
+                               const double* ant_xyz, const void* W, const float* d,
+                               const int32_t* level_of);
+
+/* Many uneven instances in one launch (not in the paper, which takes one
+ * instance per call).  inst is a host array of n_inst descriptors; the packed
+ * device arrays hold every instance's data at the descriptor offsets:
+ *  ant_xyz_packed  device, float64 n_ant_rows x 3 column-major (leading dim n_ant_rows)
+ *  W_packed        device, complex64
+ *  d_packed        device, float32
+ *  level_packed    device, int32
+ *  workspace       device, ws_bytes >= bb_batched_workspace_size(...)
+ * Results equal calling bb_synth_collect_eig once per instance, up to the
+ * order of floating-point summation across instances of one slot. */
+bb_status bb_batched_workspace_size(bb_synth h, int32_t n_inst, const bb_instance* inst, size_t* bytes);
+bb_status bb_synth_collect_eig_batched(bb_synth h, int32_t n_inst, const bb_instance* inst,
+                                       int64_t n_ant_rows, const double* ant_xyz_packed,
+                                       const void* W_packed, const float* d_packed,
+                                       const int32_t* level_packed, void* workspace, size_t ws_bytes);
+
+/* Backward of collect_eig for the loss sum_l sum_p grad_images[l][p] * I_l(p)
+ * (images of this one instance, before accumulation).  Outputs (overwritten):
+ *  dW    device, complex64 n_ant x n_eig: dLoss/dRe(W) + j dLoss/dIm(W)
+ *  dd    device, float32 n_eig
+ *  dx    device, float64 n_ant x 3 column-major
+ *  grad_images  device, float32 [n_levels][n_pix]
+ *  workspace    device, ws_bytes >= bb_backward_workspace_size(...) */
+bb_status bb_backward_workspace_size(bb_synth h, int32_t n_ant, int32_t n_eig, size_t* bytes);
+bb_status bb_synth_eig_backward(bb_synth h, int32_t n_ant, int32_t n_eig, double wavelength_m,
+                                const double* ant_xyz, const void* W, const float* d,
+                                const int32_t* level_of, const float* grad_images,
+                                void* dW, float* dd, double* dx, void* workspace, size_t ws_bytes);
+
+/* Wait for all enqueued work; BB_ERR_DEVICE on an asynchronous device error. */
+bb_status bb_synth_sync(bb_synth h);
+/* Zero every image (stream-ordered) and set the instance count to 0. */
+bb_status bb_synth_reset(bb_synth h);
+/* Number of instances accumulated since creation / reset; settable for resume. */
+bb_status bb_synth_get_count(bb_synth h, int64_t* count);
+bb_status bb_synth_set_count(bb_synth h, int64_t count);
+/* Device time (ms) of the last call's stages: [0] pre-step (Gram + eigensolve),
+ * [1] selection and staging, [2] synthesis.  Waits for the stream.  At most
+ * 3 values are written. */
+bb_status bb_synth_timings(bb_synth h, double* ms_out, int32_t n);
+bb_status bb_synth_destroy(bb_synth h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLUEBILD_H */

@@ -1,0 +1,689 @@
+// Host side of the C ABI declared in include/bluebild.h: argument validation,
+// workspace carving, stream-ordered launches, the rocSOLVER eigensolve of the
+// FP64 pre-step, status codes.  No exception crosses the ABI.
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bb_internal.h"
+#include "bluebild.h"
+
+using bb::InstDesc;
+using bb::InstDyn;
+
+struct bb_context_ {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  rocblas_handle rb = nullptr;
+  std::string err;
+  int live = 0;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Device metadata block for single-instance calls (written by a kernel from
+// its arguments, so no host buffer has to outlive the call).
+struct SingleMeta {
+  InstDesc desc;
+  InstDyn dyn;
+  int group_slot;
+  int group_begin[2];
+  int inst_list;
+};
+
+struct Layout {  // byte offsets into a handle's workspace
+  size_t meta, err, apack, xs, wts, levs, kbr, perm;
+  size_t A, G, evals, E, info, dsel, lsel, wcol, solver, solver_bytes;
+  size_t total;
+};
+
+size_t staging_bytes(int L_pad, int K_alloc, size_t* off_xs = nullptr, size_t* off_wts = nullptr,
+                     size_t* off_levs = nullptr, size_t* off_kbr = nullptr, size_t* off_perm = nullptr) {
+  size_t o = 0;
+  o += align_up((size_t)2 * K_alloc * 2 * L_pad * 4);  // apack (fp32; bf16 hi+lo has the same size)
+  if (off_xs) *off_xs = o;
+  o += align_up((size_t)L_pad * 4 * 8);
+  if (off_wts) *off_wts = o;
+  o += align_up((size_t)K_alloc * 4);
+  if (off_levs) *off_levs = o;
+  o += align_up((size_t)K_alloc * 4);
+  if (off_kbr) *off_kbr = o;
+  o += align_up((size_t)(K_alloc / 32) * 8);
+  if (off_perm) *off_perm = o;
+  o += align_up((size_t)K_alloc * 4);
+  return o;
+}
+
+Layout make_layout(const bb_options& o, size_t solver_bytes) {
+  Layout l{};
+  const int L_pad = bb::round_up(o.n_ant_max, bb::kAntChunk);
+  const int K_alloc = bb::round_up(o.k_max, 32);
+  const size_t Lm = (size_t)o.n_ant_max;
+  size_t p = 0;
+  l.meta = p;
+  p += align_up(sizeof(SingleMeta));
+  l.err = p;
+  p += kAlign;
+  l.apack = p;
+  size_t xs, wts, levs, kbr, perm;
+  const size_t st = staging_bytes(L_pad, K_alloc, &xs, &wts, &levs, &kbr, &perm);
+  l.xs = p + xs;
+  l.wts = p + wts;
+  l.levs = p + levs;
+  l.kbr = p + kbr;
+  l.perm = p + perm;
+  p += st;
+  l.A = p;
+  p += align_up(16 * Lm * Lm);
+  l.G = p;
+  p += align_up(16 * Lm * Lm);
+  l.evals = p;
+  p += align_up(8 * Lm);
+  l.E = p;
+  p += align_up(8 * Lm);
+  l.info = p;
+  p += kAlign;
+  l.dsel = p;
+  p += align_up(4 * Lm);
+  l.lsel = p;
+  p += align_up(4 * Lm);
+  l.wcol = p;
+  p += align_up(4 * Lm);
+  l.solver = p;
+  l.solver_bytes = solver_bytes;
+  p += align_up(solver_bytes);
+  l.total = p;
+  return l;
+}
+
+}  // namespace
+
+struct bb_synth_ {
+  bb_context ctx = nullptr;
+  bb_options opt{};
+  int64_t n_pix = 0;
+  const double* pix = nullptr;
+  float* images = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  Layout lay{};
+  int64_t count = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool timed = false;
+};
+
+namespace {
+
+bb_status fail(bb_context ctx, bb_status s, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return s;
+}
+
+#define BB_HIP(ctx, call)                                                                       \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess) return fail((ctx), BB_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+bb_status check_options(bb_context ctx, const bb_options* o) {
+  if (!o) return fail(ctx, BB_ERR_INVALID_ARG, "options is NULL");
+  if (o->n_levels < 1 || o->n_levels > bb::kMaxLevels)
+    return fail(ctx, BB_ERR_INVALID_ARG, "n_levels must be in [1, %d]", bb::kMaxLevels);
+  if (o->n_slots < 1) return fail(ctx, BB_ERR_INVALID_ARG, "n_slots must be >= 1");
+  if (o->n_ant_max < 1 || o->n_ant_max > bb::kMaxAnt)
+    return fail(ctx, BB_ERR_INVALID_ARG, "n_ant_max must be in [1, %d]", bb::kMaxAnt);
+  if (o->k_max < 1 || o->k_max > bb::kMaxEig)
+    return fail(ctx, BB_ERR_INVALID_ARG, "k_max must be in [1, %d]", bb::kMaxEig);
+  if (o->precision != BB_PREC_FP32 && o->precision != BB_PREC_BF16X3)
+    return fail(ctx, BB_ERR_INVALID_ARG, "unknown precision %d", o->precision);
+  if (o->filter != BB_FILTER_LSQ && o->filter != BB_FILTER_STD)
+    return fail(ctx, BB_ERR_INVALID_ARG, "unknown filter %d", o->filter);
+  return BB_OK;
+}
+
+size_t solver_query(bb_context ctx, int n) {
+  // Size query mode: rocSOLVER returns its workspace need without computing.
+  // Null pointers make a call that is not honoured as a query fail its
+  // argument check instead of launching.
+  size_t sz = 0;
+  if (rocblas_start_device_memory_size_query(ctx->rb) != rocblas_status_success) return 0;
+  rocsolver_zhegvd(ctx->rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, n, nullptr, n, nullptr, n,
+                   nullptr, nullptr, nullptr);
+  if (rocblas_stop_device_memory_size_query(ctx->rb, &sz) != rocblas_status_success) return 0;
+  return sz;
+}
+
+__global__ void write_meta_kernel(SingleMeta* dst, InstDesc d, int slot) {
+  dst->desc = d;
+  dst->group_slot = slot;
+  dst->group_begin[0] = 0;
+  dst->group_begin[1] = 1;
+  dst->inst_list = 0;
+}
+
+__global__ void zero_int_kernel(int* p) { *p = 0; }
+
+template <class T>
+T* at(bb_synth h, size_t off) {
+  return reinterpret_cast<T*>(h->ws + off);
+}
+
+InstDesc staging_desc(bb_synth h, char* base, int L, int K, double wl, int slot) {
+  InstDesc d{};
+  d.L = L;
+  d.K = K;
+  d.L_pad = bb::round_up(L, bb::kAntChunk);
+  d.K_alloc = bb::round_up(K, 32);
+  d.scale = 4.0 / wl;
+  d.slot = slot;
+  size_t xs, wts, levs, kbr, perm;
+  staging_bytes(d.L_pad, d.K_alloc, &xs, &wts, &levs, &kbr, &perm);
+  d.apack = base;
+  d.xs = reinterpret_cast<double*>(base + xs);
+  d.wts = reinterpret_cast<float*>(base + wts);
+  d.levs = reinterpret_cast<int*>(base + levs);
+  d.kbr = reinterpret_cast<int2*>(base + kbr);
+  d.perm = reinterpret_cast<int*>(base + perm);
+  (void)h;
+  return d;
+}
+
+// Stage + synthesize one instance whose descriptor is `d` (single-instance calls).
+bb_status run_single(bb_synth h, const InstDesc& d) {
+  bb_context ctx = h->ctx;
+  hipStream_t s = ctx->stream;
+  SingleMeta* meta = at<SingleMeta>(h, h->lay.meta);
+  hipLaunchKernelGGL(write_meta_kernel, dim3(1), dim3(1), 0, s, meta, d, d.slot);
+  BB_HIP(ctx, hipGetLastError());
+  BB_HIP(ctx, bb::launch_stage(&meta->desc, &meta->dyn, 1, d.K_alloc, d.L_pad, h->opt.n_levels, h->opt.precision,
+                               at<int>(h, h->lay.err), s));
+  BB_HIP(ctx, hipEventRecord(h->ev[2], s));
+  bb::FwdParams p{};
+  p.pix = h->pix;
+  p.pix_ld = h->n_pix;
+  p.n_pix = h->n_pix;
+  p.descs = &meta->desc;
+  p.dyn = &meta->dyn;
+  p.group_slot = &meta->group_slot;
+  p.group_begin = meta->group_begin;
+  p.inst_list = &meta->inst_list;
+  p.img = h->images;
+  p.img_ld = h->n_pix;
+  p.n_levels = h->opt.n_levels;
+  const int nt = bb::synth_tile_pixels(d.K_alloc);
+  p.n_tiles = (int)((h->n_pix + nt - 1) / nt);
+  p.n_items = p.n_tiles;
+  BB_HIP(ctx, bb::launch_synth(p, d.K_alloc, h->opt.precision, nullptr, s));
+  BB_HIP(ctx, hipEventRecord(h->ev[3], s));
+  h->timed = true;
+  h->count += 1;
+  return BB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bb_status_string(bb_status s) {
+  switch (s) {
+    case BB_OK: return "BB_OK";
+    case BB_ERR_INVALID_ARG: return "BB_ERR_INVALID_ARG";
+    case BB_ERR_SHAPE: return "BB_ERR_SHAPE";
+    case BB_ERR_NOT_POSDEF: return "BB_ERR_NOT_POSDEF";
+    case BB_ERR_EIGEN: return "BB_ERR_EIGEN";
+    case BB_ERR_WORKSPACE: return "BB_ERR_WORKSPACE";
+    case BB_ERR_DEVICE: return "BB_ERR_DEVICE";
+    case BB_ERR_STATE: return "BB_ERR_STATE";
+  }
+  return "BB_ERR_UNKNOWN";
+}
+
+bb_status bb_context_create(int device, void* hip_stream, bb_context* out) {
+  if (!out) return BB_ERR_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return BB_ERR_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return BB_ERR_DEVICE;
+  bb_context c = new (std::nothrow) bb_context_;
+  if (!c) return BB_ERR_DEVICE;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (rocblas_create_handle(&c->rb) != rocblas_status_success) {
+    delete c;
+    return BB_ERR_DEVICE;
+  }
+  rocblas_set_stream(c->rb, c->stream);
+  *out = c;
+  return BB_OK;
+}
+
+bb_status bb_context_set_stream(bb_context ctx, void* hip_stream) {
+  if (!ctx) return BB_ERR_INVALID_ARG;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  rocblas_set_stream(ctx->rb, ctx->stream);
+  return BB_OK;
+}
+
+bb_status bb_context_destroy(bb_context ctx) {
+  if (!ctx) return BB_ERR_INVALID_ARG;
+  if (ctx->live > 0) return fail(ctx, BB_ERR_STATE, "%d synthesis handle(s) still alive", ctx->live);
+  rocblas_destroy_handle(ctx->rb);
+  delete ctx;
+  return BB_OK;
+}
+
+const char* bb_last_error(bb_context ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+bb_status bb_workspace_size(bb_context ctx, const bb_options* opt, int64_t n_pix, size_t* bytes) {
+  if (!ctx || !bytes) return BB_ERR_INVALID_ARG;
+  bb_status st = check_options(ctx, opt);
+  if (st != BB_OK) return st;
+  if (n_pix < 1) return fail(ctx, BB_ERR_INVALID_ARG, "n_pix must be >= 1");
+  if (hipSetDevice(ctx->device) != hipSuccess) return BB_ERR_DEVICE;
+  *bytes = make_layout(*opt, solver_query(ctx, opt->n_ant_max)).total;
+  return BB_OK;
+}
+
+bb_status bb_synth_create(bb_context ctx, const bb_options* opt, int64_t n_pix, const double* pix_xyz,
+                          float* images, void* workspace, size_t ws_bytes, bb_synth* out) {
+  if (!ctx || !out) return BB_ERR_INVALID_ARG;
+  *out = nullptr;
+  bb_status st = check_options(ctx, opt);
+  if (st != BB_OK) return st;
+  if (n_pix < 1) return fail(ctx, BB_ERR_INVALID_ARG, "n_pix must be >= 1");
+  if (!pix_xyz || !images || !workspace) return fail(ctx, BB_ERR_INVALID_ARG, "null device pointer");
+  if (hipSetDevice(ctx->device) != hipSuccess) return BB_ERR_DEVICE;
+  const Layout lay = make_layout(*opt, solver_query(ctx, opt->n_ant_max));
+  if (ws_bytes < lay.total)
+    return fail(ctx, BB_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, lay.total);
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return fail(ctx, BB_ERR_INVALID_ARG, "workspace must be %zu-byte aligned", kAlign);
+  bb_synth h = new (std::nothrow) bb_synth_;
+  if (!h) return BB_ERR_DEVICE;
+  h->ctx = ctx;
+  h->opt = *opt;
+  h->n_pix = n_pix;
+  h->pix = pix_xyz;
+  h->images = images;
+  h->ws = static_cast<char*>(workspace);
+  h->ws_bytes = ws_bytes;
+  h->lay = lay;
+  for (auto& e : h->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete h;
+      return fail(ctx, BB_ERR_DEVICE, "hipEventCreate failed");
+    }
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, ctx->stream, at<int>(h, h->lay.err));
+  if (hipGetLastError() != hipSuccess) {
+    for (auto& e : h->ev) (void)hipEventDestroy(e);
+    delete h;
+    return fail(ctx, BB_ERR_DEVICE, "launch failed");
+  }
+  ctx->live += 1;
+  *out = h;
+  return BB_OK;
+}
+
+bb_status bb_synth_destroy(bb_synth h) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  (void)hipStreamSynchronize(h->ctx->stream);
+  for (auto& e : h->ev) (void)hipEventDestroy(e);
+  h->ctx->live -= 1;
+  delete h;
+  return BB_OK;
+}
+
+static bb_status check_instance_args(bb_synth h, int32_t slot, int32_t n_ant, int32_t n_eig, double wl) {
+  bb_context ctx = h->ctx;
+  if (slot < 0 || slot >= h->opt.n_slots) return fail(ctx, BB_ERR_INVALID_ARG, "slot %d out of range", slot);
+  if (n_ant < 1) return fail(ctx, BB_ERR_INVALID_ARG, "n_ant must be >= 1");
+  if (n_ant > h->opt.n_ant_max) return fail(ctx, BB_ERR_SHAPE, "n_ant %d > n_ant_max %d", n_ant, h->opt.n_ant_max);
+  if (n_eig < 1) return fail(ctx, BB_ERR_INVALID_ARG, "n_eig must be >= 1");
+  if (n_eig > h->opt.k_max) return fail(ctx, BB_ERR_SHAPE, "n_eig %d > k_max %d", n_eig, h->opt.k_max);
+  if (!finite_pos(wl)) return fail(ctx, BB_ERR_INVALID_ARG, "wavelength must be finite and > 0");
+  return BB_OK;
+}
+
+bb_status bb_synth_collect_eig(bb_synth h, int32_t slot, int32_t n_ant, int32_t n_eig, double wavelength_m,
+                               const double* ant_xyz, const void* W, const float* d, const int32_t* level_of) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  bb_status st = check_instance_args(h, slot, n_ant, n_eig, wavelength_m);
+  if (st != BB_OK) return st;
+  if (!ant_xyz || !W || !d || !level_of) return fail(ctx, BB_ERR_INVALID_ARG, "null device pointer");
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  BB_HIP(ctx, hipEventRecord(h->ev[0], s));
+  BB_HIP(ctx, hipEventRecord(h->ev[1], s));
+  InstDesc dsc = staging_desc(h, h->ws + h->lay.apack, n_ant, n_eig, wavelength_m, slot);
+  dsc.ant = ant_xyz;
+  dsc.ant_ld = n_ant;
+  dsc.W = W;
+  dsc.W_ld = n_ant;
+  dsc.W_c128 = 0;
+  dsc.wcol = nullptr;
+  dsc.d = d;
+  dsc.lev_in = level_of;
+  return run_single(h, dsc);
+}
+
+// FP64 pre-step shared by bb_synth_collect and bb_synth_prestep: Gram,
+// generalized eigensolve, selection; leaves weights / level ids / column map
+// in the workspace.  Waits for the eigensolver status.
+static bb_status run_prestep(bb_synth h, int32_t n_ant, double wavelength_m, const double* ant_xyz,
+                             const double* vis, int32_t n_eig, const double* intervals) {
+  bb_context ctx = h->ctx;
+  if (n_eig > n_ant) return fail(ctx, BB_ERR_INVALID_ARG, "n_eig %d > n_ant %d", n_eig, n_ant);
+  if (!ant_xyz || !vis || !intervals) return fail(ctx, BB_ERR_INVALID_ARG, "null pointer");
+  const int nl = h->opt.n_levels;
+  bb::Intervals iv{};
+  for (int l = 0; l < nl; ++l) {
+    iv.lo[l] = intervals[l];
+    iv.hi[l] = intervals[l + nl];
+    if (std::isnan(iv.lo[l]) || std::isnan(iv.hi[l]) || iv.lo[l] > iv.hi[l])
+      return fail(ctx, BB_ERR_INVALID_ARG, "interval %d is not [min <= max]", l);
+  }
+  // Intervals may touch (k-means bounds are shared); a positive-length overlap
+  // is rejected.  A value on a shared bound goes to the first such level.
+  for (int a = 0; a < nl; ++a)
+    for (int b = a + 1; b < nl; ++b)
+      if (std::max(iv.lo[a], iv.lo[b]) < std::min(iv.hi[a], iv.hi[b]))
+        return fail(ctx, BB_ERR_INVALID_ARG, "intervals %d and %d overlap", a, b);
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const Layout& L = h->lay;
+  double* A = at<double>(h, L.A);
+  double* G = at<double>(h, L.G);
+  BB_HIP(ctx, hipEventRecord(h->ev[0], s));
+  BB_HIP(ctx, bb::launch_gram(ant_xyz, n_ant, n_ant, wavelength_m, G, n_ant, s));
+  BB_HIP(ctx, bb::launch_copy_c128(vis, n_ant, A, n_ant, s));
+  rocblas_set_stream(ctx->rb, s);
+  if (L.solver_bytes > 0 && rocblas_set_workspace(ctx->rb, h->ws + L.solver, L.solver_bytes) != rocblas_status_success)
+    return fail(ctx, BB_ERR_DEVICE, "rocblas_set_workspace failed");
+  rocblas_status rs = rocsolver_zhegvd(ctx->rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, n_ant,
+                                       reinterpret_cast<rocblas_double_complex*>(A), n_ant,
+                                       reinterpret_cast<rocblas_double_complex*>(G), n_ant, at<double>(h, L.evals),
+                                       at<double>(h, L.E), at<rocblas_int>(h, L.info));
+  if (L.solver_bytes > 0) rocblas_set_workspace(ctx->rb, nullptr, 0);
+  if (rs == rocblas_status_memory_error) return fail(ctx, BB_ERR_WORKSPACE, "rocSOLVER workspace too small");
+  if (rs != rocblas_status_success) return fail(ctx, BB_ERR_DEVICE, "rocsolver_zhegvd status %d", (int)rs);
+  BB_HIP(ctx, hipEventRecord(h->ev[1], s));
+  rocblas_int info = 0;
+  BB_HIP(ctx, hipMemcpyAsync(&info, at<rocblas_int>(h, L.info), sizeof info, hipMemcpyDeviceToHost, s));
+  BB_HIP(ctx, hipStreamSynchronize(s));
+  if (info > n_ant) return fail(ctx, BB_ERR_NOT_POSDEF, "Gram matrix not positive definite (leading minor %d)", info - n_ant);
+  if (info != 0) return fail(ctx, BB_ERR_EIGEN, "eigensolver did not converge (info %d)", info);
+  BB_HIP(ctx, bb::launch_select(at<double>(h, L.evals), n_ant, n_eig, iv, nl, h->opt.filter, at<float>(h, L.dsel),
+                                at<int>(h, L.lsel), at<int>(h, L.wcol), s));
+  return BB_OK;
+}
+
+bb_status bb_synth_collect(bb_synth h, int32_t slot, int32_t n_ant, double wavelength_m, const double* ant_xyz,
+                           const double* vis, int32_t n_eig, const double* intervals) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  bb_status st = check_instance_args(h, slot, n_ant, n_eig, wavelength_m);
+  if (st != BB_OK) return st;
+  st = run_prestep(h, n_ant, wavelength_m, ant_xyz, vis, n_eig, intervals);
+  if (st != BB_OK) return st;
+  const Layout& L = h->lay;
+  InstDesc dsc = staging_desc(h, h->ws + L.apack, n_ant, n_eig, wavelength_m, slot);
+  dsc.ant = ant_xyz;
+  dsc.ant_ld = n_ant;
+  dsc.W = at<double>(h, L.A);
+  dsc.W_ld = n_ant;
+  dsc.W_c128 = 1;
+  dsc.wcol = at<int>(h, L.wcol);
+  dsc.d = at<float>(h, L.dsel);
+  dsc.lev_in = at<int>(h, L.lsel);
+  return run_single(h, dsc);
+}
+
+bb_status bb_synth_prestep(bb_synth h, int32_t n_ant, double wavelength_m, const double* ant_xyz,
+                           const double* vis, int32_t n_eig, const double* intervals, void* W_out,
+                           double* lam_out, float* d_out, int32_t* level_out) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  bb_status st = check_instance_args(h, 0, n_ant, n_eig, wavelength_m);
+  if (st != BB_OK) return st;
+  if (!W_out || !lam_out || !d_out || !level_out) return fail(ctx, BB_ERR_INVALID_ARG, "null output pointer");
+  st = run_prestep(h, n_ant, wavelength_m, ant_xyz, vis, n_eig, intervals);
+  if (st != BB_OK) return st;
+  const Layout& L = h->lay;
+  BB_HIP(ctx, bb::launch_export_eig(at<double>(h, L.A), at<double>(h, L.evals), n_ant, n_eig, at<int>(h, L.wcol),
+                                    at<float>(h, L.dsel), at<int>(h, L.lsel), static_cast<float*>(W_out), lam_out,
+                                    d_out, level_out, ctx->stream));
+  BB_HIP(ctx, hipEventRecord(h->ev[2], ctx->stream));
+  BB_HIP(ctx, hipEventRecord(h->ev[3], ctx->stream));
+  h->timed = true;
+  return BB_OK;
+}
+
+// ---- batched ----------------------------------------------------------------
+namespace {
+
+struct BatchPlan {
+  std::vector<InstDesc> descs;
+  std::vector<int> group_slot, group_begin, inst_list;
+  size_t off_descs, off_dyn, off_gslot, off_gbegin, off_ilist, off_stage, total;
+  int max_K_alloc = 0, max_L_pad = 0;
+};
+
+bb_status plan_batch(bb_synth h, int32_t n_inst, const bb_instance* inst, int64_t n_ant_rows, BatchPlan& bp) {
+  bb_context ctx = h->ctx;
+  if (n_inst < 1 || !inst) return fail(ctx, BB_ERR_INVALID_ARG, "empty instance table");
+  std::vector<double> cost(h->opt.n_slots, 0.0);
+  std::vector<std::vector<int>> by_slot(h->opt.n_slots);
+  for (int i = 0; i < n_inst; ++i) {
+    const bb_instance& b = inst[i];
+    bb_status st = check_instance_args(h, b.slot, b.n_ant, b.n_eig, b.wavelength_m);
+    if (st != BB_OK) return st;
+    if (b.ant_off < 0 || b.w_off < 0 || b.eig_off < 0 || b.ant_off + b.n_ant > n_ant_rows)
+      return fail(ctx, BB_ERR_INVALID_ARG, "instance %d: offsets out of range", i);
+    const int L_pad = bb::round_up(b.n_ant, bb::kAntChunk), K_alloc = bb::round_up(b.n_eig, 32);
+    bp.max_K_alloc = std::max(bp.max_K_alloc, K_alloc);
+    bp.max_L_pad = std::max(bp.max_L_pad, L_pad);
+    cost[b.slot] += (double)L_pad * K_alloc;
+    by_slot[b.slot].push_back(i);
+  }
+  std::vector<int> slots;
+  for (int s = 0; s < h->opt.n_slots; ++s)
+    if (!by_slot[s].empty()) slots.push_back(s);
+  std::stable_sort(slots.begin(), slots.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  bp.group_begin.push_back(0);
+  for (int s : slots) {
+    bp.group_slot.push_back(s);
+    for (int i : by_slot[s]) bp.inst_list.push_back(i);
+    bp.group_begin.push_back((int)bp.inst_list.size());
+  }
+  size_t p = 0;
+  bp.off_descs = p;
+  p += align_up(sizeof(InstDesc) * n_inst);
+  bp.off_dyn = p;
+  p += align_up(sizeof(InstDyn) * n_inst);
+  bp.off_gslot = p;
+  p += align_up(sizeof(int) * bp.group_slot.size());
+  bp.off_gbegin = p;
+  p += align_up(sizeof(int) * bp.group_begin.size());
+  bp.off_ilist = p;
+  p += align_up(sizeof(int) * bp.inst_list.size());
+  bp.off_stage = p;
+  for (int i = 0; i < n_inst; ++i)
+    p += staging_bytes(bb::round_up(inst[i].n_ant, bb::kAntChunk), bb::round_up(inst[i].n_eig, 32));
+  bp.total = p;
+  return BB_OK;
+}
+
+}  // namespace
+
+bb_status bb_batched_workspace_size(bb_synth h, int32_t n_inst, const bb_instance* inst, size_t* bytes) {
+  if (!h || !bytes) return BB_ERR_INVALID_ARG;
+  BatchPlan bp;
+  int64_t rows = 0;
+  for (int i = 0; inst && i < n_inst; ++i) rows = std::max<int64_t>(rows, inst[i].ant_off + inst[i].n_ant);
+  bb_status st = plan_batch(h, n_inst, inst, rows, bp);
+  if (st != BB_OK) return st;
+  *bytes = bp.total;
+  return BB_OK;
+}
+
+bb_status bb_synth_collect_eig_batched(bb_synth h, int32_t n_inst, const bb_instance* inst, int64_t n_ant_rows,
+                                       const double* ant_xyz_packed, const void* W_packed, const float* d_packed,
+                                       const int32_t* level_packed, void* workspace, size_t ws_bytes) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  if (!ant_xyz_packed || !W_packed || !d_packed || !level_packed || !workspace)
+    return fail(ctx, BB_ERR_INVALID_ARG, "null device pointer");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return fail(ctx, BB_ERR_INVALID_ARG, "workspace must be %zu-byte aligned", kAlign);
+  BatchPlan bp;
+  bb_status st = plan_batch(h, n_inst, inst, n_ant_rows, bp);
+  if (st != BB_OK) return st;
+  if (ws_bytes < bp.total) return fail(ctx, BB_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, bp.total);
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  char* ws = static_cast<char*>(workspace);
+  size_t stage = bp.off_stage;
+  bp.descs.resize(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    const bb_instance& b = inst[i];
+    InstDesc d = staging_desc(h, ws + stage, b.n_ant, b.n_eig, b.wavelength_m, b.slot);
+    stage += staging_bytes(d.L_pad, d.K_alloc);
+    d.ant = ant_xyz_packed + b.ant_off;
+    d.ant_ld = n_ant_rows;
+    d.W = static_cast<const float*>(W_packed) + 2 * b.w_off;
+    d.W_ld = b.n_ant;
+    d.W_c128 = 0;
+    d.wcol = nullptr;
+    d.d = d_packed + b.eig_off;
+    d.lev_in = level_packed + b.eig_off;
+    bp.descs[i] = d;
+  }
+  // one host image of the metadata block, uploaded in one copy
+  std::vector<char> meta(bp.off_stage, 0);
+  std::memcpy(meta.data() + bp.off_descs, bp.descs.data(), sizeof(InstDesc) * n_inst);
+  std::memcpy(meta.data() + bp.off_gslot, bp.group_slot.data(), sizeof(int) * bp.group_slot.size());
+  std::memcpy(meta.data() + bp.off_gbegin, bp.group_begin.data(), sizeof(int) * bp.group_begin.size());
+  std::memcpy(meta.data() + bp.off_ilist, bp.inst_list.data(), sizeof(int) * bp.inst_list.size());
+  hipStream_t s = ctx->stream;
+  BB_HIP(ctx, hipEventRecord(h->ev[0], s));
+  BB_HIP(ctx, hipEventRecord(h->ev[1], s));
+  // pageable source: the copy is staged before the call returns
+  BB_HIP(ctx, hipMemcpyAsync(ws, meta.data(), meta.size(), hipMemcpyHostToDevice, s));
+  InstDesc* d_descs = reinterpret_cast<InstDesc*>(ws + bp.off_descs);
+  InstDyn* d_dyn = reinterpret_cast<InstDyn*>(ws + bp.off_dyn);
+  BB_HIP(ctx, bb::launch_stage(d_descs, d_dyn, n_inst, bp.max_K_alloc, bp.max_L_pad, h->opt.n_levels,
+                               h->opt.precision, at<int>(h, h->lay.err), s));
+  BB_HIP(ctx, hipEventRecord(h->ev[2], s));
+  bb::FwdParams p{};
+  p.pix = h->pix;
+  p.pix_ld = h->n_pix;
+  p.n_pix = h->n_pix;
+  p.descs = d_descs;
+  p.dyn = d_dyn;
+  p.group_slot = reinterpret_cast<int*>(ws + bp.off_gslot);
+  p.group_begin = reinterpret_cast<int*>(ws + bp.off_gbegin);
+  p.inst_list = reinterpret_cast<int*>(ws + bp.off_ilist);
+  p.img = h->images;
+  p.img_ld = h->n_pix;
+  p.n_levels = h->opt.n_levels;
+  const int nt = bb::synth_tile_pixels(bp.max_K_alloc);
+  p.n_tiles = (int)((h->n_pix + nt - 1) / nt);
+  p.n_items = (int64_t)p.n_tiles * (int64_t)bp.group_slot.size();
+  BB_HIP(ctx, bb::launch_synth(p, bp.max_K_alloc, h->opt.precision, nullptr, s));
+  BB_HIP(ctx, hipEventRecord(h->ev[3], s));
+  h->timed = true;
+  h->count += n_inst;
+  return BB_OK;
+}
+
+// ---- backward -------------------------------------------------------------
+bb_status bb_backward_workspace_size(bb_synth h, int32_t n_ant, int32_t n_eig, size_t* bytes) {
+  if (!h || !bytes) return BB_ERR_INVALID_ARG;
+  (void)n_ant;
+  (void)n_eig;
+  return fail(h->ctx, BB_ERR_STATE, "backward not available in this build");
+}
+
+bb_status bb_synth_eig_backward(bb_synth h, int32_t n_ant, int32_t n_eig, double wavelength_m,
+                                const double* ant_xyz, const void* W, const float* d, const int32_t* level_of,
+                                const float* grad_images, void* dW, float* dd, double* dx, void* workspace,
+                                size_t ws_bytes) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  (void)n_ant; (void)n_eig; (void)wavelength_m; (void)ant_xyz; (void)W; (void)d; (void)level_of;
+  (void)grad_images; (void)dW; (void)dd; (void)dx; (void)workspace; (void)ws_bytes;
+  return fail(h->ctx, BB_ERR_STATE, "backward not available in this build");
+}
+
+// ---- misc -------------------------------------------------------------------
+bb_status bb_synth_sync(bb_synth h) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  BB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  int err = 0;
+  BB_HIP(ctx, hipMemcpy(&err, at<int>(h, h->lay.err), sizeof err, hipMemcpyDeviceToHost));
+  if (err) {
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, ctx->stream, at<int>(h, h->lay.err));
+    BB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return fail(ctx, BB_ERR_INVALID_ARG, "a level id outside [-1, n_levels) was treated as -1");
+  }
+  return BB_OK;
+}
+
+bb_status bb_synth_reset(bb_synth h) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  const int64_t n = (int64_t)h->opt.n_slots * h->opt.n_levels * h->n_pix;
+  BB_HIP(ctx, bb::launch_fill_zero(h->images, n, ctx->stream));
+  h->count = 0;
+  return BB_OK;
+}
+
+bb_status bb_synth_get_count(bb_synth h, int64_t* count) {
+  if (!h || !count) return BB_ERR_INVALID_ARG;
+  *count = h->count;
+  return BB_OK;
+}
+
+bb_status bb_synth_set_count(bb_synth h, int64_t count) {
+  if (!h || count < 0) return BB_ERR_INVALID_ARG;
+  h->count = count;
+  return BB_OK;
+}
+
+bb_status bb_synth_timings(bb_synth h, double* ms_out, int32_t n) {
+  if (!h || !ms_out || n < 0) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  if (!h->timed) return fail(ctx, BB_ERR_STATE, "no timed call yet");
+  BB_HIP(ctx, hipEventSynchronize(h->ev[3]));
+  for (int i = 0; i < n && i < 3; ++i) {
+    float ms = 0.0f;
+    BB_HIP(ctx, hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]));
+    ms_out[i] = ms;
+  }
+  return BB_OK;
+}
+
+}  // extern "C"

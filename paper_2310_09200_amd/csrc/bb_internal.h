@@ -1,0 +1,103 @@
+// Internal declarations shared by the host API and the kernels (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bb {
+
+// Antennas per LDS phase chunk; every instance's antenna count is padded to it.
+constexpr int kAntChunk = 32;
+// Largest level count a handle may use (sizes the per-tile level accumulators in LDS).
+constexpr int kMaxLevels = 16;
+// Largest antenna / eigenpair counts.
+constexpr int kMaxAnt = 1024;
+constexpr int kMaxEig = 1024;
+
+__host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// One instance as seen by the staging and synthesis kernels.  Built on the
+// host; the device-computed part (kept eigenpair count) lives in InstDyn.
+struct InstDesc {
+  const double* ant;     // antenna x column; y at ant + ant_ld, z at ant + 2*ant_ld
+  int64_t ant_ld;
+  const void* W;         // eigenvectors, column-major, leading dim W_ld
+  int64_t W_ld;
+  const int* wcol;       // optional column map (nullptr = identity)
+  const float* d;        // filter weights, one per eigenpair
+  const int* lev_in;     // level id per eigenpair, -1 = unused
+  double scale;          // 4 / wavelength: positions in quarter turns per unit direction
+  int L, K, L_pad, K_alloc;
+  int slot, W_c128, pad0, pad1;
+  // workspace regions owned by this instance
+  void* apack;           // packed real-embedded W^H, MFMA operand order
+  double* xs;            // [L_pad][4] scaled positions
+  float* wts;            // [K_alloc] weights after level sort (0 beyond K_eff)
+  int* levs;             // [K_alloc] level ids after sort (-1 beyond K_eff)
+  int2* kbr;             // [K_alloc/32] (lowest, highest) level of each 32-block
+  int* perm;             // [K_alloc] source eigenpair of each sorted position (-1 = pad)
+};
+
+struct InstDyn {
+  int K_pad;             // kept eigenpairs rounded up to 32
+  int K_eff;
+};
+
+struct FwdParams {
+  const double* pix;     // x column; y at pix + pix_ld, z at pix + 2*pix_ld
+  int64_t pix_ld;
+  int64_t n_pix;
+  const InstDesc* descs;
+  const InstDyn* dyn;
+  const int* group_slot;   // work item i covers group i / n_tiles (image slot group_slot[g]), tile i % n_tiles
+  const int* group_begin;  // instances of group g: inst_list[group_begin[g] .. group_begin[g+1])
+  const int* inst_list;
+  float* img;              // [n_slots][n_levels][img_ld]
+  int64_t img_ld;
+  int n_levels;
+  int n_tiles;
+  int64_t n_items;
+};
+
+// Staging (launchers in synth_kernels.hip).
+hipError_t launch_stage(const InstDesc* d_descs, InstDyn* d_dyn, int n_inst, int max_K_alloc, int max_L_pad,
+                        int n_levels, int precision, int* d_err, hipStream_t s);
+
+// Synthesis: picks a tile configuration from the largest K_alloc of the call.
+hipError_t launch_synth(const FwdParams& p, int max_K_alloc, int precision, int tile_pixels_out[1],
+                        hipStream_t s);
+int synth_tile_pixels(int max_K_alloc);
+
+// Zero-fill of a float buffer (graph-capture safe, no memset nodes).
+hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
+
+// Pre-step kernels (prestep.hip).
+hipError_t launch_gram(const double* ant, int64_t ant_ld, int L, double wl, double* G_c128, int ldg,
+                       hipStream_t s);
+hipError_t launch_copy_c128(const double* src, int L, double* dst, int ldd, hipStream_t s);
+struct Intervals {
+  double lo[kMaxLevels];
+  double hi[kMaxLevels];
+};
+hipError_t launch_select(const double* evals, int L, int K, Intervals iv, int n_levels, int filter,
+                         float* d_out, int* lev_out, int* wcol_out, hipStream_t s);
+hipError_t launch_export_eig(const double* A_c128, const double* evals, int L, int K, const int* wcol,
+                             const float* dsel, const int* lsel, float* W_out_c64, double* lam_out, float* d_out,
+                             int* lev_out, hipStream_t s);
+
+// Backward (synth_bwd.hip).
+struct BwdParams {
+  const double* pix; int64_t pix_ld; int64_t n_pix;
+  const InstDesc* desc; const InstDyn* dyn;
+  const float* gimg; int64_t gimg_ld; int n_levels;
+  // outputs / partials
+  float* dW_part;   // [n_ptiles][2*K_alloc][2*L_pad] real partials (dW = 2 B M^T)
+  double* dx_part;  // [n_ptiles][L_pad][3]
+  float* dd_part;   // [n_ptiles][K_alloc]
+  int n_ptiles;
+};
+hipError_t launch_backward(const BwdParams& p, int K_alloc, int L_pad, hipStream_t s);
+hipError_t launch_backward_reduce(const BwdParams& p, int K_alloc, int L_pad, int L, int K, void* dW,
+                                  float* dd, double* dx, hipStream_t s);
+
+}  // namespace bb

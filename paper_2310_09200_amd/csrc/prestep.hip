@@ -1,0 +1,112 @@
+// FP64 pre-step of one instance (Algorithm 1 up to the synthesis call):
+// Gram matrix, copy of V for the in-place eigensolver, and selection of the
+// kept eigenpairs with their filter weights and level ids.  The generalized
+// eigensolve itself is rocSOLVER's zhegvd, called from the host API.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "bb_internal.h"
+
+namespace bb {
+
+// G_pq = sinc(2 ||x_p - x_q|| / lambda_w), sinc(u) = sin(pi u) / (pi u)
+// (Section 2.2, Eq. gram), stored complex128 column-major for zhegvd.
+__global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ ant, int64_t ant_ld, int L,
+                                                   double inv_wl, double* __restrict__ G, int ldg) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)L * L) return;
+  const int p = (int)(idx % L), q = (int)(idx / L);
+  const double dx = ant[p] - ant[q];
+  const double dy = ant[p + ant_ld] - ant[q + ant_ld];
+  const double dz = ant[p + 2 * ant_ld] - ant[q + 2 * ant_ld];
+  const double u = 2.0 * sqrt(dx * dx + dy * dy + dz * dz) * inv_wl;
+  const double v = (u == 0.0) ? 1.0 : sinpi(u) / (M_PI * u);
+  double* g = G + 2 * ((int64_t)q * ldg + p);
+  g[0] = v;
+  g[1] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void copy_c128_kernel(const double* __restrict__ src, int L,
+                                                        double* __restrict__ dst, int ldd) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)L * L) return;
+  const int p = (int)(idx % L), q = (int)(idx / L);
+  const double* s = src + 2 * ((int64_t)q * L + p);
+  double* d = dst + 2 * ((int64_t)q * ldd + p);
+  d[0] = s[0];
+  d[1] = s[1];
+}
+
+// zhegvd returns eigenvalues ascending; keep the K largest, descending
+// (Section 2.6 truncation; Algorithm 1 selection).  Weight: lambda (LSQ
+// filter) or 1 (standardized filter).  Level: first closed interval that
+// contains lambda, else -1.  wcol maps kept position k to its eigenvector column.
+__global__ __launch_bounds__(256) void select_kernel(const double* __restrict__ evals, int L, int K,
+                                                     Intervals iv, int n_levels, int filter,
+                                                     float* __restrict__ d_out, int* __restrict__ lev_out,
+                                                     int* __restrict__ wcol_out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const int col = L - 1 - k;
+  const double lam = evals[col];
+  int lv = -1;
+  for (int l = n_levels - 1; l >= 0; --l)
+    if (lam >= iv.lo[l] && lam <= iv.hi[l]) lv = l;
+  d_out[k] = filter == 0 ? (float)lam : 1.0f;
+  lev_out[k] = lv;
+  wcol_out[k] = col;
+}
+
+hipError_t launch_gram(const double* ant, int64_t ant_ld, int L, double wl, double* G, int ldg, hipStream_t s) {
+  const int64_t n = (int64_t)L * L;
+  hipLaunchKernelGGL(gram_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ant, ant_ld, L, 1.0 / wl,
+                     G, ldg);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_c128(const double* src, int L, double* dst, int ldd, hipStream_t s) {
+  const int64_t n = (int64_t)L * L;
+  hipLaunchKernelGGL(copy_c128_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, L, dst, ldd);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const double* evals, int L, int K, Intervals iv, int n_levels, int filter, float* d_out,
+                         int* lev_out, int* wcol_out, hipStream_t s) {
+  hipLaunchKernelGGL(select_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, evals, L, K, iv, n_levels,
+                     filter, d_out, lev_out, wcol_out);
+  return hipGetLastError();
+}
+
+// Copy the kept eigenpairs out: W (complex64, L x K column-major), lambda,
+// weights and level ids.
+__global__ __launch_bounds__(256) void export_eig_kernel(const double* __restrict__ A, const double* __restrict__ evals,
+                                                         int L, int K, const int* __restrict__ wcol,
+                                                         const float* __restrict__ dsel, const int* __restrict__ lsel,
+                                                         float* __restrict__ W_out, double* __restrict__ lam_out,
+                                                         float* __restrict__ d_out, int* __restrict__ lev_out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)L * K) return;
+  const int l = (int)(idx % L), k = (int)(idx / L);
+  const int col = wcol[k];
+  const double* a = A + 2 * ((int64_t)col * L + l);
+  W_out[2 * idx] = (float)a[0];
+  W_out[2 * idx + 1] = (float)a[1];
+  if (l == 0) {
+    lam_out[k] = evals[col];
+    d_out[k] = dsel[k];
+    lev_out[k] = lsel[k];
+  }
+}
+
+hipError_t launch_export_eig(const double* A, const double* evals, int L, int K, const int* wcol, const float* dsel,
+                             const int* lsel, float* W_out, double* lam_out, float* d_out, int* lev_out,
+                             hipStream_t s) {
+  const int64_t n = (int64_t)L * K;
+  hipLaunchKernelGGL(export_eig_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, evals, L, K, wcol,
+                     dsel, lsel, W_out, lam_out, d_out, lev_out);
+  return hipGetLastError();
+}
+
+}  // namespace bb

@@ -1,0 +1,219 @@
+"""Python front end: Context and StandardSynthesis over the C ABI (torch tensors for memory and streams).
+
+Every step of the computation runs in libbluebild.so; this module only turns
+tensors into column-major device pointers, allocates the caller-owned
+buffers (images, workspaces) with torch, and passes torch's current stream.
+"""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import bb_instance, bb_options, check, load
+
+_PREC = {"fp32": _lib.BB_PREC_FP32, "bf16x3": _lib.BB_PREC_BF16X3}
+_FILT = {"lsq": _lib.BB_FILTER_LSQ, "std": _lib.BB_FILTER_STD}
+
+
+def _colmajor(t, dtype, device):
+    """(rows, cols) tensor -> contiguous (cols, rows) tensor: its storage is the column-major matrix."""
+    return t.to(device=device, dtype=dtype).transpose(0, 1).contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Device + stream + eigensolver handle (the paper's Context, Section 3.1)."""
+
+    def __init__(self, device=0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("Bluebild needs a HIP device; none is visible")
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        check(self.lib.bb_context_create(device, ctypes.c_void_p(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def bind_current_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        check(self.lib.bb_context_set_stream(self.handle, ctypes.c_void_p(s)), self.handle)
+
+    def close(self):
+        if self.handle:
+            check(self.lib.bb_context_destroy(self.handle), self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class StandardSynthesis:
+    """Imaging handle: accumulates per-level images over collected instances.
+
+    ``pix`` is (n_pix, 3) float64 unit vectors.  Images are a float32 tensor
+    ``[n_slots, n_levels, n_pix]`` owned by this object (``.images``).
+    """
+
+    def __init__(self, ctx, pix, n_levels, n_slots=1, n_ant_max=512, k_max=512, precision="fp32", filter="lsq",
+                 images=None):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        dev = ctx.device
+        self.n_pix = int(pix.shape[0])
+        self.n_levels = int(n_levels)
+        self.n_slots = int(n_slots)
+        self.opt = bb_options(n_levels=n_levels, n_slots=n_slots, n_ant_max=n_ant_max, k_max=k_max,
+                              precision=_PREC[precision], filter=_FILT[filter])
+        self.pix_cm = _colmajor(torch.as_tensor(pix), torch.float64, dev)
+        if images is None:
+            images = torch.zeros((n_slots, n_levels, self.n_pix), dtype=torch.float32, device=dev)
+        assert images.shape == (n_slots, n_levels, self.n_pix) and images.dtype == torch.float32
+        assert images.is_contiguous()
+        self.images = images
+        sz = ctypes.c_size_t()
+        check(self.lib.bb_workspace_size(ctx.handle, ctypes.byref(self.opt), self.n_pix, ctypes.byref(sz)),
+              ctx.handle)
+        self.workspace = torch.empty(int(sz.value) + 256, dtype=torch.uint8, device=dev)
+        ws_ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        h = ctypes.c_void_p()
+        ctx.bind_current_stream()
+        check(self.lib.bb_synth_create(ctx.handle, ctypes.byref(self.opt), self.n_pix, _ptr(self.pix_cm),
+                                       _ptr(self.images), ctypes.c_void_p(ws_ptr), sz.value, ctypes.byref(h)),
+              ctx.handle)
+        self.handle = h
+        self._keep = []
+
+    # -- calls ---------------------------------------------------------------
+    def collect(self, slot, x, wavelength, V, n_eig, intervals):
+        """Full step (Algorithm 1): x (L,3) f64, V (L,L) complex128 Hermitian, intervals (n_levels,2)."""
+        dev = self.ctx.device
+        L = int(x.shape[0])
+        xc = _colmajor(torch.as_tensor(x), torch.float64, dev)
+        Vc = _colmajor(torch.as_tensor(V), torch.complex128, dev)
+        iv = np.ascontiguousarray(np.asarray(intervals, np.float64).reshape(self.n_levels, 2).T).ravel()
+        ivp = iv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self.ctx.bind_current_stream()
+        check(self.lib.bb_synth_collect(self.handle, slot, L, float(wavelength), _ptr(xc), _ptr(Vc), int(n_eig),
+                                        ivp), self.ctx.handle)
+        self._keep = [xc, Vc]
+
+    def prestep(self, x, wavelength, V, n_eig, intervals):
+        """FP64 pre-step alone: returns (W (L,K) complex64, lam (K,) f64, d (K,) f32, level_of (K,) i32) on device."""
+        dev = self.ctx.device
+        L = int(x.shape[0])
+        K = int(n_eig)
+        xc = _colmajor(torch.as_tensor(x), torch.float64, dev)
+        Vc = _colmajor(torch.as_tensor(V), torch.complex128, dev)
+        iv = np.ascontiguousarray(np.asarray(intervals, np.float64).reshape(self.n_levels, 2).T).ravel()
+        ivp = iv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        Wt = torch.empty((K, L), dtype=torch.complex64, device=dev)   # column-major (L, K)
+        lam = torch.empty(K, dtype=torch.float64, device=dev)
+        d = torch.empty(K, dtype=torch.float32, device=dev)
+        lev = torch.empty(K, dtype=torch.int32, device=dev)
+        self.ctx.bind_current_stream()
+        check(self.lib.bb_synth_prestep(self.handle, L, float(wavelength), _ptr(xc), _ptr(Vc), K, ivp, _ptr(Wt),
+                                        _ptr(lam), _ptr(d), _ptr(lev)), self.ctx.handle)
+        self._keep = [xc, Vc]
+        return Wt.transpose(0, 1), lam, d, lev
+
+    def collect_eig(self, slot, x, wavelength, W, d, level_of):
+        """Hot path: x (L,3) f64, W (L,K) complex, d (K,) weights, level_of (K,) int (-1 = unused)."""
+        dev = self.ctx.device
+        L, K = int(W.shape[0]), int(W.shape[1])
+        xc = _colmajor(torch.as_tensor(x), torch.float64, dev)
+        Wc = _colmajor(torch.as_tensor(W), torch.complex64, dev)
+        dc = torch.as_tensor(d).to(device=dev, dtype=torch.float32).contiguous()
+        lc = torch.as_tensor(level_of).to(device=dev, dtype=torch.int32).contiguous()
+        self.ctx.bind_current_stream()
+        check(self.lib.bb_synth_collect_eig(self.handle, slot, L, K, float(wavelength), _ptr(xc), _ptr(Wc),
+                                            _ptr(dc), _ptr(lc)), self.ctx.handle)
+        self._keep = [xc, Wc, dc, lc]
+
+    def collect_eig_batched(self, batch):
+        """Many instances in one launch; ``batch`` is a :class:`Batch` (packed device arrays)."""
+        arr = (bb_instance * len(batch.inst))(*batch.inst)
+        sz = ctypes.c_size_t()
+        check(self.lib.bb_batched_workspace_size(self.handle, len(batch.inst), arr, ctypes.byref(sz)),
+              self.ctx.handle)
+        ws = torch.empty(int(sz.value) + 256, dtype=torch.uint8, device=self.ctx.device)
+        ws_ptr = (ws.data_ptr() + 255) // 256 * 256
+        self.ctx.bind_current_stream()
+        check(self.lib.bb_synth_collect_eig_batched(
+            self.handle, len(batch.inst), arr, batch.n_ant_rows, _ptr(batch.ant), _ptr(batch.W), _ptr(batch.d),
+            _ptr(batch.lev), ctypes.c_void_p(ws_ptr), sz.value), self.ctx.handle)
+        self._keep = [ws]
+
+    def sync(self):
+        check(self.lib.bb_synth_sync(self.handle), self.ctx.handle)
+
+    def reset(self):
+        self.ctx.bind_current_stream()
+        check(self.lib.bb_synth_reset(self.handle), self.ctx.handle)
+
+    @property
+    def count(self):
+        c = ctypes.c_int64()
+        check(self.lib.bb_synth_get_count(self.handle, ctypes.byref(c)), self.ctx.handle)
+        return c.value
+
+    @count.setter
+    def count(self, v):
+        check(self.lib.bb_synth_set_count(self.handle, int(v)), self.ctx.handle)
+
+    def timings(self):
+        """(pre-step, staging, synthesis) device milliseconds of the last call."""
+        out = (ctypes.c_double * 3)()
+        check(self.lib.bb_synth_timings(self.handle, out, 3), self.ctx.handle)
+        return tuple(out)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(self.lib.bb_synth_destroy(self.handle), self.ctx.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Packed device arrays + instance table for :meth:`StandardSynthesis.collect_eig_batched`.
+
+    ``items`` is a list of (slot, x (L,3), wavelength, W (L,K), d (K,), level_of (K,)); arrays may be
+    numpy arrays or tensors on any device.
+    """
+
+    def __init__(self, items, device):
+        xs, Ws, ds, ls, inst = [], [], [], [], []
+        ant_off = w_off = eig_off = 0
+        for slot, x, wl, W, d, lev in items:
+            x = torch.as_tensor(x).to(device=device, dtype=torch.float64)
+            W = torch.as_tensor(W).to(device=device, dtype=torch.complex64)
+            L, K = int(W.shape[0]), int(W.shape[1])
+            inst.append(bb_instance(n_ant=L, n_eig=K, slot=int(slot), wavelength_m=float(wl), ant_off=ant_off,
+                                    w_off=w_off, eig_off=eig_off))
+            xs.append(x)
+            Ws.append(W.transpose(0, 1).contiguous().reshape(-1))      # column-major L x K
+            ds.append(torch.as_tensor(d).to(device=device, dtype=torch.float32).reshape(-1))
+            ls.append(torch.as_tensor(lev).to(device=device, dtype=torch.int32).reshape(-1))
+            ant_off += L
+            w_off += L * K
+            eig_off += K
+        X = torch.cat(xs, dim=0)
+        self.n_ant_rows = int(X.shape[0])
+        self.ant = X.transpose(0, 1).contiguous()                      # column-major n_rows x 3
+        self.W = torch.cat(Ws)
+        self.d = torch.cat(ds)
+        self.lev = torch.cat(ls)
+        self.inst = inst
+        self.products = sum(int(i.n_ant) * int(i.n_eig) for i in inst)

@@ -1,0 +1,292 @@
+"""GPU parity of the HIP synthesis path against the FP64 oracle (through the C ABI).
+
+Tolerances (per level, error normalised by the level's peak, BASELINE target):
+FP32 contraction <= 1e-5, BF16 x3 compensated contraction <= 1e-4.
+"""
+
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as ref
+import sims
+from sims import configs
+from tests._helpers import eig_inputs, level_errors, oracle_images
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "bf16x3": 1e-4}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    from paper_2310_09200_amd import Context
+    c = Context(0)
+    yield c
+
+
+def run_eig(ctx, pix, n_levels, x, wl, W, d, lev, precision="fp32", n_ant_max=None, k_max=None):
+    from paper_2310_09200_amd import StandardSynthesis
+    L, K = W.shape
+    s = StandardSynthesis(ctx, pix, n_levels, 1, n_ant_max or L, k_max or K, precision)
+    s.collect_eig(0, x, wl, W, d, lev)
+    s.sync()
+    out = s.images[0].double().cpu().numpy()
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_c1_against_oracle(ctx, precision):
+    """C1 (L=64, K=64, 128^2 px, 4+1 k-means levels): full image, every level."""
+    say(f"case C1 precision={precision}")
+    w = configs.c1()
+    inst = w.instance(0)
+    lam, W, iv, lev = eig_inputs(inst.V, inst.x, inst.wl, 64, 4)
+    want = oracle_images(W, lam, lev, inst.x, inst.wl, w.pix, 5)
+    got = run_eig(ctx, w.pix, 5, inst.x, inst.wl, W, lam, lev, precision)
+    err = level_errors(got, want)
+    say("C1", precision, "max err per level", err[:, 0])
+    assert np.all(err[:, 0] <= TOL[precision]), err
+
+
+CASES = [  # (L, K, n_side): ragged antenna / eigenpair / pixel counts covering every tile shape
+    (7, 5, 23), (50, 37, 37), (64, 64, 40), (129, 100, 41), (300, 200, 29), (333, 300, 19), (512, 512, 17),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("L,K,n_side", CASES)
+def test_ragged_random_eigpairs(ctx, L, K, n_side, precision):
+    """Random W/lambda with unsorted level ids incl. -1; pixel tail not a multiple of the tile."""
+    say(f"case ragged L={L} K={K} n_side={n_side} precision={precision}")
+    g = np.random.default_rng(1000 + L + K)
+    x = sims.disk_layout(L, 3000.0, g, z_sigma_m=2.0)
+    wl = sims.wavelength_m(150e6)
+    pix = sims.pixel_grid(n_side, 6.0, 60.0)
+    W = sims.random_eigvecs(L, K, g)
+    d = g.normal(0, 1, K)
+    n_levels = 3
+    lev = g.integers(-1, n_levels, K).astype(np.int32)
+    d32 = d.astype(np.float32).astype(np.float64)
+    want = oracle_images(W.astype(np.complex64).astype(np.complex128), d32, lev, x, wl, pix, n_levels)
+    got = run_eig(ctx, pix, n_levels, x, wl, W, d, lev, precision)
+    err = level_errors(got, want)
+    say("max err per level", err[:, 0] if err.size else err)
+    assert np.all(err[:, 0] <= TOL[precision]), err
+
+
+def test_all_levels_dropped_leaves_images_zero(ctx):
+    say("case all level ids -1")
+    g = np.random.default_rng(5)
+    x = sims.disk_layout(40, 1000.0, g)
+    pix = sims.pixel_grid(16, 5.0, 90.0)
+    W = sims.random_eigvecs(40, 20, g)
+    got = run_eig(ctx, pix, 2, x, 2.0, W, np.ones(20), -np.ones(20, np.int32))
+    assert np.all(got == 0)
+
+
+def test_accumulation_and_determinism(ctx):
+    """Two collects accumulate (sum over time steps); identical runs are bitwise equal."""
+    from paper_2310_09200_amd import StandardSynthesis
+    say("case accumulation/determinism")
+    w = configs.c1(n_ant=48, n_side=64)
+    inst = w.instance(0)
+    lam, W, iv, lev = eig_inputs(inst.V, inst.x, inst.wl, 48, 2)
+    outs = []
+    for rep in range(2):
+        s = StandardSynthesis(ctx, w.pix, 3, 2, 48, 48)
+        s.collect_eig(1, inst.x, inst.wl, W, lam, lev)
+        s.collect_eig(1, inst.x, inst.wl, W, lam, lev)
+        s.sync()
+        assert s.count == 2
+        outs.append(s.images.cpu().numpy())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+    assert np.all(outs[0][0] == 0)
+    want = 2 * oracle_images(W, lam, lev, inst.x, inst.wl, w.pix, 3)
+    assert np.all(level_errors(outs[0][1], want)[:, 0] <= 1e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_full_collect_prestep_on_gpu(ctx, precision):
+    """bb_synth_collect: FP64 Gram + rocSOLVER eigensolve + selection + levels + synthesis on the GPU."""
+    from paper_2310_09200_amd import StandardSynthesis
+    say(f"case full collect C1 precision={precision}")
+    w = configs.c1()
+    inst = w.instance(0)
+    img_ref, lam, W, member = ref.collect(inst.V, inst.x, inst.wl, w.pix, 64,
+                                          sims.kmeans1d_intervals(ref.geneig(inst.V, ref.gram(inst.x, inst.wl))[0],
+                                                                  4, negative_level=True))
+    iv = sims.kmeans1d_intervals(lam, 4, negative_level=True)
+    s = StandardSynthesis(ctx, w.pix, 5, 1, 64, 64, precision)
+    s.collect(0, inst.x, inst.wl, inst.V, 64, iv)
+    s.sync()
+    got = s.images[0].double().cpu().numpy()
+    t = s.timings()
+    s.close()
+    err = level_errors(got, img_ref)
+    say("full collect max err per level", err[:, 0], "timings ms", t)
+    assert np.all(err[:, 0] <= TOL[precision]), err
+
+
+def test_full_collect_truncated(ctx):
+    """n_eig < L keeps the largest eigenvalues (signed), here with the standardized filter."""
+    from paper_2310_09200_amd import StandardSynthesis
+    say("case full collect truncated, std filter")
+    w = configs.c1(n_ant=40, n_side=48)
+    inst = w.instance(0)
+    lam_all, A = ref.geneig(inst.V, ref.gram(inst.x, inst.wl))
+    lam, W = ref.select_top(lam_all, A, 12)
+    iv = sims.kmeans1d_intervals(lam, 2, negative_level=True)
+    member = ref.level_membership(lam, iv)
+    want = ref.synthesize_blas(W, ref.std_filter(lam), member, inst.x, w.pix, inst.wl)
+    s = StandardSynthesis(ctx, w.pix, 3, 1, 40, 40, "fp32", filter="std")
+    s.collect(0, inst.x, inst.wl, inst.V, 12, iv)
+    s.sync()
+    got = s.images[0].double().cpu().numpy()
+    s.close()
+    assert np.all(level_errors(got, want)[:, 0] <= 1e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_batched_uneven_instances(ctx, precision):
+    """One launch over uneven instances in several slots equals the per-slot oracle sums."""
+    from paper_2310_09200_amd import Batch, StandardSynthesis
+    say(f"case batched precision={precision}")
+    w = configs.c4(n_channels=3, n_steps=4, n_side=40)
+    items, want = [], np.zeros((3, 4, w.n_pix))
+    for i in range(w.n_instances()):
+        inst = w.instance(i)
+        items.append((inst.slot, inst.x, inst.wl, inst.W, inst.lam, inst.level_of))
+        Wc = inst.W.astype(np.complex64).astype(np.complex128)
+        want[inst.slot] += oracle_images(Wc, inst.lam.astype(np.float32), inst.level_of, inst.x, inst.wl, w.pix, 4)
+    b = Batch(items, ctx.device)
+    s = StandardSynthesis(ctx, w.pix, 4, 3, 512, 128, precision)
+    s.collect_eig_batched(b)
+    s.sync()
+    got = s.images.double().cpu().numpy()
+    s.close()
+    for sl in range(3):
+        err = level_errors(got[sl], want[sl])
+        say("slot", sl, "max err", err[:, 0])
+        assert np.all(err[:, 0] <= TOL[precision]), (sl, err)
+
+
+def _sample_pixels(n_side, src, stride=8):
+    iy, ix = np.meshgrid(np.arange(0, n_side, stride), np.arange(0, n_side, stride), indexing="ij")
+    sel = set((iy * n_side + ix).ravel().tolist())
+    for p in src:
+        cy, cx = divmod(int(p), n_side)
+        for dy in range(-4, 5):
+            for dx in range(-4, 5):
+                y, x_ = cy + dy, cx + dx
+                if 0 <= y < n_side and 0 <= x_ < n_side:
+                    sel.add(y * n_side + x_)
+    return np.array(sorted(sel))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_c2_full_size_sampled(ctx, precision):
+    """C2 at full size (L=512, K=512, 1024^2, 8+1 levels), two epochs, sampled pixels vs oracle."""
+    from paper_2310_09200_amd import StandardSynthesis
+    say(f"case C2 full size precision={precision}")
+    w = configs.c2(n_steps=100)
+    steps = [0, 63]
+    sel = _sample_pixels(w.n_side, w.source_pixels(), stride=16)
+    want = np.zeros((9, sel.size))
+    s = StandardSynthesis(ctx, w.pix, 9, 1, 512, 512, precision)
+    iv = None
+    for st in steps:
+        inst = w.instance(st)
+        lam, A = ref.geneig(inst.V, ref.gram(inst.x, inst.wl))
+        lam, W = ref.select_top(lam, A, 512)
+        if iv is None:
+            iv = sims.kmeans1d_intervals(lam, 8, negative_level=True)
+        lev = sims.levels_from_intervals(lam, iv)
+        Wc = W.astype(np.complex64).astype(np.complex128)
+        want += oracle_images(Wc, lam.astype(np.float32), lev, inst.x, inst.wl, w.pix[sel], 9)
+        s.collect_eig(0, inst.x, inst.wl, W, lam, lev)
+    s.sync()
+    got = s.images[0][:, torch.as_tensor(sel, device=ctx.device)].double().cpu().numpy()
+    s.close()
+    err = level_errors(got, want)
+    say("C2 max err per level", err[:, 0])
+    assert np.all(err[:, 0] <= TOL[precision]), err
+
+
+# ---------------------------------------------------------------- error paths (forced from the host)
+def _status(fn):
+    from paper_2310_09200_amd import BluebildError
+    with pytest.raises(BluebildError) as e:
+        fn()
+    return e.value.status
+
+
+def test_error_codes_from_host(ctx):
+    from paper_2310_09200_amd import StandardSynthesis, _lib
+    say("case error codes")
+    g = np.random.default_rng(0)
+    pix = sims.pixel_grid(8, 5.0, 90.0)
+    s = StandardSynthesis(ctx, pix, 2, 1, 16, 16)
+    x = sims.disk_layout(16, 100.0, g)
+    V = sims.add_noise_snr(sims.visibility(x, pix[:3], np.ones(3), 2.0), sims.psd_noise(16, g), 10.0)
+    iv = np.array([[1.0, np.inf], [-np.inf, 0.5]])
+    before = s.images.clone()
+    # shape beyond the handle's maxima
+    assert _status(lambda: s.collect(0, np.zeros((17, 3)), 2.0, np.eye(17), 4, iv)) == _lib.BB_ERR_SHAPE
+    # bad slot, bad wavelength, n_eig > n_ant
+    assert _status(lambda: s.collect(1, x, 2.0, V, 4, iv)) == _lib.BB_ERR_INVALID_ARG
+    assert _status(lambda: s.collect(0, x, -2.0, V, 4, iv)) == _lib.BB_ERR_INVALID_ARG
+    assert _status(lambda: s.collect(0, x, float("nan"), V, 4, iv)) == _lib.BB_ERR_INVALID_ARG
+    # interval with min > max, overlapping intervals, NaN bound
+    assert _status(lambda: s.collect(0, x, 2.0, V, 4, np.array([[2.0, 1.0], [-1.0, 0.0]]))) == _lib.BB_ERR_INVALID_ARG
+    assert _status(lambda: s.collect(0, x, 2.0, V, 4, np.array([[0.0, 2.0], [1.0, 3.0]]))) == _lib.BB_ERR_INVALID_ARG
+    assert _status(lambda: s.collect(0, x, 2.0, V, 4, np.array([[np.nan, 2.0], [-1.0, 0.0]]))) == _lib.BB_ERR_INVALID_ARG
+    # coincident antennas: G is singular, the Cholesky factorisation fails
+    x2 = x.copy()
+    x2[3] = x2[2]
+    assert _status(lambda: s.collect(0, x2, 2.0, V, 4, iv)) == _lib.BB_ERR_NOT_POSDEF
+    s.sync()
+    assert torch.equal(s.images, before)  # failed calls leave the images untouched
+    # level id out of range is reported by sync and ignored
+    W = sims.random_eigvecs(16, 4, g)
+    s.collect_eig(0, x, 2.0, W, np.ones(4), np.array([0, 5, 1, -1], np.int32))
+    assert _status(lambda: s.sync()) == _lib.BB_ERR_INVALID_ARG
+    s.sync()  # flag cleared
+    # too small a workspace
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    st = lib.bb_synth_create(ctx.handle, ctypes.byref(s.opt), s.n_pix, ctypes.c_void_p(s.pix_cm.data_ptr()),
+                             ctypes.c_void_p(s.images.data_ptr()), ctypes.c_void_p(s.workspace.data_ptr()), 1024,
+                             ctypes.byref(h))
+    assert st == _lib.BB_ERR_WORKSPACE
+    # destroying a context with a live handle
+    assert lib.bb_context_destroy(ctx.handle) == _lib.BB_ERR_STATE
+    s.close()
+
+
+def test_reset_and_count(ctx):
+    from paper_2310_09200_amd import StandardSynthesis
+    say("case reset/count")
+    g = np.random.default_rng(1)
+    pix = sims.pixel_grid(8, 5.0, 90.0)
+    s = StandardSynthesis(ctx, pix, 1, 1, 8, 8)
+    x = sims.disk_layout(8, 100.0, g)
+    s.collect_eig(0, x, 2.0, sims.random_eigvecs(8, 8, g), np.ones(8), np.zeros(8, np.int32))
+    s.sync()
+    assert s.count == 1 and float(s.images.abs().sum()) > 0
+    s.reset()
+    s.sync()
+    assert s.count == 0 and float(s.images.abs().sum()) == 0
+    s.count = 7
+    assert s.count == 7
+    s.close()
