@@ -618,11 +618,46 @@ bb_status bb_synth_collect_eig_batched(bb_synth h, int32_t n_inst, const bb_inst
 }
 
 // ---- backward -------------------------------------------------------------
+namespace {
+
+struct BwdPlan {
+  int L_pad, K_alloc, n_split;
+  int64_t split_len;
+  size_t off_E, off_dd, off_dW, off_dx, total;
+};
+
+BwdPlan plan_backward(int64_t n_pix, int n_ant, int n_eig) {
+  BwdPlan b{};
+  b.L_pad = bb::round_up(n_ant, bb::kAntChunk);
+  b.K_alloc = bb::round_up(n_eig, 32);
+  const int64_t tiles = (int64_t)(b.L_pad / 32) * (b.K_alloc / 32);
+  int64_t want = (1024 + tiles - 1) / tiles;
+  const int64_t max_split = (n_pix + 63) / 64;
+  if (want > max_split) want = max_split;
+  if (want < 1) want = 1;
+  b.split_len = ((n_pix + want - 1) / want + 63) / 64 * 64;
+  b.n_split = (int)((n_pix + b.split_len - 1) / b.split_len);
+  size_t p = 0;
+  b.off_E = p;
+  p += align_up((size_t)2 * b.K_alloc * n_pix * 4);
+  b.off_dd = p;
+  p += align_up((size_t)b.K_alloc * b.n_split * 8);
+  b.off_dW = p;
+  p += align_up((size_t)b.n_split * b.L_pad * b.K_alloc * 2 * 8);
+  b.off_dx = p;
+  p += align_up((size_t)b.n_split * b.L_pad * 3 * 8);
+  b.total = p;
+  return b;
+}
+
+}  // namespace
+
 bb_status bb_backward_workspace_size(bb_synth h, int32_t n_ant, int32_t n_eig, size_t* bytes) {
   if (!h || !bytes) return BB_ERR_INVALID_ARG;
-  (void)n_ant;
-  (void)n_eig;
-  return fail(h->ctx, BB_ERR_STATE, "backward not available in this build");
+  bb_status st = check_instance_args(h, 0, n_ant, n_eig, 1.0);
+  if (st != BB_OK) return st;
+  *bytes = plan_backward(h->n_pix, n_ant, n_eig).total;
+  return BB_OK;
 }
 
 bb_status bb_synth_eig_backward(bb_synth h, int32_t n_ant, int32_t n_eig, double wavelength_m,
@@ -630,9 +665,79 @@ bb_status bb_synth_eig_backward(bb_synth h, int32_t n_ant, int32_t n_eig, double
                                 const float* grad_images, void* dW, float* dd, double* dx, void* workspace,
                                 size_t ws_bytes) {
   if (!h) return BB_ERR_INVALID_ARG;
-  (void)n_ant; (void)n_eig; (void)wavelength_m; (void)ant_xyz; (void)W; (void)d; (void)level_of;
-  (void)grad_images; (void)dW; (void)dd; (void)dx; (void)workspace; (void)ws_bytes;
-  return fail(h->ctx, BB_ERR_STATE, "backward not available in this build");
+  bb_context ctx = h->ctx;
+  bb_status st = check_instance_args(h, 0, n_ant, n_eig, wavelength_m);
+  if (st != BB_OK) return st;
+  if (!ant_xyz || !W || !d || !level_of || !grad_images || !dW || !dd || !dx || !workspace)
+    return fail(ctx, BB_ERR_INVALID_ARG, "null device pointer");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return fail(ctx, BB_ERR_INVALID_ARG, "workspace must be %zu-byte aligned", kAlign);
+  const BwdPlan bp = plan_backward(h->n_pix, n_ant, n_eig);
+  if (ws_bytes < bp.total) return fail(ctx, BB_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, bp.total);
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  char* ws = static_cast<char*>(workspace);
+  InstDesc dsc = staging_desc(h, h->ws + h->lay.apack, n_ant, n_eig, wavelength_m, 0);
+  dsc.ant = ant_xyz;
+  dsc.ant_ld = n_ant;
+  dsc.W = W;
+  dsc.W_ld = n_ant;
+  dsc.W_c128 = 0;
+  dsc.wcol = nullptr;
+  dsc.d = d;
+  dsc.lev_in = level_of;
+  SingleMeta* meta = at<SingleMeta>(h, h->lay.meta);
+  BB_HIP(ctx, hipEventRecord(h->ev[0], s));
+  BB_HIP(ctx, hipEventRecord(h->ev[1], s));
+  hipLaunchKernelGGL(write_meta_kernel, dim3(1), dim3(1), 0, s, meta, dsc, 0);
+  BB_HIP(ctx, hipGetLastError());
+  BB_HIP(ctx, bb::launch_stage(&meta->desc, &meta->dyn, 1, dsc.K_alloc, dsc.L_pad, h->opt.n_levels, 0,
+                               at<int>(h, h->lay.err), s));
+  BB_HIP(ctx, hipEventRecord(h->ev[2], s));
+  bb::FwdParams p{};
+  p.pix = h->pix;
+  p.pix_ld = h->n_pix;
+  p.n_pix = h->n_pix;
+  p.descs = &meta->desc;
+  p.dyn = &meta->dyn;
+  p.group_slot = &meta->group_slot;
+  p.group_begin = meta->group_begin;
+  p.inst_list = &meta->inst_list;
+  p.img = nullptr;
+  p.img_ld = h->n_pix;
+  p.n_levels = h->opt.n_levels;
+  const int nt = bb::fields_tile_pixels(dsc.K_alloc);
+  p.n_tiles = (int)((h->n_pix + nt - 1) / nt);
+  p.n_items = p.n_tiles;
+  p.e_out = reinterpret_cast<float*>(ws + bp.off_E);
+  p.e_ld = h->n_pix;
+  p.e_rows = dsc.K_alloc;
+  BB_HIP(ctx, bb::launch_fields(p, dsc.K_alloc, s));
+  bb::BwdParams b{};
+  b.pix = h->pix;
+  b.pix_ld = h->n_pix;
+  b.n_pix = h->n_pix;
+  b.desc = &meta->desc;
+  b.dyn = &meta->dyn;
+  b.gimg = grad_images;
+  b.gimg_ld = h->n_pix;
+  b.E = p.e_out;
+  b.K_alloc = dsc.K_alloc;
+  b.L_pad = dsc.L_pad;
+  b.L = n_ant;
+  b.K = n_eig;
+  b.W = W;
+  b.n_split = bp.n_split;
+  b.split_len = bp.split_len;
+  b.dd_part = reinterpret_cast<double*>(ws + bp.off_dd);
+  b.dW_part = reinterpret_cast<double*>(ws + bp.off_dW);
+  b.dx_part = reinterpret_cast<double*>(ws + bp.off_dx);
+  b.scale_x = -4.0 * M_PI / wavelength_m;
+  BB_HIP(ctx, bb::launch_backward(b, s));
+  BB_HIP(ctx, bb::launch_backward_reduce(b, dW, dd, dx, s));
+  BB_HIP(ctx, hipEventRecord(h->ev[3], s));
+  h->timed = true;
+  return BB_OK;
 }
 
 // ---- misc -------------------------------------------------------------------

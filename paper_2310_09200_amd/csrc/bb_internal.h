@@ -57,6 +57,9 @@ struct FwdParams {
   int n_levels;
   int n_tiles;
   int64_t n_items;
+  float* e_out;            // backward only: E planes [2][e_rows][e_ld]
+  int64_t e_ld;
+  int e_rows;
 };
 
 // Staging (launchers in synth_kernels.hip).
@@ -85,19 +88,26 @@ hipError_t launch_export_eig(const double* A_c128, const double* evals, int L, i
                              const float* dsel, const int* lsel, float* W_out_c64, double* lam_out, float* d_out,
                              int* lev_out, hipStream_t s);
 
-// Backward (synth_bwd.hip).
+// Backward.
+// E recompute (FP32 MFMA, one instance) into two planes [2][K_alloc][n_pix].
+hipError_t launch_fields(const FwdParams& p, int K_alloc, hipStream_t s);
+int fields_tile_pixels(int K_alloc);
+
 struct BwdParams {
   const double* pix; int64_t pix_ld; int64_t n_pix;
   const InstDesc* desc; const InstDyn* dyn;
-  const float* gimg; int64_t gimg_ld; int n_levels;
-  // outputs / partials
-  float* dW_part;   // [n_ptiles][2*K_alloc][2*L_pad] real partials (dW = 2 B M^T)
-  double* dx_part;  // [n_ptiles][L_pad][3]
-  float* dd_part;   // [n_ptiles][K_alloc]
-  int n_ptiles;
+  const float* gimg; int64_t gimg_ld;   // upstream gradient [n_levels][gimg_ld]
+  float* E;                             // [2][K_alloc][n_pix], overwritten by M = d c conj(E)
+  int K_alloc, L_pad, L, K;
+  const void* W;                        // caller's W (complex64, L x K column-major)
+  int n_split;                          // pixel splits of the contractions over pixels
+  int64_t split_len;                    // pixels per split (multiple of 64)
+  double* dd_part;                      // [K_alloc][n_split]
+  double* dW_part;                      // [n_split][L_pad][K_alloc][2]
+  double* dx_part;                      // [n_split][L_pad][3]
+  double scale_x;                       // -(4 pi / wavelength)
 };
-hipError_t launch_backward(const BwdParams& p, int K_alloc, int L_pad, hipStream_t s);
-hipError_t launch_backward_reduce(const BwdParams& p, int K_alloc, int L_pad, int L, int K, void* dW,
-                                  float* dd, double* dx, hipStream_t s);
+hipError_t launch_backward(const BwdParams& p, hipStream_t s);
+hipError_t launch_backward_reduce(const BwdParams& p, void* dW, float* dd, double* dx, hipStream_t s);
 
 }  // namespace bb

@@ -347,7 +347,9 @@ __device__ __forceinline__ void mfma_chunk(f32x16 (&acc)[2 * MB][NB], const f32x
   }
 }
 
-template <int MB, int NB, int WK, int WN, int PREC>
+// MODE 0: level images (the product).  MODE 1: write E itself (two planes,
+// re and im, [K_alloc][n_pix] each) for the backward pass; one instance only.
+template <int MB, int NB, int WK, int WN, int PREC, int MODE>
 __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams P) {
   using C = TileCfg<MB, NB, WK, WN>;
   __shared__ f32x4 s_buf[2][C::CHUNK_VEC];
@@ -410,6 +412,26 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
           __syncthreads();
         }
 
+        if (MODE == 1) {
+#pragma unroll
+          for (int m = 0; m < MB; ++m) {
+            if (m >= mact) break;
+            const int kb = kb0 + m;
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+              const int64_t p = p0 + (cb0 + n) * 32 + (lane & 31);
+              if (p < P.n_pix) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                  const int k = kb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                  P.e_out[(int64_t)k * P.e_ld + p] = acc[2 * m][n][r];
+                  P.e_out[(int64_t)(P.e_rows + k) * P.e_ld + p] = acc[2 * m + 1][n][r];
+                }
+              }
+            }
+          }
+          continue;
+        }
         // epilogue: weighted |E|^2 into per-level partial sums
 #pragma unroll
         for (int m = 0; m < MB; ++m) {
@@ -445,6 +467,7 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
       }
     }
     __syncthreads();
+    if (MODE == 1) continue;
     for (int i = tid; i < n_levels * C::NT; i += C::THREADS) {
       const int l = i / C::NT, pl = i % C::NT;
       const int64_t p = p0 + pl;
@@ -460,13 +483,13 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
   }
 }
 
-template <int MB, int NB, int WK, int WN, int PREC>
+template <int MB, int NB, int WK, int WN, int PREC, int MODE = 0>
 static hipError_t launch_cfg(const FwdParams& p, hipStream_t s) {
   using C = TileCfg<MB, NB, WK, WN>;
   const int64_t grid = p.n_items;
   if (grid <= 0) return hipSuccess;
   const unsigned g = (unsigned)(grid > 0x7fffffff ? 0x7fffffff : grid);
-  hipLaunchKernelGGL((synth_fwd_kernel<MB, NB, WK, WN, PREC>), dim3(g), dim3(C::THREADS), 0, s, p);
+  hipLaunchKernelGGL((synth_fwd_kernel<MB, NB, WK, WN, PREC, MODE>), dim3(g), dim3(C::THREADS), 0, s, p);
   return hipGetLastError();
 }
 
@@ -491,6 +514,19 @@ hipError_t launch_synth(const FwdParams& p, int max_K_alloc, int precision, int 
                         hipStream_t s) {
   if (tile_pixels_out) tile_pixels_out[0] = synth_tile_pixels(max_K_alloc);
   return precision ? launch_prec<1>(p, max_K_alloc, s) : launch_prec<0>(p, max_K_alloc, s);
+}
+
+int fields_tile_pixels(int K_alloc) {
+  if (K_alloc > 256) return TileCfg<2, 2, 8, 1>::NT;
+  if (K_alloc > 128) return TileCfg<1, 4, 8, 1>::NT;
+  return TileCfg<1, 4, 4, 2>::NT;
+}
+
+hipError_t launch_fields(const FwdParams& p, int K_alloc, hipStream_t s) {
+  // FP32 recompute of E for the backward pass (the handle's precision does not apply)
+  if (K_alloc > 256) return launch_cfg<2, 2, 8, 1, 0, 1>(p, s);
+  if (K_alloc > 128) return launch_cfg<1, 4, 8, 1, 0, 1>(p, s);
+  return launch_cfg<1, 4, 4, 2, 0, 1>(p, s);
 }
 
 __global__ void fill_zero_kernel(float* p, int64_t n) {

@@ -151,6 +151,33 @@ class StandardSynthesis:
             _ptr(batch.lev), ctypes.c_void_p(ws_ptr), sz.value), self.ctx.handle)
         self._keep = [ws]
 
+    def eig_backward(self, x, wavelength, W, d, level_of, grad_images):
+        """Gradient of sum(grad_images * I) for one instance's images I (before accumulation).
+
+        Returns (dW (L,K) complex64 = dLoss/dRe W + j dLoss/dIm W, dd (K,) float32, dx (L,3) float64).
+        """
+        dev = self.ctx.device
+        L, K = int(W.shape[0]), int(W.shape[1])
+        xc = _colmajor(torch.as_tensor(x), torch.float64, dev)
+        Wc = _colmajor(torch.as_tensor(W), torch.complex64, dev)
+        dc = torch.as_tensor(d).to(device=dev, dtype=torch.float32).contiguous()
+        lc = torch.as_tensor(level_of).to(device=dev, dtype=torch.int32).contiguous()
+        g = torch.as_tensor(grad_images).to(device=dev, dtype=torch.float32).reshape(self.n_levels,
+                                                                                     self.n_pix).contiguous()
+        dWt = torch.empty((K, L), dtype=torch.complex64, device=dev)
+        dd = torch.empty(K, dtype=torch.float32, device=dev)
+        dxt = torch.empty((3, L), dtype=torch.float64, device=dev)
+        sz = ctypes.c_size_t()
+        check(self.lib.bb_backward_workspace_size(self.handle, L, K, ctypes.byref(sz)), self.ctx.handle)
+        ws = torch.empty(int(sz.value) + 256, dtype=torch.uint8, device=dev)
+        ws_ptr = (ws.data_ptr() + 255) // 256 * 256
+        self.ctx.bind_current_stream()
+        check(self.lib.bb_synth_eig_backward(self.handle, L, K, float(wavelength), _ptr(xc), _ptr(Wc), _ptr(dc),
+                                             _ptr(lc), _ptr(g), _ptr(dWt), _ptr(dd), _ptr(dxt),
+                                             ctypes.c_void_p(ws_ptr), sz.value), self.ctx.handle)
+        self._keep = [xc, Wc, dc, lc, g, ws]
+        return dWt.transpose(0, 1), dd, dxt.transpose(0, 1)
+
     def sync(self):
         check(self.lib.bb_synth_sync(self.handle), self.ctx.handle)
 

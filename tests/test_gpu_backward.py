@@ -1,0 +1,113 @@
+"""GPU backward kernels vs the FP64 oracle gradient (itself checked against finite differences)."""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as ref
+import sims
+from sims import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    from paper_2310_09200_amd import Context
+    return Context(0)
+
+
+def _case(L, K, n_side, seed, n_levels=3, drop=True):
+    g = np.random.default_rng(seed)
+    x = sims.disk_layout(L, 2000.0, g, z_sigma_m=1.0)
+    wl = sims.wavelength_m(150e6)
+    pix = sims.pixel_grid(n_side, 5.0, 90.0)
+    W = sims.random_eigvecs(L, K, g).astype(np.complex64)
+    d = g.normal(0, 1, K).astype(np.float32)
+    lev = g.integers(-1 if drop else 0, n_levels, K).astype(np.int32)
+    wts = g.standard_normal((n_levels, pix.shape[0])).astype(np.float32)
+    return x, wl, pix, W, d, lev, wts
+
+
+def _compare(ctx, x, wl, pix, W, d, lev, wts, n_levels, tol):
+    from paper_2310_09200_amd import StandardSynthesis
+    s = StandardSynthesis(ctx, pix, n_levels, 1, W.shape[0], W.shape[1])
+    dW, dd, dx = s.eig_backward(x, wl, W, d, lev, wts)
+    s.sync()
+    dW, dd, dx = dW.cpu().numpy(), dd.cpu().numpy(), dx.cpu().numpy()
+    s.close()
+    member = ref.membership_from_level_of(lev, n_levels)
+    rW, rd, rx = ref.grad_ref.grad(W.astype(np.complex128), d.astype(np.float64), x, member,
+                                   wts.astype(np.float64), pix, wl)
+    eW = np.max(np.abs(dW - rW)) / np.max(np.abs(rW))
+    ed = np.max(np.abs(dd - rd)) / np.max(np.abs(rd))
+    ex = np.max(np.abs(dx - rx)) / np.max(np.abs(rx))
+    say(f"grad rel errors: dW {eW:.2e} dd {ed:.2e} dx {ex:.2e}")
+    assert eW < tol and ed < tol and ex < tol, (eW, ed, ex)
+    # eigenpairs in no level get exactly zero gradient
+    assert np.all(dW[:, lev < 0] == 0) and np.all(dd[lev < 0] == 0)
+
+
+@pytest.mark.parametrize("L,K,n_side", [(8, 4, 16), (37, 20, 33), (100, 70, 40), (256, 64, 64)])
+def test_backward_matches_oracle_gradient(ctx, L, K, n_side):
+    say(f"case backward L={L} K={K} n_side={n_side}")
+    x, wl, pix, W, d, lev, wts = _case(L, K, n_side, 7 + L)
+    _compare(ctx, x, wl, pix, W, d, lev, wts, 3, 2e-4)
+
+
+def test_backward_c5_full_size(ctx):
+    """C5: L=256, K=64 top eigenpairs, 512^2 pixels, 4 levels, loss weights w ~ N(0,1)."""
+    say("case backward C5 full size")
+    w = configs.c5()
+    inst = w.instance(0)
+    lam, A = ref.geneig(inst.V, ref.gram(inst.x, inst.wl))
+    lam, W = ref.select_top(lam, A, 64)
+    iv = sims.kmeans1d_intervals(lam, 4, negative_level=False)
+    lev = sims.levels_from_intervals(lam, iv)
+    wts = w.meta["loss_weights"]().astype(np.float32)
+    _compare(ctx, inst.x, inst.wl, w.pix, W.astype(np.complex64), lam.astype(np.float32), lev, wts, 4, 2e-4)
+
+
+def test_autograd_function(ctx):
+    """torch.autograd through bluebild_image equals the oracle gradient; forward equals the oracle image."""
+    from paper_2310_09200_amd import bluebild_image
+    say("case autograd")
+    x, wl, pix, W, d, lev, wts = _case(48, 24, 32, 99, drop=False)
+    dev = ctx.device
+    Wt = torch.tensor(W, device=dev, requires_grad=True)
+    dt = torch.tensor(d, device=dev, requires_grad=True)
+    xt = torch.tensor(x, device=dev, requires_grad=True)
+    pt = torch.tensor(pix, device=dev)
+    img = bluebild_image(Wt, dt, xt, pt, torch.tensor(lev, device=dev), wl, 3)
+    member = ref.membership_from_level_of(lev, 3)
+    want = ref.synthesize_blas(W.astype(np.complex128), d.astype(np.float64), member, x, pix, wl)
+    assert np.max(np.abs(img.detach().double().cpu().numpy() - want)) <= 1e-5 * np.max(np.abs(want))
+    loss = (img * torch.tensor(wts, device=dev)).sum()
+    loss.backward()
+    rW, rd, rx = ref.grad_ref.grad(W.astype(np.complex128), d.astype(np.float64), x, member,
+                                   wts.astype(np.float64), pix, wl)
+    assert np.max(np.abs(Wt.grad.cpu().numpy() - rW)) <= 2e-4 * np.max(np.abs(rW))
+    assert np.max(np.abs(dt.grad.cpu().numpy() - rd)) <= 2e-4 * np.max(np.abs(rd))
+    assert np.max(np.abs(xt.grad.cpu().numpy() - rx)) <= 2e-4 * np.max(np.abs(rx))
+
+
+def test_backward_deterministic(ctx):
+    from paper_2310_09200_amd import StandardSynthesis
+    say("case backward determinism")
+    x, wl, pix, W, d, lev, wts = _case(64, 32, 40, 5)
+    outs = []
+    for _ in range(2):
+        s = StandardSynthesis(ctx, pix, 3, 1, 64, 32)
+        r = s.eig_backward(x, wl, W, d, lev, wts)
+        s.sync()
+        outs.append([t.cpu().numpy() for t in r])
+        s.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
