@@ -131,6 +131,9 @@ def main():
     ap.add_argument("--cpu-stride", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the other precision")
+    ap.add_argument("--calibration-copy-mb", type=int, default=0,
+                    help="before timing, copy this many MiB device-to-device once (a kernel of known traffic "
+                         "for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (instances or pixel tiles would be "
@@ -142,6 +145,14 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda", 0)
 
+    if args.calibration_copy_mb > 0:
+        n = args.calibration_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibration_copy_mb} MiB read + {args.calibration_copy_mb} MiB written")
+        del src, dst
     ctx, w, intervals, items, insts = build_inputs(args, torch, dev)
     n_levels = intervals.shape[0]
     other = "bf16x3" if args.precision == "fp32" else "fp32"
