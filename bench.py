@@ -120,17 +120,23 @@ def cpu_baseline(args, w, items, n_levels):
                       f"L=512, K=512, FP64 numpy/BLAS, {dt:.1f} s"}, sel, img
 
 
+MODES = ("fp32_3m", "fp32", "bf16x3", "bf16x3_3m")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--precision", default="fp32_3m", choices=MODES,
+                    help="contraction of the headline line: fp32_3m (FP32, three real products per complex "
+                         "product), fp32 (FP32, four), bf16x3 (BF16 hi/lo, three bf16 products per real product, "
+                         "four real products), bf16x3_3m (BF16 hi/lo, three real products)")
     ap.add_argument("--epochs", type=int, default=100)
     ap.add_argument("--n-side", type=int, default=1024)
     ap.add_argument("--cpu-stride", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-compare", action="store_true", help="skip the other precision")
+    ap.add_argument("--no-compare", action="store_true", help="time only the headline contraction mode")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="before timing, copy this many MiB device-to-device once (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -155,26 +161,25 @@ def main():
         del src, dst
     ctx, w, intervals, items, insts = build_inputs(args, torch, dev)
     n_levels = intervals.shape[0]
-    other = "bf16x3" if args.precision == "fp32" else "fp32"
+    modes = [args.precision] + ([] if args.no_compare else [m for m in MODES if m != args.precision])
 
-    ms, kern, stage, products = time_mode(args, torch, ctx, w, items, args.precision, n_levels)
-    value = products * w.n_pix / (ms / 1000.0)
-    res = {}
-    if not args.no_compare:
-        ms_o, kern_o, stage_o, _ = time_mode(args, torch, ctx, w, items, other, n_levels)
-        res[other] = (ms_o, kern_o)
+    timing = {}
+    for m in modes:
+        timing[m] = time_mode(args, torch, ctx, w, items, m, n_levels)
+    ms, kern, stage, products = timing[args.precision]
+    total_products = products * w.n_pix
+    value = total_products / (ms / 1000.0)
 
     cpu, sel, ref_img = (None, None, None)
     if not args.no_cpu_baseline:
         cpu, sel, ref_img = cpu_baseline(args, w, items, n_levels)
 
-    flops = 8.0 * products * w.n_pix
-    if args.precision == "fp32":
-        achieved = flops / (kern / 1000.0) / 1e12
-        peak = FP32_PEAK_TFLOPS
-    else:
-        achieved = 3 * flops / (kern / 1000.0) / 1e12
-        peak = BF16_PEAK_TFLOPS
+    # executed MFMA work per product: 8 flop (four real MACs), 6 (three); BF16 x3 three times that in bf16
+    exec_flop = {"fp32": 8.0, "fp32_3m": 6.0, "bf16x3": 24.0, "bf16x3_3m": 18.0}
+    peak = {"fp32": FP32_PEAK_TFLOPS, "fp32_3m": FP32_PEAK_TFLOPS, "bf16x3": BF16_PEAK_TFLOPS,
+            "bf16x3_3m": BF16_PEAK_TFLOPS}
+    flops = exec_flop[args.precision] * total_products
+    achieved = flops / (kern / 1000.0) / 1e12
     out = {
         "metric": "pixel*antenna*eigvec products/s for standard synthesis; compensated vs plain FP32 at 1e-4",
         "value": value,
@@ -186,34 +191,44 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "bf16x3",
+        "dtype": "bf16x3" if args.precision.startswith("bf16") else "f32",
         "data": "synthetic",
         "config": {"workload": f"LOFAR-like single channel: L=512 stations (50 km), K=512 eigenpairs, "
                                f"{w.n_side}x{w.n_side} pixels over 10 deg, {args.epochs} epochs over 6 h, "
                                f"{n_levels - 1}+1 k-means levels, FP64 phase arguments",
                    "n_ant": 512, "n_eig": 512, "n_pix": w.n_pix, "n_instances": args.epochs,
-                   "n_levels": n_levels, "precision": args.precision, "launch": "batched (one synthesis launch "
-                   "over all epochs per step)"},
+                   "n_levels": n_levels, "contraction": args.precision,
+                   "launch": "batched: one synthesis launch over all epochs per step"},
         "fp32_equivalent_mfma_fraction": 8.0 * value / (FP32_PEAK_TFLOPS * 1e12),
         "kernel_ms_per_step": kern,
         "staging_ms_per_step": stage,
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "synth_fwd_kernel", "flops_per_launch": flops * (3 if args.precision != "fp32" else 1)},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak[args.precision], "unit": "TFLOP/s",
+                     "frac": achieved / peak[args.precision], "traffic": None,
+                     "kernel": "synth_fwd_kernel",
+                     "flops_per_launch": flops,
+                     "flop_per_product": exec_flop[args.precision]},
     }
-    if res:
-        ms_o, kern_o = res[other]
-        v_o = products * w.n_pix / (ms_o / 1000.0)
-        t_fp32 = ms if args.precision == "fp32" else ms_o
-        t_bf = ms_o if args.precision == "fp32" else ms
-        out["compensated_vs_fp32"] = {"other_precision": other, "other_value": v_o, "other_ms_per_step": ms_o,
-                                      "other_kernel_ms": kern_o, "speedup_bf16x3_over_fp32": t_fp32 / t_bf}
+    modes_out = {}
+    for m in modes:
+        ms_m, kern_m, _, _ = timing[m]
+        modes_out[m] = {"value": total_products / (ms_m / 1000.0), "ms_per_step": ms_m, "kernel_ms": kern_m,
+                        "fp32_equivalent_mfma_fraction": 8.0 * total_products / (kern_m / 1000.0)
+                        / (FP32_PEAK_TFLOPS * 1e12),
+                        "mfma_fraction_of_own_peak": exec_flop[m] * total_products / (kern_m / 1000.0)
+                        / (peak[m] * 1e12)}
+    out["modes"] = modes_out
+    # compensated (BF16 x3) forms against the plain FP32 forms, whole-step times
+    comp = {}
+    for cm in ("bf16x3", "bf16x3_3m"):
+        for pm in ("fp32", "fp32_3m"):
+            if cm in timing and pm in timing:
+                comp[f"speedup_{cm}_over_{pm}"] = timing[pm][0] / timing[cm][0]
+    if comp:
+        out["compensated_vs_fp32"] = comp
     if cpu is not None:
         out["cpu_baseline"] = cpu
-        errs = {args.precision: spot_error(args, torch, ctx, w, items, args.precision, n_levels, sel, ref_img)}
-        if res:
-            errs[other] = spot_error(args, torch, ctx, w, items, other, n_levels, sel, ref_img)
-        out["max_level_error_vs_oracle"] = errs
+        out["max_level_error_vs_oracle"] = {
+            m: spot_error(args, torch, ctx, w, items, m, n_levels, sel, ref_img) for m in modes}
     print(json.dumps(out), flush=True)
 
 

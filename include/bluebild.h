@@ -56,7 +56,15 @@ typedef enum {
   BB_ERR_STATE = 7        /* wrong object state (e.g. destroying a context with live handles) */
 } bb_status;
 
-typedef enum { BB_PREC_FP32 = 0, BB_PREC_BF16X3 = 1 } bb_precision;
+/* Contraction arithmetic of the synthesis (FP64 phase arguments in every mode):
+ *  BB_PREC_FP32     FP32 MFMA, four real products per complex product
+ *  BB_PREC_BF16X3   BF16 hi/lo split of both operands, hi*hi + hi*lo + lo*hi in FP32 accumulators
+ *  BB_PREC_FP32_3M  FP32 MFMA, three real products per complex product (Gauss):
+ *                   conj(w) b = (k1 - k3) + j (k1 + k2), k1 = (wr - wi) br,
+ *                   k2 = wr (bi - br), k3 = -wi (br + bi)
+ *  BB_PREC_BF16X3_3M  the three-product form with BF16 hi/lo operands and three
+ *                   compensating products each, FP32 accumulators */
+typedef enum { BB_PREC_FP32 = 0, BB_PREC_BF16X3 = 1, BB_PREC_FP32_3M = 2, BB_PREC_BF16X3_3M = 3 } bb_precision;
 typedef enum { BB_FILTER_LSQ = 0, BB_FILTER_STD = 1 } bb_filter;
 
 typedef struct bb_context_* bb_context;
@@ -67,8 +75,7 @@ typedef struct bb_synth_* bb_synth;
  *  n_slots    number of image slots (e.g. channels), >= 1
  *  n_ant_max  largest antenna count of any instance, 1..1024
  *  k_max      largest number of kept eigenpairs, 1..1024, <= n_ant_max for bb_synth_collect
- *  precision  bb_precision: contraction in FP32 MFMA, or BF16 hi/lo split with three
- *             products accumulated in FP32
+ *  precision  bb_precision of the contraction (see above)
  *  filter     bb_filter applied by bb_synth_collect (collect_eig takes weights directly) */
 typedef struct {
   int32_t n_levels;

@@ -20,7 +20,7 @@ STATUS = {
 }
 BB_OK, BB_ERR_INVALID_ARG, BB_ERR_SHAPE, BB_ERR_NOT_POSDEF, BB_ERR_EIGEN, BB_ERR_WORKSPACE, BB_ERR_DEVICE, \
     BB_ERR_STATE = range(8)
-BB_PREC_FP32, BB_PREC_BF16X3 = 0, 1
+BB_PREC_FP32, BB_PREC_BF16X3, BB_PREC_FP32_3M, BB_PREC_BF16X3_3M = 0, 1, 2, 3
 BB_FILTER_LSQ, BB_FILTER_STD = 0, 1
 
 

@@ -156,7 +156,7 @@ bb_status check_options(bb_context ctx, const bb_options* o) {
     return fail(ctx, BB_ERR_INVALID_ARG, "n_ant_max must be in [1, %d]", bb::kMaxAnt);
   if (o->k_max < 1 || o->k_max > bb::kMaxEig)
     return fail(ctx, BB_ERR_INVALID_ARG, "k_max must be in [1, %d]", bb::kMaxEig);
-  if (o->precision != BB_PREC_FP32 && o->precision != BB_PREC_BF16X3)
+  if (o->precision < BB_PREC_FP32 || o->precision > BB_PREC_BF16X3_3M)
     return fail(ctx, BB_ERR_INVALID_ARG, "unknown precision %d", o->precision);
   if (o->filter != BB_FILTER_LSQ && o->filter != BB_FILTER_STD)
     return fail(ctx, BB_ERR_INVALID_ARG, "unknown filter %d", o->filter);
@@ -232,9 +232,9 @@ bb_status run_single(bb_synth h, const InstDesc& d) {
   p.img = h->images;
   p.img_ld = h->n_pix;
   p.n_levels = h->opt.n_levels;
-  const int nt = bb::synth_tile_pixels(d.K_alloc);
-  p.n_tiles = (int)((h->n_pix + nt - 1) / nt);
-  p.n_items = p.n_tiles;
+  const int nt = bb::synth_tile_pixels(d.K_alloc, h->opt.precision);
+  p.n_tiles = (h->n_pix + nt - 1) / nt;
+  p.n_groups = 1;
   BB_HIP(ctx, bb::launch_synth(p, d.K_alloc, h->opt.precision, nullptr, s));
   BB_HIP(ctx, hipEventRecord(h->ev[3], s));
   h->timed = true;
@@ -483,8 +483,18 @@ bb_status bb_synth_prestep(bb_synth h, int32_t n_ant, double wavelength_m, const
 // ---- batched ----------------------------------------------------------------
 namespace {
 
+// Instances are grouped by the tile shape their eigenpair count selects (one
+// persistent launch per shape, largest first); inside a shape, by image slot
+// (slots in decreasing cost order).  Launches are stream-ordered, each has one
+// writer per image tile: the result is deterministic.
+struct Bucket {
+  int kc = 0, max_K_alloc = 0, n_groups = 0;
+  size_t gslot_idx = 0, gbegin_idx = 0;
+};
+
 struct BatchPlan {
   std::vector<InstDesc> descs;
+  std::vector<Bucket> buckets;
   std::vector<int> group_slot, group_begin, inst_list;
   size_t off_descs, off_dyn, off_gslot, off_gbegin, off_ilist, off_stage, total;
   int max_K_alloc = 0, max_L_pad = 0;
@@ -493,8 +503,7 @@ struct BatchPlan {
 bb_status plan_batch(bb_synth h, int32_t n_inst, const bb_instance* inst, int64_t n_ant_rows, BatchPlan& bp) {
   bb_context ctx = h->ctx;
   if (n_inst < 1 || !inst) return fail(ctx, BB_ERR_INVALID_ARG, "empty instance table");
-  std::vector<double> cost(h->opt.n_slots, 0.0);
-  std::vector<std::vector<int>> by_slot(h->opt.n_slots);
+  std::vector<int> kcs;
   for (int i = 0; i < n_inst; ++i) {
     const bb_instance& b = inst[i];
     bb_status st = check_instance_args(h, b.slot, b.n_ant, b.n_eig, b.wavelength_m);
@@ -504,18 +513,37 @@ bb_status plan_batch(bb_synth h, int32_t n_inst, const bb_instance* inst, int64_
     const int L_pad = bb::round_up(b.n_ant, bb::kAntChunk), K_alloc = bb::round_up(b.n_eig, 32);
     bp.max_K_alloc = std::max(bp.max_K_alloc, K_alloc);
     bp.max_L_pad = std::max(bp.max_L_pad, L_pad);
-    cost[b.slot] += (double)L_pad * K_alloc;
-    by_slot[b.slot].push_back(i);
+    const int kc = bb::synth_tile_kc(K_alloc, h->opt.precision);
+    if (std::find(kcs.begin(), kcs.end(), kc) == kcs.end()) kcs.push_back(kc);
   }
-  std::vector<int> slots;
-  for (int s = 0; s < h->opt.n_slots; ++s)
-    if (!by_slot[s].empty()) slots.push_back(s);
-  std::stable_sort(slots.begin(), slots.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-  bp.group_begin.push_back(0);
-  for (int s : slots) {
-    bp.group_slot.push_back(s);
-    for (int i : by_slot[s]) bp.inst_list.push_back(i);
+  std::sort(kcs.begin(), kcs.end(), [](int a, int b) { return a > b; });
+  for (int kc : kcs) {
+    Bucket bk;
+    bk.kc = kc;
+    std::vector<double> cost(h->opt.n_slots, 0.0);
+    std::vector<std::vector<int>> by_slot(h->opt.n_slots);
+    for (int i = 0; i < n_inst; ++i) {
+      const bb_instance& b = inst[i];
+      const int K_alloc = bb::round_up(b.n_eig, 32);
+      if (bb::synth_tile_kc(K_alloc, h->opt.precision) != kc) continue;
+      bk.max_K_alloc = std::max(bk.max_K_alloc, K_alloc);
+      cost[b.slot] += (double)bb::round_up(b.n_ant, bb::kAntChunk) * K_alloc;
+      by_slot[b.slot].push_back(i);
+    }
+    std::vector<int> slots;
+    for (int sl = 0; sl < h->opt.n_slots; ++sl)
+      if (!by_slot[sl].empty()) slots.push_back(sl);
+    std::stable_sort(slots.begin(), slots.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    bk.gslot_idx = bp.group_slot.size();
+    bk.gbegin_idx = bp.group_begin.size();
     bp.group_begin.push_back((int)bp.inst_list.size());
+    for (int sl : slots) {
+      bp.group_slot.push_back(sl);
+      for (int i : by_slot[sl]) bp.inst_list.push_back(i);
+      bp.group_begin.push_back((int)bp.inst_list.size());
+    }
+    bk.n_groups = (int)slots.size();
+    bp.buckets.push_back(bk);
   }
   size_t p = 0;
   bp.off_descs = p;
@@ -595,22 +623,24 @@ bb_status bb_synth_collect_eig_batched(bb_synth h, int32_t n_inst, const bb_inst
   BB_HIP(ctx, bb::launch_stage(d_descs, d_dyn, n_inst, bp.max_K_alloc, bp.max_L_pad, h->opt.n_levels,
                                h->opt.precision, at<int>(h, h->lay.err), s));
   BB_HIP(ctx, hipEventRecord(h->ev[2], s));
-  bb::FwdParams p{};
-  p.pix = h->pix;
-  p.pix_ld = h->n_pix;
-  p.n_pix = h->n_pix;
-  p.descs = d_descs;
-  p.dyn = d_dyn;
-  p.group_slot = reinterpret_cast<int*>(ws + bp.off_gslot);
-  p.group_begin = reinterpret_cast<int*>(ws + bp.off_gbegin);
-  p.inst_list = reinterpret_cast<int*>(ws + bp.off_ilist);
-  p.img = h->images;
-  p.img_ld = h->n_pix;
-  p.n_levels = h->opt.n_levels;
-  const int nt = bb::synth_tile_pixels(bp.max_K_alloc);
-  p.n_tiles = (int)((h->n_pix + nt - 1) / nt);
-  p.n_items = (int64_t)p.n_tiles * (int64_t)bp.group_slot.size();
-  BB_HIP(ctx, bb::launch_synth(p, bp.max_K_alloc, h->opt.precision, nullptr, s));
+  for (const Bucket& bk : bp.buckets) {
+    bb::FwdParams p{};
+    p.pix = h->pix;
+    p.pix_ld = h->n_pix;
+    p.n_pix = h->n_pix;
+    p.descs = d_descs;
+    p.dyn = d_dyn;
+    p.group_slot = reinterpret_cast<int*>(ws + bp.off_gslot) + bk.gslot_idx;
+    p.group_begin = reinterpret_cast<int*>(ws + bp.off_gbegin) + bk.gbegin_idx;
+    p.inst_list = reinterpret_cast<int*>(ws + bp.off_ilist);
+    p.img = h->images;
+    p.img_ld = h->n_pix;
+    p.n_levels = h->opt.n_levels;
+    const int nt = bb::synth_tile_pixels(bk.max_K_alloc, h->opt.precision);
+    p.n_tiles = (h->n_pix + nt - 1) / nt;
+    p.n_groups = bk.n_groups;
+    BB_HIP(ctx, bb::launch_synth(p, bk.max_K_alloc, h->opt.precision, nullptr, s));
+  }
   BB_HIP(ctx, hipEventRecord(h->ev[3], s));
   h->timed = true;
   h->count += n_inst;
@@ -707,8 +737,8 @@ bb_status bb_synth_eig_backward(bb_synth h, int32_t n_ant, int32_t n_eig, double
   p.img_ld = h->n_pix;
   p.n_levels = h->opt.n_levels;
   const int nt = bb::fields_tile_pixels(dsc.K_alloc);
-  p.n_tiles = (int)((h->n_pix + nt - 1) / nt);
-  p.n_items = p.n_tiles;
+  p.n_tiles = (h->n_pix + nt - 1) / nt;
+  p.n_groups = 1;
   p.e_out = reinterpret_cast<float*>(ws + bp.off_E);
   p.e_ld = h->n_pix;
   p.e_rows = dsc.K_alloc;

@@ -49,14 +49,14 @@ struct FwdParams {
   int64_t n_pix;
   const InstDesc* descs;
   const InstDyn* dyn;
-  const int* group_slot;   // work item i covers group i / n_tiles (image slot group_slot[g]), tile i % n_tiles
+  const int* group_slot;   // image slot of group g (groups in processing order)
   const int* group_begin;  // instances of group g: inst_list[group_begin[g] .. group_begin[g+1])
   const int* inst_list;
+  int n_groups;
   float* img;              // [n_slots][n_levels][img_ld]
   int64_t img_ld;
   int n_levels;
-  int n_tiles;
-  int64_t n_items;
+  int64_t n_tiles;
   float* e_out;            // backward only: E planes [2][e_rows][e_ld]
   int64_t e_ld;
   int e_rows;
@@ -69,7 +69,9 @@ hipError_t launch_stage(const InstDesc* d_descs, InstDyn* d_dyn, int n_inst, int
 // Synthesis: picks a tile configuration from the largest K_alloc of the call.
 hipError_t launch_synth(const FwdParams& p, int max_K_alloc, int precision, int tile_pixels_out[1],
                         hipStream_t s);
-int synth_tile_pixels(int max_K_alloc);
+int synth_tile_pixels(int max_K_alloc, int precision);
+// Eigenpairs per pass of the tile shape picked for this K (identifies the shape).
+int synth_tile_kc(int max_K_alloc, int precision);
 
 // Zero-fill of a float buffer (graph-capture safe, no memset nodes).
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);

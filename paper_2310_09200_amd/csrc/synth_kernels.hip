@@ -30,6 +30,7 @@ namespace bb {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // Phase: (cos, sin) of (q + f) * pi/2 for f in [-1/2, 1/2], q any integer.
@@ -223,16 +224,87 @@ __global__ __launch_bounds__(256) void stage_pack_bf16_kernel(const InstDesc* __
   ((bf16x8*)D.apack)[base + 64] = lo;
 }
 
+// Staging, part 2, FP32 with three real products per complex product (Gauss):
+// conj(W) B = (k1 - k3) + j (k1 + k2) with k1 = (Wr - Wi) Br, k2 = Wr (Bi - Br),
+// k3 = -Wi (Br + Bi).  Three planes (Wr - Wi, Wr, -Wi); 32x32x2 operand order
+// with the two contraction rows of an MFMA step being two antennas:
+// lane = row + 32 * (antenna parity), float4 = 4 steps = 8 antennas.
+__global__ __launch_bounds__(256) void stage_pack_f32g_kernel(const InstDesc* __restrict__ descs) {
+  const InstDesc D = descs[blockIdx.y];
+  const int G8 = D.L_pad / 8;
+  const int64_t total = (int64_t)(D.K_alloc / 32) * 3 * G8 * 64;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int lane = (int)(idx % 64);
+  int64_t rest = idx / 64;
+  const int g = (int)(rest % G8);
+  rest /= G8;
+  const int q = (int)(rest % 3);
+  const int kb = (int)(rest / 3);
+  const int k = kb * 32 + (lane & 31);
+  const int h = lane >> 5;
+  const int src = D.perm[k];
+  f32x4 out;
+  for (int s = 0; s < 4; ++s) {
+    const int l = 8 * g + 2 * s + h;
+    float wr = 0.0f, wi = 0.0f;
+    if (src >= 0 && l < D.L) load_w(D, l, D.wcol ? D.wcol[src] : src, wr, wi);
+    out[s] = q == 0 ? wr - wi : (q == 1 ? wr : -wi);
+  }
+  ((f32x4*)D.apack)[idx] = out;
+}
+
+// Staging, part 2, BF16 x3 with three real products per complex product: the
+// three planes of the FP32 three-product form, each split hi = bf16(a),
+// lo = bf16(a - hi); 32x32x16 operand order with the 16 contraction rows of an
+// MFMA step being 16 antennas: lane = row + 32 * (antenna / 8), 8 antennas per lane.
+__global__ __launch_bounds__(256) void stage_pack_bf16g_kernel(const InstDesc* __restrict__ descs) {
+  const InstDesc D = descs[blockIdx.y];
+  const int G16 = D.L_pad / 16;
+  const int64_t total = (int64_t)(D.K_alloc / 32) * 3 * G16 * 64;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int lane = (int)(idx % 64);
+  int64_t rest = idx / 64;
+  const int g = (int)(rest % G16);
+  rest /= G16;
+  const int q = (int)(rest % 3);
+  const int kb = (int)(rest / 3);
+  const int k = kb * 32 + (lane & 31);
+  const int h = lane >> 5;
+  const int src = D.perm[k];
+  bf16x8 hi, lo;
+  for (int e = 0; e < 8; ++e) {
+    const int l = 16 * g + 8 * h + e;
+    float wr = 0.0f, wi = 0.0f;
+    if (src >= 0 && l < D.L) load_w(D, l, D.wcol ? D.wcol[src] : src, wr, wi);
+    const float v = q == 0 ? wr - wi : (q == 1 ? wr : -wi);
+    const __bf16 vh = (__bf16)v;
+    hi[e] = vh;
+    lo[e] = (__bf16)(v - (float)vh);
+  }
+  const int64_t base = (((int64_t)(kb * 3 + q) * G16 + g) * 2) * 64 + lane;
+  ((bf16x8*)D.apack)[base] = hi;
+  ((bf16x8*)D.apack)[base + 64] = lo;
+}
+
 hipError_t launch_stage(const InstDesc* d_descs, InstDyn* d_dyn, int n_inst, int max_K_alloc, int max_L_pad,
                         int n_levels, int precision, int* d_err, hipStream_t s) {
   if (n_inst <= 0) return hipSuccess;
   hipLaunchKernelGGL(stage_meta_kernel, dim3(n_inst), dim3(256), 0, s, d_descs, d_dyn, n_levels, d_err);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t per = (int64_t)(max_K_alloc / 32) * 2 * (max_L_pad / (precision ? 8 : 4)) * 64;
+  int64_t per = (int64_t)(max_K_alloc / 32) * 2 * (max_L_pad / 4) * 64;
+  if (precision == 1) per = (int64_t)(max_K_alloc / 32) * 2 * (max_L_pad / 8) * 64;
+  if (precision == 2) per = (int64_t)(max_K_alloc / 32) * 3 * (max_L_pad / 8) * 64;
+  if (precision == 3) per = (int64_t)(max_K_alloc / 32) * 3 * (max_L_pad / 16) * 64;
   const unsigned gx = (unsigned)((per + 255) / 256);
-  if (precision)
+  if (precision == 3)
+    hipLaunchKernelGGL(stage_pack_bf16g_kernel, dim3(gx, n_inst), dim3(256), 0, s, d_descs);
+  else if (precision == 1)
     hipLaunchKernelGGL(stage_pack_bf16_kernel, dim3(gx, n_inst), dim3(256), 0, s, d_descs);
+  else if (precision == 2)
+    hipLaunchKernelGGL(stage_pack_f32g_kernel, dim3(gx, n_inst), dim3(256), 0, s, d_descs);
   else
     hipLaunchKernelGGL(stage_pack_f32_kernel, dim3(gx, n_inst), dim3(256), 0, s, d_descs);
   return hipGetLastError();
@@ -240,8 +312,11 @@ hipError_t launch_stage(const InstDesc* d_descs, InstDyn* d_dyn, int n_inst, int
 
 // ---------------------------------------------------------------------------
 // Synthesis kernel.
-//   MB x NB: 32x32 output blocks per wave (k-blocks x pixel blocks), each
-//            k-block holding an Er and an Ei accumulator;
+//   PREC:    0 = FP32, four real products per complex product (accumulators Er, Ei)
+//            1 = BF16 x3 (hi/lo split, three bf16 MFMAs per real product; Er, Ei)
+//            2 = FP32, three real products (Gauss; accumulators k1, k2, k3)
+//            3 = BF16 x3 of the three-product form (k1, k2, k3)
+//   MB x NB: 32x32 output blocks per wave (k-blocks x pixel blocks);
 //   WK x WN: waves along k and along pixels.
 template <int MB, int NB, int WK, int WN>
 struct TileCfg {
@@ -253,11 +328,23 @@ struct TileCfg {
   static constexpr int LCH = NT <= 128 ? 32 : 16;  // antennas per LDS chunk
   static constexpr int G4 = LCH / 4;
   static constexpr int G8 = LCH / 8;
+  static constexpr int G16 = LCH / 16;
   static constexpr int CHUNK_VEC = LCH * NT / 2;   // 16-byte vectors per chunk buffer
-  static constexpr int JT = NT * G4 / THREADS;     // (pixel, 4-antenna) tasks per thread
+  static constexpr int TASKS = NT * G4;           // (pixel, 4-antenna) phase tasks per chunk
+  static constexpr int JT = (TASKS + THREADS - 1) / THREADS;
   static_assert(THREADS % NT == 0, "a thread keeps one pixel");
-  static_assert(JT >= 1 && NT * G4 % THREADS == 0, "task split");
+  static_assert(TASKS % THREADS == 0 || TASKS < THREADS, "task split");
   static_assert(kAntChunk % LCH == 0, "antenna padding covers the chunk");
+};
+
+template <int PREC>
+struct Acc {
+  static constexpr int N = PREC >= 2 ? 3 : 2;  // accumulator tiles per output block
+};
+
+template <class C, int PREC>
+struct ChunkVec {  // 16-byte vectors per LDS phase chunk
+  static constexpr int N = PREC >= 2 ? 3 * C::LCH * C::NT / 4 : C::CHUNK_VEC;
 };
 
 template <class C, int PREC>
@@ -266,10 +353,49 @@ __device__ __forceinline__ void gen_chunk(f32x4* __restrict__ buf, const double*
 #pragma unroll
   for (int j = 0; j < C::JT; ++j) {
     const int t = tid + j * C::THREADS;
+    if (C::TASKS < C::THREADS && t >= C::TASKS) break;
     const int pl = t % C::NT;
-    const int g4 = __builtin_amdgcn_readfirstlane(t / C::NT);
+    // wave-uniform when a wave's 64 lanes share one antenna group
+    const int g4 = C::NT % 64 == 0 ? __builtin_amdgcn_readfirstlane(t / C::NT) : t / C::NT;
     const int cb = pl >> 5, jj = pl & 31;
     float cr[4], ci[4];
+    if (PREC == 3) {
+      // lane (h, jj) of a plane holds antennas 16 g16 + 8 h + e, e = 0..7; this
+      // task fills e = 4 half .. 4 half + 3 (8 bytes of each 16-byte operand)
+      const int g16 = g4 >> 2, h = (g4 >> 1) & 1, half = g4 & 1;
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        phase_pair(xs_chunk + 4 * (16 * g16 + 8 * h + 4 * half + s), px, py, pz, cr[s], ci[s]);
+      bf16x4* b4 = (bf16x4*)buf;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        bf16x4 hi, lo;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const float v = q == 0 ? cr[s] : (q == 1 ? ci[s] - cr[s] : cr[s] + ci[s]);
+          const __bf16 vh = (__bf16)v;
+          hi[s] = vh;
+          lo[s] = (__bf16)(v - (float)vh);
+        }
+        const int o = ((((g16 * 3 + q) * C::NCB + cb) * 2) * 64 + h * 32 + jj) * 2 + half;
+        b4[o] = hi;
+        b4[o + 128] = lo;
+      }
+      continue;
+    }
+    if (PREC == 2) {
+      // antennas 8 g8 + 2 s + h (s = 0..3): one lane of each of the three B planes
+      const int g8 = g4 >> 1, h = g4 & 1;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) phase_pair(xs_chunk + 4 * (8 * g8 + 2 * s + h), px, py, pz, cr[s], ci[s]);
+      f32x4 vr = {cr[0], cr[1], cr[2], cr[3]};
+      f32x4 vd = {ci[0] - cr[0], ci[1] - cr[1], ci[2] - cr[2], ci[3] - cr[3]};
+      f32x4 vs = {cr[0] + ci[0], cr[1] + ci[1], cr[2] + ci[2], cr[3] + ci[3]};
+      buf[((g8 * 3 + 0) * C::NCB + cb) * 64 + h * 32 + jj] = vr;
+      buf[((g8 * 3 + 1) * C::NCB + cb) * 64 + h * 32 + jj] = vd;
+      buf[((g8 * 3 + 2) * C::NCB + cb) * 64 + h * 32 + jj] = vs;
+      continue;
+    }
 #pragma unroll
     for (int s = 0; s < 4; ++s) phase_pair(xs_chunk + 4 * (4 * g4 + s), px, py, pz, cr[s], ci[s]);
     if (PREC == 0) {
@@ -297,10 +423,66 @@ __device__ __forceinline__ void gen_chunk(f32x4* __restrict__ buf, const double*
 
 // MFMA over one LDS chunk for the first M (<= MB) k-blocks of this wave.
 template <class C, int PREC, int M, int MB, int NB>
-__device__ __forceinline__ void mfma_chunk(f32x16 (&acc)[2 * MB][NB], const f32x4* __restrict__ buf,
+__device__ __forceinline__ void mfma_chunk(f32x16 (&acc)[Acc<PREC>::N * MB][NB], const f32x4* __restrict__ buf,
                                            const void* __restrict__ apack, int64_t a_rt_stride_vec,
                                            int64_t a_base_vec, int cb0, int lane) {
-  if (PREC == 0) {
+  if (PREC == 3) {
+    // a_rt_stride_vec: vectors per (k-block, plane); hi at +0, lo at +64 of each group
+    const bf16x8* A = (const bf16x8*)apack;
+    const bf16x8* Bb = (const bf16x8*)buf;
+#pragma unroll
+    for (int g = 0; g < C::G16; ++g) {
+      bf16x8 ah[3 * M], al[3 * M], bh[3 * NB], bl[3 * NB];
+#pragma unroll
+      for (int t = 0; t < 3 * M; ++t) {
+        const int64_t o = a_base_vec + t * a_rt_stride_vec + (int64_t)g * 128 + lane;
+        ah[t] = A[o];
+        al[t] = A[o + 64];
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+          const int o = (((g * 3 + q) * C::NCB + cb0 + n) * 2) * 64 + lane;
+          bh[3 * n + q] = Bb[o];
+          bl[3 * n + q] = Bb[o + 64];
+        }
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            f32x16& c = acc[3 * m + q][n];
+            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[3 * m + q], bh[3 * n + q], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[3 * m + q], bl[3 * n + q], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[3 * m + q], bh[3 * n + q], c, 0, 0, 0);
+          }
+    }
+  } else if (PREC == 2) {
+    // a_rt_stride_vec: vectors per (k-block, plane); planes q = 0, 1, 2 pair with Br, Bi - Br, Br + Bi
+    const f32x4* A = (const f32x4*)apack;
+#pragma unroll
+    for (int g = 0; g < C::G8; ++g) {
+      f32x4 a[3 * M], b[3 * NB];
+#pragma unroll
+      for (int t = 0; t < 3 * M; ++t) a[t] = A[a_base_vec + t * a_rt_stride_vec + (int64_t)g * 64 + lane];
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int n = 0; n < NB; ++n) b[3 * n + q] = buf[((g * 3 + q) * C::NCB + cb0 + n) * 64 + lane];
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+#pragma unroll
+          for (int n = 0; n < NB; ++n)
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+              acc[3 * m + q][n] =
+                  __builtin_amdgcn_mfma_f32_32x32x2f32(a[3 * m + q][s], b[3 * n + q][s], acc[3 * m + q][n], 0, 0, 0);
+    }
+  } else if (PREC == 0) {
     const f32x4* A = (const f32x4*)apack;
 #pragma unroll
     for (int g = 0; g < C::G4; ++g) {
@@ -352,7 +534,8 @@ __device__ __forceinline__ void mfma_chunk(f32x16 (&acc)[2 * MB][NB], const f32x
 template <int MB, int NB, int WK, int WN, int PREC, int MODE>
 __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams P) {
   using C = TileCfg<MB, NB, WK, WN>;
-  __shared__ f32x4 s_buf[2][C::CHUNK_VEC];
+  __shared__ f32x4 s_buf[2][ChunkVec<C, PREC>::N];
+  constexpr int NA = Acc<PREC>::N;
   __shared__ float s_part[WK][kMaxLevels][C::NT];
 
   const int tid = threadIdx.x;
@@ -363,36 +546,36 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
   const int cb0 = wn * NB;
   const int n_levels = P.n_levels;
 
-  for (int64_t item = blockIdx.x; item < P.n_items; item += gridDim.x) {
-    const int grp = (int)(item / P.n_tiles);
-    const int slot = P.group_slot[grp];
-    const int64_t tile = item % P.n_tiles;
-    const int64_t p0 = tile * C::NT;
-
-    for (int i = tid; i < WK * kMaxLevels * C::NT; i += C::THREADS) (&s_part[0][0][0])[i] = 0.0f;
-
-    // this thread's pixel (phase generation); clamp the ragged tail
-    int64_t pg = p0 + (tid % C::NT);
-    if (pg >= P.n_pix) pg = P.n_pix - 1;
-    const double px = P.pix[pg], py = P.pix[pg + P.pix_ld], pz = P.pix[pg + 2 * P.pix_ld];
-
-    const int ib = P.group_begin[grp], ie = P.group_begin[grp + 1];
-    for (int ii = ib; ii < ie; ++ii) {
-      const int inst = P.inst_list[ii];
+  // Persistent grid: workgroup b owns pixel tiles b, b + gridDim.x, ...; every
+  // workgroup walks the groups (slots) and their instances in the same order,
+  // so the workgroups running at one time stream the same instance's W operand
+  // through L2.  Each image tile has exactly one writer (its owner).
+  for (int grp = 0; grp < P.n_groups; ++grp) {
+   const int slot = P.group_slot[grp];
+   for (int ii = P.group_begin[grp]; ii < P.group_begin[grp + 1]; ++ii) {
+    const int inst = P.inst_list[ii];
+    for (int64_t tile = blockIdx.x; tile < P.n_tiles; tile += gridDim.x) {
+      const int64_t p0 = tile * C::NT;
+      for (int i = tid; i < WK * kMaxLevels * C::NT; i += C::THREADS) (&s_part[0][0][0])[i] = 0.0f;
+      // this thread's pixel (phase generation); clamp the ragged tail
+      int64_t pg = p0 + (tid % C::NT);
+      if (pg >= P.n_pix) pg = P.n_pix - 1;
+      const double px = P.pix[pg], py = P.pix[pg + P.pix_ld], pz = P.pix[pg + 2 * P.pix_ld];
       const InstDesc& D = P.descs[inst];
       const int K_pad = P.dyn[inst].K_pad;
       const int L_pad = D.L_pad;
       const int n_chunks = L_pad / C::LCH;
       const int n_pass = (K_pad + C::KC - 1) / C::KC;
       const double* xs = D.xs;
-      const int64_t a_rt_stride = (int64_t)(L_pad / 4) * 64;  // 16-byte vectors per A row tile (both precisions)
+      // 16-byte vectors per A row tile (per k-block plane for PREC 2)
+      const int64_t a_rt_stride = PREC >= 2 ? (int64_t)(L_pad / 8) * 64 : (int64_t)(L_pad / 4) * 64;
       for (int pass = 0; pass < n_pass; ++pass) {
         const int kb0 = pass * (C::KC / 32) + wk * MB;
         int mact = K_pad / 32 - kb0;
         mact = mact < 0 ? 0 : (mact > MB ? MB : mact);
-        f32x16 acc[2 * MB][NB];
+        f32x16 acc[NA * MB][NB];
 #pragma unroll
-        for (int rt = 0; rt < 2 * MB; ++rt)
+        for (int rt = 0; rt < NA * MB; ++rt)
 #pragma unroll
           for (int n = 0; n < NB; ++n)
 #pragma unroll
@@ -401,14 +584,31 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
         __syncthreads();  // previous users of s_buf are done
         gen_chunk<C, PREC>(s_buf[0], xs, px, py, pz, tid);
         __syncthreads();
+        // Ping-pong: the first half of the waves generates the next chunk and
+        // then multiplies, the second half multiplies first.  Waves are laid
+        // out round-robin over the four SIMDs, so each SIMD holds one wave of
+        // each half and its VALU (phases) and matrix core (MFMA) overlap.
+        const bool gen_first = wave < C::WAVES / 2;
         for (int c = 0; c < n_chunks; ++c) {
-          if (c + 1 < n_chunks)
-            gen_chunk<C, PREC>(s_buf[(c + 1) & 1], xs + 4 * (c + 1) * C::LCH, px, py, pz, tid);
-          const int64_t a_base = (int64_t)(kb0 * 2) * a_rt_stride + (int64_t)c * (C::LCH / 4) * 64;
-          if (mact == MB)
-            mfma_chunk<C, PREC, MB, MB, NB>(acc, s_buf[c & 1], D.apack, a_rt_stride, a_base, cb0, lane);
-          else if (MB > 1 && mact == 1)
-            mfma_chunk<C, PREC, 1, MB, NB>(acc, s_buf[c & 1], D.apack, a_rt_stride, a_base, cb0, lane);
+          const int64_t a_base = PREC >= 2 ? (int64_t)(kb0 * 3) * a_rt_stride + (int64_t)c * (C::LCH / 8) * 64
+                                           : (int64_t)(kb0 * 2) * a_rt_stride + (int64_t)c * (C::LCH / 4) * 64;
+          auto gen = [&]() {
+            if (c + 1 < n_chunks)
+              gen_chunk<C, PREC>(s_buf[(c + 1) & 1], xs + 4 * (c + 1) * C::LCH, px, py, pz, tid);
+          };
+          auto mma = [&]() {
+            if (mact == MB)
+              mfma_chunk<C, PREC, MB, MB, NB>(acc, s_buf[c & 1], D.apack, a_rt_stride, a_base, cb0, lane);
+            else if (MB > 1 && mact == 1)
+              mfma_chunk<C, PREC, 1, MB, NB>(acc, s_buf[c & 1], D.apack, a_rt_stride, a_base, cb0, lane);
+          };
+          if (gen_first) {
+            gen();
+            mma();
+          } else {
+            mma();
+            gen();
+          }
           __syncthreads();
         }
 
@@ -424,8 +624,16 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                   const int k = kb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                  P.e_out[(int64_t)k * P.e_ld + p] = acc[2 * m][n][r];
-                  P.e_out[(int64_t)(P.e_rows + k) * P.e_ld + p] = acc[2 * m + 1][n][r];
+                  float er, ei;
+                  if (PREC >= 2) {
+                    er = acc[3 * m][n][r] - acc[3 * m + 2][n][r];
+                    ei = acc[3 * m][n][r] + acc[3 * m + 1][n][r];
+                  } else {
+                    er = acc[2 * m][n][r];
+                    ei = acc[2 * m + 1][n][r];
+                  }
+                  P.e_out[(int64_t)k * P.e_ld + p] = er;
+                  P.e_out[(int64_t)(P.e_rows + k) * P.e_ld + p] = ei;
                 }
               }
             }
@@ -452,7 +660,14 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
             float e2[16];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-              const float er = acc[2 * m][n][r], ei = acc[2 * m + 1][n][r];
+              float er, ei;
+              if (PREC >= 2) {
+                er = acc[3 * m][n][r] - acc[3 * m + 2][n][r];
+                ei = acc[3 * m][n][r] + acc[3 * m + 1][n][r];
+              } else {
+                er = acc[2 * m][n][r];
+                ei = acc[2 * m + 1][n][r];
+              }
               e2[r] = w[r] * fmaf(er, er, ei * ei);
             }
             for (int l = lr.x; l <= lr.y; ++l) {
@@ -465,55 +680,119 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
           }
         }
       }
-    }
-    __syncthreads();
-    if (MODE == 1) continue;
-    for (int i = tid; i < n_levels * C::NT; i += C::THREADS) {
-      const int l = i / C::NT, pl = i % C::NT;
-      const int64_t p = p0 + pl;
-      if (p < P.n_pix) {
-        float s = 0.0f;
+      __syncthreads();
+      if (MODE == 1) continue;
+      for (int i = tid; i < n_levels * C::NT; i += C::THREADS) {
+        const int l = i / C::NT, pl = i % C::NT;
+        const int64_t p = p0 + pl;
+        if (p < P.n_pix) {
+          float s = 0.0f;
 #pragma unroll
-        for (int q = 0; q < WK; ++q) s += s_part[q][l][pl];
-        float* dst = P.img + ((int64_t)slot * n_levels + l) * P.img_ld + p;
-        *dst += s;
+          for (int q = 0; q < WK; ++q) s += s_part[q][l][pl];
+          float* dst = P.img + ((int64_t)slot * n_levels + l) * P.img_ld + p;
+          *dst += s;
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
+   }
   }
+}
+
+// Resident workgroups of a kernel on the current device (persistent grid size).
+template <class K>
+static int resident_blocks(K kernel, int threads) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess) return 0;
+  return ncu * (per_cu > 0 ? per_cu : 1);
 }
 
 template <int MB, int NB, int WK, int WN, int PREC, int MODE = 0>
 static hipError_t launch_cfg(const FwdParams& p, hipStream_t s) {
   using C = TileCfg<MB, NB, WK, WN>;
-  const int64_t grid = p.n_items;
-  if (grid <= 0) return hipSuccess;
-  const unsigned g = (unsigned)(grid > 0x7fffffff ? 0x7fffffff : grid);
-  hipLaunchKernelGGL((synth_fwd_kernel<MB, NB, WK, WN, PREC, MODE>), dim3(g), dim3(C::THREADS), 0, s, p);
+  if (p.n_tiles <= 0 || p.n_groups <= 0) return hipSuccess;
+  auto kern = synth_fwd_kernel<MB, NB, WK, WN, PREC, MODE>;
+  static int resident = 0;  // per instantiation; one device type per process
+  if (resident <= 0) resident = resident_blocks(kern, C::THREADS);
+  int64_t grid = resident > 0 ? resident : 1024;
+  if (grid > p.n_tiles) grid = p.n_tiles;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(C::THREADS), 0, s, p);
   return hipGetLastError();
 }
 
-int synth_tile_pixels(int max_K_alloc) {
-  if (max_K_alloc > 256) return TileCfg<2, 2, 8, 1>::NT;
-  if (max_K_alloc > 128) return TileCfg<1, 4, 8, 1>::NT;
-  if (max_K_alloc > 64) return TileCfg<1, 4, 4, 2>::NT;
-  if (max_K_alloc > 32) return TileCfg<1, 2, 2, 4>::NT;
-  return TileCfg<1, 2, 1, 4>::NT;
+// Tile shape per precision and largest K of the call (register budget: two
+// waves per SIMD, <= 256 VGPRs each).
+template <int PREC>
+struct Shapes;
+template <>
+struct Shapes<0> {  // 4 products: Er/Ei accumulators, 32 regs per output block
+  template <class F> static hipError_t pick(int K, F f) {
+    if (K > 128) return f(TileCfg<1, 4, 8, 1>{});  // (2 x 2 blocks per wave measured slower)
+    if (K > 64) return f(TileCfg<1, 4, 4, 2>{});
+    if (K > 32) return f(TileCfg<1, 2, 2, 4>{});
+    return f(TileCfg<1, 2, 1, 4>{});
+  }
+};
+template <>
+struct Shapes<1> : Shapes<0> {};
+template <>
+struct Shapes<2> {  // 3 products: k1/k2/k3 accumulators, 48 regs per output block
+  template <class F> static hipError_t pick(int K, F f) {
+    if (K > 128) return f(TileCfg<1, 2, 8, 1>{});
+    if (K > 64) return f(TileCfg<1, 2, 4, 2>{});
+    if (K > 32) return f(TileCfg<1, 2, 2, 4>{});
+    return f(TileCfg<1, 2, 1, 4>{});
+  }
+};
+
+template <int PREC, int MODE, int MB, int NB, int WK, int WN>
+static hipError_t launch_tc(const FwdParams& p, TileCfg<MB, NB, WK, WN>, hipStream_t s) {
+  return launch_cfg<MB, NB, WK, WN, PREC, MODE>(p, s);
+}
+
+template <>
+struct Shapes<3> : Shapes<2> {};
+
+int synth_tile_pixels(int max_K_alloc, int precision) {
+  int nt = 0;
+  auto f = [&](auto cfg) {
+    nt = decltype(cfg)::NT;
+    return hipSuccess;
+  };
+  if (precision >= 2)
+    Shapes<2>::pick(max_K_alloc, f);
+  else
+    Shapes<0>::pick(max_K_alloc, f);
+  return nt;
+}
+
+int synth_tile_kc(int max_K_alloc, int precision) {
+  int kc = 0;
+  auto f = [&](auto cfg) {
+    kc = decltype(cfg)::KC;
+    return hipSuccess;
+  };
+  if (precision >= 2)
+    Shapes<2>::pick(max_K_alloc, f);
+  else
+    Shapes<0>::pick(max_K_alloc, f);
+  return kc;
 }
 
 template <int PREC>
 static hipError_t launch_prec(const FwdParams& p, int max_K_alloc, hipStream_t s) {
-  if (max_K_alloc > 256) return launch_cfg<2, 2, 8, 1, PREC>(p, s);
-  if (max_K_alloc > 128) return launch_cfg<1, 4, 8, 1, PREC>(p, s);
-  if (max_K_alloc > 64) return launch_cfg<1, 4, 4, 2, PREC>(p, s);
-  if (max_K_alloc > 32) return launch_cfg<1, 2, 2, 4, PREC>(p, s);
-  return launch_cfg<1, 2, 1, 4, PREC>(p, s);
+  return Shapes<PREC>::pick(max_K_alloc, [&](auto cfg) { return launch_tc<PREC, 0>(p, cfg, s); });
 }
 
 hipError_t launch_synth(const FwdParams& p, int max_K_alloc, int precision, int tile_pixels_out[1],
                         hipStream_t s) {
-  if (tile_pixels_out) tile_pixels_out[0] = synth_tile_pixels(max_K_alloc);
-  return precision ? launch_prec<1>(p, max_K_alloc, s) : launch_prec<0>(p, max_K_alloc, s);
+  if (tile_pixels_out) tile_pixels_out[0] = synth_tile_pixels(max_K_alloc, precision);
+  if (precision == 1) return launch_prec<1>(p, max_K_alloc, s);
+  if (precision == 2) return launch_prec<2>(p, max_K_alloc, s);
+  if (precision == 3) return launch_prec<3>(p, max_K_alloc, s);
+  return launch_prec<0>(p, max_K_alloc, s);
 }
 
 int fields_tile_pixels(int K_alloc) {

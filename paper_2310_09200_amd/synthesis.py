@@ -13,7 +13,8 @@ import torch
 from . import _lib
 from ._lib import bb_instance, bb_options, check, load
 
-_PREC = {"fp32": _lib.BB_PREC_FP32, "bf16x3": _lib.BB_PREC_BF16X3}
+_PREC = {"fp32": _lib.BB_PREC_FP32, "bf16x3": _lib.BB_PREC_BF16X3, "fp32_3m": _lib.BB_PREC_FP32_3M,
+         "bf16x3_3m": _lib.BB_PREC_BF16X3_3M}
 _FILT = {"lsq": _lib.BB_FILTER_LSQ, "std": _lib.BB_FILTER_STD}
 
 

@@ -18,7 +18,7 @@ from tests._helpers import eig_inputs, level_errors, oracle_images
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-5, "bf16x3": 1e-4}
+TOL = {"fp32": 1e-5, "fp32_3m": 1e-5, "bf16x3": 1e-4, "bf16x3_3m": 1e-4}
 
 
 def say(*a):
@@ -44,7 +44,7 @@ def run_eig(ctx, pix, n_levels, x, wl, W, d, lev, precision="fp32", n_ant_max=No
     return out
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32_3m", "bf16x3", "bf16x3_3m"])
 def test_c1_against_oracle(ctx, precision):
     """C1 (L=64, K=64, 128^2 px, 4+1 k-means levels): full image, every level."""
     say(f"case C1 precision={precision}")
@@ -63,7 +63,7 @@ CASES = [  # (L, K, n_side): ragged antenna / eigenpair / pixel counts covering 
 ]
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32_3m", "bf16x3", "bf16x3_3m"])
 @pytest.mark.parametrize("L,K,n_side", CASES)
 def test_ragged_random_eigpairs(ctx, L, K, n_side, precision):
     """Random W/lambda with unsorted level ids incl. -1; pixel tail not a multiple of the tile."""
@@ -116,7 +116,7 @@ def test_accumulation_and_determinism(ctx):
     assert np.all(level_errors(outs[0][1], want)[:, 0] <= 1e-5)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32_3m", "bf16x3", "bf16x3_3m"])
 def test_full_collect_prestep_on_gpu(ctx, precision):
     """bb_synth_collect: FP64 Gram + rocSOLVER eigensolve + selection + levels + synthesis on the GPU."""
     from paper_2310_09200_amd import StandardSynthesis
@@ -157,7 +157,7 @@ def test_full_collect_truncated(ctx):
     assert np.all(level_errors(got, want)[:, 0] <= 1e-5)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32_3m", "bf16x3", "bf16x3_3m"])
 def test_batched_uneven_instances(ctx, precision):
     """One launch over uneven instances in several slots equals the per-slot oracle sums."""
     from paper_2310_09200_amd import Batch, StandardSynthesis
@@ -194,7 +194,7 @@ def _sample_pixels(n_side, src, stride=8):
     return np.array(sorted(sel))
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32_3m", "bf16x3", "bf16x3_3m"])
 def test_c2_full_size_sampled(ctx, precision):
     """C2 at full size (L=512, K=512, 1024^2, 8+1 levels), two epochs, sampled pixels vs oracle."""
     from paper_2310_09200_amd import StandardSynthesis

@@ -19,7 +19,7 @@ from tests._helpers import level_errors
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-5, "bf16x3": 1e-4}
+TOL = {"fp32": 1e-5, "fp32_3m": 1e-5, "bf16x3": 1e-4, "bf16x3_3m": 1e-4}
 
 
 def say(*a):
@@ -67,7 +67,7 @@ def c3_case():
     return w, sel, items, want
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32_3m", "bf16x3", "bf16x3_3m"])
 def test_c3_precision_study(ctx, c3_case, precision):
     from paper_2310_09200_amd import Batch, StandardSynthesis
     w, sel, items, want = c3_case
@@ -102,7 +102,7 @@ def test_c4_batched_full_size(ctx):
                                                w.pix[sel], inst.wl)
     batch = Batch(items, ctx.device)
     say(f"C4 products {batch.products * w.n_pix:.3e}")
-    s = StandardSynthesis(ctx, w.pix, 4, 64, 512, 128, "fp32")
+    s = StandardSynthesis(ctx, w.pix, 4, 64, 512, 128, "fp32_3m")
     s.collect_eig_batched(batch)
     s.sync()
     t = s.timings()
