@@ -58,27 +58,38 @@ def build_inputs(args, torch, dev):
     return ctx, w, intervals, items, insts
 
 
-def time_mode(args, torch, ctx, w, items, precision, n_levels):
+def time_modes(args, torch, ctx, w, items, modes, n_levels):
+    """Time every contraction mode, interleaved step by step (same thermal / power state for all).
+
+    Returns {mode: (ms per step, synthesis kernel ms, staging ms, products per pixel)}.
+    """
     from paper_2310_09200_amd import Batch, StandardSynthesis
-    s = StandardSynthesis(ctx, w.pix, n_levels, 1, 512, 512, precision)
     batch = Batch(items, ctx.device)
+    handles = {m: StandardSynthesis(ctx, w.pix, n_levels, 1, 512, 512, m) for m in modes}
     for _ in range(args.warmup):
-        s.collect_eig_batched(batch)
+        for m in modes:
+            handles[m].collect_eig_batched(batch)
     torch.cuda.synchronize()
-    kern_ms = []
-    t0 = time.perf_counter()
+    wall = {m: [] for m in modes}
+    kern = {m: [] for m in modes}
     for _ in range(args.steps):
-        s.collect_eig_batched(batch)
-        kern_ms.append(s.timings())       # waits for this step's events (same stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    s.sync()
-    ms_step = (t1 - t0) * 1000.0 / args.steps
-    stage_ms = float(np.mean([k[1] for k in kern_ms]))
-    synth_ms = float(np.mean([k[2] for k in kern_ms]))
-    log(f"{precision}: {ms_step:.1f} ms/step, synthesis kernel {synth_ms:.1f} ms, staging {stage_ms:.2f} ms")
-    s.close()
-    return ms_step, synth_ms, stage_ms, batch.products
+        for m in modes:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            handles[m].collect_eig_batched(batch)
+            torch.cuda.synchronize()
+            wall[m].append((time.perf_counter() - t0) * 1000.0)
+            kern[m].append(handles[m].timings())
+    out = {}
+    for m in modes:
+        handles[m].sync()
+        handles[m].close()
+        ms = float(np.mean(wall[m]))
+        stage = float(np.mean([k[1] for k in kern[m]]))
+        synth = float(np.mean([k[2] for k in kern[m]]))
+        log(f"{m}: {ms:.1f} ms/step, synthesis kernel {synth:.1f} ms, staging {stage:.2f} ms")
+        out[m] = (ms, synth, stage, batch.products)
+    return out
 
 
 def spot_error(args, torch, ctx, w, items, precision, n_levels, sel, ref_img):
@@ -163,9 +174,7 @@ def main():
     n_levels = intervals.shape[0]
     modes = [args.precision] + ([] if args.no_compare else [m for m in MODES if m != args.precision])
 
-    timing = {}
-    for m in modes:
-        timing[m] = time_mode(args, torch, ctx, w, items, m, n_levels)
+    timing = time_modes(args, torch, ctx, w, items, modes, n_levels)
     ms, kern, stage, products = timing[args.precision]
     total_products = products * w.n_pix
     value = total_products / (ms / 1000.0)

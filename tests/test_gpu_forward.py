@@ -196,15 +196,15 @@ def _sample_pixels(n_side, src, stride=8):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp32_3m", "bf16x3", "bf16x3_3m"])
 def test_c2_full_size_sampled(ctx, precision):
-    """C2 at full size (L=512, K=512, 1024^2, 8+1 levels), two epochs, sampled pixels vs oracle."""
-    from paper_2310_09200_amd import StandardSynthesis
+    """C2 at full size (L=512, K=512, 1024^2, 8+1 levels) in the benchmarked launch (batched), sampled pixels."""
+    from paper_2310_09200_amd import Batch, StandardSynthesis
     say(f"case C2 full size precision={precision}")
     w = configs.c2(n_steps=100)
-    steps = [0, 63]
+    steps = [0, 63, 99]
     sel = _sample_pixels(w.n_side, w.source_pixels(), stride=16)
     want = np.zeros((9, sel.size))
-    s = StandardSynthesis(ctx, w.pix, 9, 1, 512, 512, precision)
     iv = None
+    items = []
     for st in steps:
         inst = w.instance(st)
         lam, A = ref.geneig(inst.V, ref.gram(inst.x, inst.wl))
@@ -212,15 +212,41 @@ def test_c2_full_size_sampled(ctx, precision):
         if iv is None:
             iv = sims.kmeans1d_intervals(lam, 8, negative_level=True)
         lev = sims.levels_from_intervals(lam, iv)
-        Wc = W.astype(np.complex64).astype(np.complex128)
-        want += oracle_images(Wc, lam.astype(np.float32), lev, inst.x, inst.wl, w.pix[sel], 9)
-        s.collect_eig(0, inst.x, inst.wl, W, lam, lev)
+        W64 = W.astype(np.complex64)
+        want += oracle_images(W64.astype(np.complex128), lam.astype(np.float32), lev, inst.x, inst.wl, w.pix[sel], 9)
+        items.append((0, inst.x, inst.wl, W64, lam.astype(np.float32), lev))
+    s = StandardSynthesis(ctx, w.pix, 9, 1, 512, 512, precision)
+    s.collect_eig_batched(Batch(items, ctx.device))
     s.sync()
     got = s.images[0][:, torch.as_tensor(sel, device=ctx.device)].double().cpu().numpy()
     s.close()
     err = level_errors(got, want)
     say("C2 max err per level", err[:, 0])
     assert np.all(err[:, 0] <= TOL[precision]), err
+
+
+def test_single_and_batched_launch_agree(ctx):
+    """collect_eig per instance and one batched launch give the same images (to FP32 summation order)."""
+    from paper_2310_09200_amd import Batch, StandardSynthesis
+    say("case single vs batched")
+    g = np.random.default_rng(77)
+    pix = sims.pixel_grid(48, 5.0, 90.0)
+    items = []
+    for i in range(5):
+        L, K = int(g.integers(30, 200)), int(g.integers(5, 150))
+        x = sims.disk_layout(L, 2000.0, g)
+        items.append((i % 2, x, 2.0, sims.random_eigvecs(L, K, g), g.normal(0, 1, K), g.integers(-1, 3, K)))
+    a = StandardSynthesis(ctx, pix, 3, 2, 256, 256, "fp32_3m")
+    for it in items:
+        a.collect_eig(*it)
+    b = StandardSynthesis(ctx, pix, 3, 2, 256, 256, "fp32_3m")
+    b.collect_eig_batched(Batch(items, ctx.device))
+    a.sync()
+    b.sync()
+    ia, ib = a.images.double().cpu().numpy(), b.images.double().cpu().numpy()
+    a.close()
+    b.close()
+    assert np.max(np.abs(ia - ib)) <= 1e-6 * np.max(np.abs(ia))
 
 
 # ---------------------------------------------------------------- error paths (forced from the host)
