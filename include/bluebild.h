@@ -76,7 +76,12 @@ typedef struct bb_synth_* bb_synth;
  *  n_ant_max  largest antenna count of any instance, 1..1024
  *  k_max      largest number of kept eigenpairs, 1..1024, <= n_ant_max for bb_synth_collect
  *  precision  bb_precision of the contraction (see above)
- *  filter     bb_filter applied by bb_synth_collect (collect_eig takes weights directly) */
+ *  filter     bb_filter applied by bb_synth_collect (collect_eig takes weights directly)
+ *  gram       bb_gram used by the pre-step: the instrument's Gram matrix (least-squares
+ *             image), or the identity, which makes the image the back-projected
+ *             (dirty) image diag(Psi V Psi*) of Section 2.8
+ *  reserved   must be 0 */
+typedef enum { BB_GRAM_SINC = 0, BB_GRAM_IDENTITY = 1 } bb_gram;
 typedef struct {
   int32_t n_levels;
   int32_t n_slots;
@@ -84,7 +89,8 @@ typedef struct {
   int32_t k_max;
   int32_t precision;
   int32_t filter;
-  int32_t reserved[2];
+  int32_t gram;
+  int32_t reserved;
 } bb_options;
 
 /* One instance of a batched call.  Offsets index the packed arrays passed to

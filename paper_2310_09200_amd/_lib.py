@@ -22,11 +22,12 @@ BB_OK, BB_ERR_INVALID_ARG, BB_ERR_SHAPE, BB_ERR_NOT_POSDEF, BB_ERR_EIGEN, BB_ERR
     BB_ERR_STATE = range(8)
 BB_PREC_FP32, BB_PREC_BF16X3, BB_PREC_FP32_3M, BB_PREC_BF16X3_3M = 0, 1, 2, 3
 BB_FILTER_LSQ, BB_FILTER_STD = 0, 1
+BB_GRAM_SINC, BB_GRAM_IDENTITY = 0, 1
 
 
 class bb_options(ctypes.Structure):
     _fields_ = [("n_levels", c_int32), ("n_slots", c_int32), ("n_ant_max", c_int32), ("k_max", c_int32),
-                ("precision", c_int32), ("filter", c_int32), ("reserved", c_int32 * 2)]
+                ("precision", c_int32), ("filter", c_int32), ("gram", c_int32), ("reserved", c_int32)]
 
 
 class bb_instance(ctypes.Structure):

@@ -160,6 +160,9 @@ bb_status check_options(bb_context ctx, const bb_options* o) {
     return fail(ctx, BB_ERR_INVALID_ARG, "unknown precision %d", o->precision);
   if (o->filter != BB_FILTER_LSQ && o->filter != BB_FILTER_STD)
     return fail(ctx, BB_ERR_INVALID_ARG, "unknown filter %d", o->filter);
+  if (o->gram != BB_GRAM_SINC && o->gram != BB_GRAM_IDENTITY)
+    return fail(ctx, BB_ERR_INVALID_ARG, "unknown gram mode %d", o->gram);
+  if (o->reserved != 0) return fail(ctx, BB_ERR_INVALID_ARG, "reserved option field must be 0");
   return BB_OK;
 }
 
@@ -417,7 +420,7 @@ static bb_status run_prestep(bb_synth h, int32_t n_ant, double wavelength_m, con
   double* A = at<double>(h, L.A);
   double* G = at<double>(h, L.G);
   BB_HIP(ctx, hipEventRecord(h->ev[0], s));
-  BB_HIP(ctx, bb::launch_gram(ant_xyz, n_ant, n_ant, wavelength_m, G, n_ant, s));
+  BB_HIP(ctx, bb::launch_gram(ant_xyz, n_ant, n_ant, wavelength_m, G, n_ant, h->opt.gram == BB_GRAM_IDENTITY, s));
   BB_HIP(ctx, bb::launch_copy_c128(vis, n_ant, A, n_ant, s));
   rocblas_set_stream(ctx->rb, s);
   if (L.solver_bytes > 0 && rocblas_set_workspace(ctx->rb, h->ws + L.solver, L.solver_bytes) != rocblas_status_success)

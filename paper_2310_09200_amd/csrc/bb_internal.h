@@ -77,7 +77,7 @@ int synth_tile_kc(int max_K_alloc, int precision);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
 
 // Pre-step kernels (prestep.hip).
-hipError_t launch_gram(const double* ant, int64_t ant_ld, int L, double wl, double* G_c128, int ldg,
+hipError_t launch_gram(const double* ant, int64_t ant_ld, int L, double wl, double* G_c128, int ldg, bool identity,
                        hipStream_t s);
 hipError_t launch_copy_c128(const double* src, int L, double* dst, int ldd, hipStream_t s);
 struct Intervals {

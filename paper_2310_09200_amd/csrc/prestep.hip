@@ -13,11 +13,19 @@ namespace bb {
 
 // G_pq = sinc(2 ||x_p - x_q|| / lambda_w), sinc(u) = sin(pi u) / (pi u)
 // (Section 2.2, Eq. gram), stored complex128 column-major for zhegvd.
+// With `identity`, G = I: the eigen-decomposition is then that of V itself and
+// the image is the back-projected (dirty) image of Section 2.8.
 __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ ant, int64_t ant_ld, int L,
-                                                   double inv_wl, double* __restrict__ G, int ldg) {
+                                                   double inv_wl, double* __restrict__ G, int ldg, int identity) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)L * L) return;
   const int p = (int)(idx % L), q = (int)(idx / L);
+  if (identity) {
+    double* g = G + 2 * ((int64_t)q * ldg + p);
+    g[0] = p == q ? 1.0 : 0.0;
+    g[1] = 0.0;
+    return;
+  }
   const double dx = ant[p] - ant[q];
   const double dy = ant[p + ant_ld] - ant[q + ant_ld];
   const double dz = ant[p + 2 * ant_ld] - ant[q + 2 * ant_ld];
@@ -59,10 +67,11 @@ __global__ __launch_bounds__(256) void select_kernel(const double* __restrict__ 
   wcol_out[k] = col;
 }
 
-hipError_t launch_gram(const double* ant, int64_t ant_ld, int L, double wl, double* G, int ldg, hipStream_t s) {
+hipError_t launch_gram(const double* ant, int64_t ant_ld, int L, double wl, double* G, int ldg, bool identity,
+                       hipStream_t s) {
   const int64_t n = (int64_t)L * L;
   hipLaunchKernelGGL(gram_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ant, ant_ld, L, 1.0 / wl,
-                     G, ldg);
+                     G, ldg, identity ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@ from ._lib import bb_instance, bb_options, check, load
 _PREC = {"fp32": _lib.BB_PREC_FP32, "bf16x3": _lib.BB_PREC_BF16X3, "fp32_3m": _lib.BB_PREC_FP32_3M,
          "bf16x3_3m": _lib.BB_PREC_BF16X3_3M}
 _FILT = {"lsq": _lib.BB_FILTER_LSQ, "std": _lib.BB_FILTER_STD}
+_GRAM = {"sinc": _lib.BB_GRAM_SINC, "identity": _lib.BB_GRAM_IDENTITY}
 
 
 def _colmajor(t, dtype, device):
@@ -64,7 +65,7 @@ class StandardSynthesis:
     """
 
     def __init__(self, ctx, pix, n_levels, n_slots=1, n_ant_max=512, k_max=512, precision="fp32", filter="lsq",
-                 images=None):
+                 images=None, gram="sinc"):
         self.ctx = ctx
         self.lib = ctx.lib
         dev = ctx.device
@@ -72,7 +73,7 @@ class StandardSynthesis:
         self.n_levels = int(n_levels)
         self.n_slots = int(n_slots)
         self.opt = bb_options(n_levels=n_levels, n_slots=n_slots, n_ant_max=n_ant_max, k_max=k_max,
-                              precision=_PREC[precision], filter=_FILT[filter])
+                              precision=_PREC[precision], filter=_FILT[filter], gram=_GRAM[gram])
         self.pix_cm = _colmajor(torch.as_tensor(pix), torch.float64, dev)
         if images is None:
             images = torch.zeros((n_slots, n_levels, self.n_pix), dtype=torch.float32, device=dev)

@@ -157,6 +157,21 @@ def test_full_collect_truncated(ctx):
     assert np.all(level_errors(got, want)[:, 0] <= 1e-5)
 
 
+def test_identity_gram_gives_dirty_image(ctx):
+    """gram='identity': the pipeline returns the back-projected image diag(Psi V Psi*) (Section 2.8)."""
+    from paper_2310_09200_amd import StandardSynthesis
+    say("case G = I back-projection")
+    w = configs.c1(n_ant=48, n_side=48)
+    inst = w.instance(0)
+    want = ref.backprojection_image(inst.V, inst.x, w.pix, inst.wl)
+    s = StandardSynthesis(ctx, w.pix, 1, 1, 48, 48, "fp32_3m", gram="identity")
+    s.collect(0, inst.x, inst.wl, inst.V, 48, np.array([[-np.inf, np.inf]]))
+    s.sync()
+    got = s.images[0, 0].double().cpu().numpy()
+    s.close()
+    assert np.max(np.abs(got - want)) <= 1e-5 * np.max(np.abs(want))
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp32_3m", "bf16x3", "bf16x3_3m"])
 def test_batched_uneven_instances(ctx, precision):
     """One launch over uneven instances in several slots equals the per-slot oracle sums."""
