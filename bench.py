@@ -114,6 +114,72 @@ def time_modes(args, torch, ctx, w, items, modes, n_levels):
     return out
 
 
+def measure_c4(args, torch, ctx):
+    """Batched uneven instances (a6): 64 channels x 32 epochs, L 200..512, K 16..128, 512^2 pixels, one call."""
+    from paper_2310_09200_amd import Batch, StandardSynthesis
+    from sims import configs
+    w = configs.c4()
+    items = []
+    for i in range(w.n_instances()):
+        inst = w.instance(i)
+        items.append((inst.slot, inst.x, inst.wl, inst.W.astype(np.complex64), inst.lam.astype(np.float32),
+                      inst.level_of))
+    batch = Batch(items, ctx.device)
+    s = StandardSynthesis(ctx, w.pix, 4, 64, 512, 128, args.precision)
+    s.collect_eig_batched(batch)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.collect_eig_batched(batch)
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1000.0)
+    kern = s.timings()[2]
+    s.close()
+    prods = batch.products * w.n_pix
+    log(f"C4 batched: {np.mean(ms):.1f} ms/call, synthesis {kern:.1f} ms, {prods / (np.mean(ms) / 1e3):.3e} products/s")
+    return {"workload": "2048 uneven instances (64 channels x 32 epochs, L 200..512, K 16..128, 4 levels), "
+                        "512x512 pixels, one batched call", "contraction": args.precision,
+            "products": prods, "ms_per_call": float(np.mean(ms)), "synthesis_kernels_ms": kern,
+            "value": prods / (np.mean(ms) / 1e3), "unit": "products/s",
+            "fp32_equivalent_mfma_fraction": 8.0 * prods / (np.mean(ms) / 1e3) / (FP32_PEAK_TFLOPS * 1e12)}
+
+
+def measure_c5_backward(args, torch, ctx):
+    """Backward (a7): L=256, K=64, 512^2 pixels, 4 levels; forward image and gradients w.r.t. W, d, x."""
+    from paper_2310_09200_amd import StandardSynthesis
+    from sims import configs
+    from sims.levels import kmeans1d_intervals
+    w = configs.c5()
+    inst = w.instance(0)
+    s = StandardSynthesis(ctx, w.pix, 4, 1, 256, 64, "fp32")
+    probe = StandardSynthesis(ctx, w.pix[:1], 1, 1, 256, 256)
+    _, lam, _, _ = probe.prestep(inst.x, inst.wl, inst.V, 64, np.array([[-np.inf, np.inf]]))
+    probe.close()
+    iv = kmeans1d_intervals(lam.cpu().numpy(), 4, negative_level=False)
+    W, lam, d, lev = s.prestep(inst.x, inst.wl, inst.V, 64, iv)
+    gimg = torch.as_tensor(w.meta["loss_weights"](), dtype=torch.float32, device=ctx.device)
+    s.eig_backward(inst.x, inst.wl, W, d, lev, gimg)
+    s.collect_eig(0, inst.x, inst.wl, W, d, lev)
+    torch.cuda.synchronize()
+    fwd, bwd = [], []
+    for _ in range(5):
+        s.collect_eig(0, inst.x, inst.wl, W, d, lev)
+        fwd.append(s.timings()[2])
+        s.eig_backward(inst.x, inst.wl, W, d, lev, gimg)
+        bwd.append(s.timings()[2])
+    s.close()
+    prods = 256 * 64 * w.n_pix
+    f_ms, b_ms = float(np.median(fwd)), float(np.median(bwd))
+    log(f"C5: forward {f_ms:.3f} ms, backward {b_ms:.3f} ms")
+    return {"workload": "L=256, K=64, 512x512 pixels, 4 levels, loss weights N(0,1) per level and pixel",
+            "forward_ms": f_ms, "backward_ms": b_ms, "products": prods,
+            "backward_note": "E recompute (FP32 MFMA) + dd/M, dW = 2 B M^T and H = conj(W) M -> dx on FP32 VALU; "
+                             "about 3x the forward's complex MACs",
+            "backward_vector_fp32_fraction": 3 * 8.0 * prods / (b_ms / 1e3) / (FP32_PEAK_TFLOPS / 2 * 1e12)}
+
+
 def spot_error(args, torch, ctx, w, items, precision, n_levels, sel, ref_img):
     """Per-level max error (peak-normalised) of one epoch on the oracle's sample pixels."""
     from paper_2310_09200_amd import StandardSynthesis
@@ -170,6 +236,7 @@ def main():
     ap.add_argument("--cpu-stride", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="time only the headline contraction mode")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched (C4) and backward (C5) measurements")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="before timing, copy this many MiB device-to-device once (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -256,6 +323,9 @@ def main():
                 comp[f"speedup_{cm}_over_{pm}"] = timing[pm][0] / timing[cm][0]
     if comp:
         out["compensated_vs_fp32"] = comp
+    if not args.no_extra:
+        out["batched_c4"] = measure_c4(args, torch, ctx)
+        out["backward_c5"] = measure_c5_backward(args, torch, ctx)
     if cpu is not None:
         out["cpu_baseline"] = cpu
         out["max_level_error_vs_oracle"] = {

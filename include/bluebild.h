@@ -152,6 +152,28 @@ bb_status bb_synth_collect(bb_synth h, int32_t slot, int32_t n_ant, double wavel
                            const double* ant_xyz, const double* vis, int32_t n_eig,
                            const double* intervals);
 
+/* Full step with beamforming (Section 2.7): the n_ant antenna voltages are
+ * combined into n_beam beams by W_bf, so the data are V^W = W_bf^H V W_bf and
+ * the sampling operator is Phi* = W_bf^H Psi*.  The pre-step solves
+ * V^W a = lambda (W_bf^H G W_bf) a (n_beam x n_beam, FP64), keeps the n_eig
+ * largest, and synthesizes over the n_ant antennas with U = W_bf a.
+ *  W_bf    device, complex128 n_ant x n_beam column-major, 1 <= n_beam <= n_ant
+ *  vis_bf  device, complex128 n_beam x n_beam column-major, Hermitian
+ *  n_eig   1..min(n_beam, k_max)
+ * Otherwise as bb_synth_collect. */
+bb_status bb_synth_collect_beamformed(bb_synth h, int32_t slot, int32_t n_ant, int32_t n_beam,
+                                      double wavelength_m, const double* ant_xyz, const double* W_bf,
+                                      const double* vis_bf, int32_t n_eig, const double* intervals);
+
+/* Full step with N_eig chosen from the eigenvalues (Section 2.6 truncation):
+ * the fewest leading eigenpairs whose eigenvalues add up to at least
+ * energy_fraction (0 < f <= 1) of the sum of the positive eigenvalues, at most
+ * k_max.  n_eig_out (host) receives the count used.  Otherwise as
+ * bb_synth_collect. */
+bb_status bb_synth_collect_energy(bb_synth h, int32_t slot, int32_t n_ant, double wavelength_m,
+                                  const double* ant_xyz, const double* vis, double energy_fraction,
+                                  const double* intervals, int32_t* n_eig_out);
+
 /* The FP64 pre-step of bb_synth_collect alone (Algorithm 1 up to the
  * synthesis call), for callers that keep the eigenpairs, e.g. to image them
  * again or to differentiate the synthesis with respect to them.  Arguments as

@@ -15,9 +15,9 @@ import scipy.linalg as sla
 C_LIGHT = 299_792_458.0
 
 __all__ = [
-    "C_LIGHT", "wavelength", "gram", "check_hermitian", "geneig", "select_top",
+    "C_LIGHT", "wavelength", "gram", "check_hermitian", "geneig", "select_top", "n_eig_for_energy",
     "level_membership", "membership_from_level_of", "lsq_filter", "std_filter", "phases",
-    "synthesize_blas", "synthesize_loops", "collect", "accumulate", "lsq_image",
+    "synthesize_blas", "synthesize_loops", "collect", "collect_beamformed", "accumulate", "lsq_image",
     "backprojection_image", "point_source_image", "rel_errors",
 ]
 
@@ -78,6 +78,25 @@ def select_top(lam, alpha, n_eig):
     lam = np.asarray(lam, np.float64)
     order = np.argsort(-lam, kind="stable")[:n_eig]
     return lam[order], alpha[:, order]
+
+
+def n_eig_for_energy(lam, fraction):
+    """Fewest leading eigenpairs whose eigenvalues reach ``fraction`` of the total energy (Section 2.6).
+
+    Reading: the energy is the sum of the positive eigenvalues; leading means
+    largest by signed value.  Returns K >= 1 (all positive eigenpairs at most,
+    or 1 when there is no positive eigenvalue).
+    """
+    lam = np.sort(np.asarray(lam, np.float64))[::-1]
+    total = float(np.sum(lam[lam > 0]))
+    if total <= 0:
+        return 1
+    acc = 0.0
+    for k, v in enumerate(lam):
+        acc += v
+        if acc >= fraction * total:
+            return k + 1
+    return int(np.sum(lam > 0))
 
 
 def level_membership(lam, intervals):
@@ -176,6 +195,25 @@ def collect(V, x, wl, p, n_eig, intervals, filt="lsq", gram_identity=False, eval
     d = lsq_filter(lam) if filt == "lsq" else std_filter(lam)
     f = synthesize_blas if evaluator == "blas" else synthesize_loops
     return f(W, d, member, x, p, wl), lam, W, member
+
+
+def collect_beamformed(Vw, Wbf, x, wl, p, n_eig, intervals, filt="lsq"):
+    """Full step with beamforming (Section 2.7): antennas combined into beams by Wbf (L x Kb).
+
+    The sampling operator becomes Phi* = Wbf^H Psi*, so the Gram matrix is
+    G^W = Wbf^H G Wbf and the eigenpairs solve Vw a = lambda G^W a (Kb x Kb).
+    The eigen-images are eps = Phi a = Psi (Wbf a): the synthesis runs over the
+    L antennas with U = Wbf a.  Returns (images, lam, U, member).
+    """
+    Wbf = np.asarray(Wbf, np.complex128)
+    Gw = Wbf.conj().T @ gram(x, wl) @ Wbf
+    Gw = 0.5 * (Gw + Gw.conj().T)
+    lam, alpha = geneig(Vw, Gw)
+    lam, alpha = select_top(lam, alpha, n_eig)
+    U = Wbf @ alpha
+    member = level_membership(lam, intervals)
+    d = lsq_filter(lam) if filt == "lsq" else std_filter(lam)
+    return synthesize_blas(U, d, member, x, p, wl), lam, U, member
 
 
 def accumulate(images, slot, step_images):

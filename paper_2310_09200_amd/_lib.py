@@ -47,6 +47,10 @@ PROTOS = {
                                   POINTER(c_void_p)]),
     "bb_synth_collect": (c_int32, [c_void_p, c_int32, c_int32, c_double, c_void_p, c_void_p, c_int32,
                                    POINTER(c_double)]),
+    "bb_synth_collect_beamformed": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_double, c_void_p, c_void_p,
+                                              c_void_p, c_int32, POINTER(c_double)]),
+    "bb_synth_collect_energy": (c_int32, [c_void_p, c_int32, c_int32, c_double, c_void_p, c_void_p, c_double,
+                                          POINTER(c_double), POINTER(c_int32)]),
     "bb_synth_prestep": (c_int32, [c_void_p, c_int32, c_double, c_void_p, c_void_p, c_int32, POINTER(c_double),
                                    c_void_p, c_void_p, c_void_p, c_void_p]),
     "bb_synth_collect_eig": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_double, c_void_p, c_void_p,

@@ -46,7 +46,7 @@ struct SingleMeta {
 
 struct Layout {  // byte offsets into a handle's workspace
   size_t meta, err, apack, xs, wts, levs, kbr, perm;
-  size_t A, G, evals, E, info, dsel, lsel, wcol, solver, solver_bytes;
+  size_t A, G, T, U, evals, E, info, dsel, lsel, wcol, solver, solver_bytes;
   size_t total;
 };
 
@@ -89,6 +89,10 @@ Layout make_layout(const bb_options& o, size_t solver_bytes) {
   l.A = p;
   p += align_up(16 * Lm * Lm);
   l.G = p;
+  p += align_up(16 * Lm * Lm);
+  l.T = p;  // beamforming: G W_bf
+  p += align_up(16 * Lm * Lm);
+  l.U = p;  // beamforming: W_bf alpha
   p += align_up(16 * Lm * Lm);
   l.evals = p;
   p += align_up(8 * Lm);
@@ -395,10 +399,19 @@ bb_status bb_synth_collect_eig(bb_synth h, int32_t slot, int32_t n_ant, int32_t 
 // FP64 pre-step shared by bb_synth_collect and bb_synth_prestep: Gram,
 // generalized eigensolve, selection; leaves weights / level ids / column map
 // in the workspace.  Waits for the eigensolver status.
+// With energy_fraction > 0, n_eig is chosen from the eigenvalues (fewest
+// leading eigenpairs reaching that fraction of the positive eigenvalues' sum,
+// at most k_max) and returned through n_eig_used.
+// With a beamforming matrix W_bf (n_ant x n_beam), the eigenproblem is the
+// beamformed one (V^W, W_bf^H G W_bf) of size n_beam and the eigenvectors
+// are mapped back to antennas, U = W_bf alpha (left in the U region).
 static bb_status run_prestep(bb_synth h, int32_t n_ant, double wavelength_m, const double* ant_xyz,
-                             const double* vis, int32_t n_eig, const double* intervals) {
+                             const double* vis, int32_t n_eig, const double* intervals,
+                             double energy_fraction = 0.0, int32_t* n_eig_used = nullptr,
+                             const double* W_bf = nullptr, int32_t n_beam = 0) {
   bb_context ctx = h->ctx;
-  if (n_eig > n_ant) return fail(ctx, BB_ERR_INVALID_ARG, "n_eig %d > n_ant %d", n_eig, n_ant);
+  const int n_sys = W_bf ? n_beam : n_ant;  // size of the eigenproblem
+  if (energy_fraction <= 0.0 && n_eig > n_ant) return fail(ctx, BB_ERR_INVALID_ARG, "n_eig %d > n_ant %d", n_eig, n_ant);
   if (!ant_xyz || !vis || !intervals) return fail(ctx, BB_ERR_INVALID_ARG, "null pointer");
   const int nl = h->opt.n_levels;
   bb::Intervals iv{};
@@ -421,24 +434,71 @@ static bb_status run_prestep(bb_synth h, int32_t n_ant, double wavelength_m, con
   double* G = at<double>(h, L.G);
   BB_HIP(ctx, hipEventRecord(h->ev[0], s));
   BB_HIP(ctx, bb::launch_gram(ant_xyz, n_ant, n_ant, wavelength_m, G, n_ant, h->opt.gram == BB_GRAM_IDENTITY, s));
-  BB_HIP(ctx, bb::launch_copy_c128(vis, n_ant, A, n_ant, s));
+  BB_HIP(ctx, bb::launch_copy_c128(vis, n_sys, A, n_sys, s));
   rocblas_set_stream(ctx->rb, s);
   if (L.solver_bytes > 0 && rocblas_set_workspace(ctx->rb, h->ws + L.solver, L.solver_bytes) != rocblas_status_success)
     return fail(ctx, BB_ERR_DEVICE, "rocblas_set_workspace failed");
-  rocblas_status rs = rocsolver_zhegvd(ctx->rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, n_ant,
-                                       reinterpret_cast<rocblas_double_complex*>(A), n_ant,
-                                       reinterpret_cast<rocblas_double_complex*>(G), n_ant, at<double>(h, L.evals),
+  using cplx = rocblas_double_complex;
+  const cplx one = {1.0, 0.0}, zero = {0.0, 0.0};
+  cplx* Gc = reinterpret_cast<cplx*>(G);
+  if (W_bf) {
+    // G^W = W_bf^H (G W_bf), written over G's leading n_beam x n_beam block (ld n_beam)
+    cplx* T = at<cplx>(h, L.T);
+    const cplx* Wb = reinterpret_cast<const cplx*>(W_bf);
+    rocblas_status gs = rocblas_zgemm(ctx->rb, rocblas_operation_none, rocblas_operation_none, n_ant, n_beam, n_ant,
+                                      &one, Gc, n_ant, Wb, n_ant, &zero, T, n_ant);
+    if (gs == rocblas_status_success)
+      gs = rocblas_zgemm(ctx->rb, rocblas_operation_conjugate_transpose, rocblas_operation_none, n_beam, n_beam, n_ant,
+                         &one, Wb, n_ant, T, n_ant, &zero, Gc, n_beam);
+    if (gs != rocblas_status_success) {
+      if (L.solver_bytes > 0) rocblas_set_workspace(ctx->rb, nullptr, 0);
+      return fail(ctx, BB_ERR_DEVICE, "rocblas_zgemm status %d", (int)gs);
+    }
+  }
+  rocblas_status rs = rocsolver_zhegvd(ctx->rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, n_sys,
+                                       reinterpret_cast<cplx*>(A), n_sys, Gc, n_sys, at<double>(h, L.evals),
                                        at<double>(h, L.E), at<rocblas_int>(h, L.info));
+  if (rs == rocblas_status_success && W_bf)
+    rs = rocblas_zgemm(ctx->rb, rocblas_operation_none, rocblas_operation_none, n_ant, n_beam, n_beam, &one,
+                       reinterpret_cast<const cplx*>(W_bf), n_ant, reinterpret_cast<cplx*>(A), n_beam, &zero,
+                       at<cplx>(h, L.U), n_ant);
   if (L.solver_bytes > 0) rocblas_set_workspace(ctx->rb, nullptr, 0);
   if (rs == rocblas_status_memory_error) return fail(ctx, BB_ERR_WORKSPACE, "rocSOLVER workspace too small");
-  if (rs != rocblas_status_success) return fail(ctx, BB_ERR_DEVICE, "rocsolver_zhegvd status %d", (int)rs);
+  if (rs != rocblas_status_success) return fail(ctx, BB_ERR_DEVICE, "rocsolver_zhegvd / zgemm status %d", (int)rs);
   BB_HIP(ctx, hipEventRecord(h->ev[1], s));
   rocblas_int info = 0;
+  std::vector<double> ev;
   BB_HIP(ctx, hipMemcpyAsync(&info, at<rocblas_int>(h, L.info), sizeof info, hipMemcpyDeviceToHost, s));
+  if (energy_fraction > 0.0) {
+    ev.resize(n_sys);
+    BB_HIP(ctx, hipMemcpyAsync(ev.data(), at<double>(h, L.evals), sizeof(double) * n_sys, hipMemcpyDeviceToHost, s));
+  }
   BB_HIP(ctx, hipStreamSynchronize(s));
-  if (info > n_ant) return fail(ctx, BB_ERR_NOT_POSDEF, "Gram matrix not positive definite (leading minor %d)", info - n_ant);
+  if (info > n_sys) return fail(ctx, BB_ERR_NOT_POSDEF, "Gram matrix not positive definite (leading minor %d)", info - n_sys);
   if (info != 0) return fail(ctx, BB_ERR_EIGEN, "eigensolver did not converge (info %d)", info);
-  BB_HIP(ctx, bb::launch_select(at<double>(h, L.evals), n_ant, n_eig, iv, nl, h->opt.filter, at<float>(h, L.dsel),
+  if (energy_fraction > 0.0) {
+    // eigenvalues ascending: walk from the largest (Section 2.6 truncation by energy)
+    double total = 0.0;
+    for (double v : ev)
+      if (v > 0.0) total += v;
+    int k = 1;
+    if (total > 0.0) {
+      double acc = 0.0;
+      int npos = 0;
+      for (double v : ev) npos += v > 0.0;
+      k = npos;
+      for (int i = 0; i < n_sys; ++i) {
+        acc += ev[n_sys - 1 - i];
+        if (acc >= energy_fraction * total) {
+          k = i + 1;
+          break;
+        }
+      }
+    }
+    n_eig = std::min(std::min(k, h->opt.k_max), n_sys);
+    if (n_eig_used) *n_eig_used = n_eig;
+  }
+  BB_HIP(ctx, bb::launch_select(at<double>(h, L.evals), n_sys, n_eig, iv, nl, h->opt.filter, at<float>(h, L.dsel),
                                 at<int>(h, L.lsel), at<int>(h, L.wcol), s));
   return BB_OK;
 }
@@ -455,6 +515,58 @@ bb_status bb_synth_collect(bb_synth h, int32_t slot, int32_t n_ant, double wavel
   dsc.ant = ant_xyz;
   dsc.ant_ld = n_ant;
   dsc.W = at<double>(h, L.A);
+  dsc.W_ld = n_ant;
+  dsc.W_c128 = 1;
+  dsc.wcol = at<int>(h, L.wcol);
+  dsc.d = at<float>(h, L.dsel);
+  dsc.lev_in = at<int>(h, L.lsel);
+  return run_single(h, dsc);
+}
+
+bb_status bb_synth_collect_energy(bb_synth h, int32_t slot, int32_t n_ant, double wavelength_m,
+                                  const double* ant_xyz, const double* vis, double energy_fraction,
+                                  const double* intervals, int32_t* n_eig_out) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  bb_status st = check_instance_args(h, slot, n_ant, 1, wavelength_m);
+  if (st != BB_OK) return st;
+  if (!(energy_fraction > 0.0 && energy_fraction <= 1.0))
+    return fail(ctx, BB_ERR_INVALID_ARG, "energy_fraction must be in (0, 1]");
+  if (!n_eig_out) return fail(ctx, BB_ERR_INVALID_ARG, "n_eig_out is NULL");
+  int32_t k = 0;
+  st = run_prestep(h, n_ant, wavelength_m, ant_xyz, vis, 0, intervals, energy_fraction, &k);
+  if (st != BB_OK) return st;
+  *n_eig_out = k;
+  const Layout& L = h->lay;
+  InstDesc dsc = staging_desc(h, h->ws + L.apack, n_ant, k, wavelength_m, slot);
+  dsc.ant = ant_xyz;
+  dsc.ant_ld = n_ant;
+  dsc.W = at<double>(h, L.A);
+  dsc.W_ld = n_ant;
+  dsc.W_c128 = 1;
+  dsc.wcol = at<int>(h, L.wcol);
+  dsc.d = at<float>(h, L.dsel);
+  dsc.lev_in = at<int>(h, L.lsel);
+  return run_single(h, dsc);
+}
+
+bb_status bb_synth_collect_beamformed(bb_synth h, int32_t slot, int32_t n_ant, int32_t n_beam,
+                                      double wavelength_m, const double* ant_xyz, const double* W_bf,
+                                      const double* vis_bf, int32_t n_eig, const double* intervals) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  bb_status st = check_instance_args(h, slot, n_ant, n_eig, wavelength_m);
+  if (st != BB_OK) return st;
+  if (n_beam < 1 || n_beam > n_ant) return fail(ctx, BB_ERR_INVALID_ARG, "n_beam must be in [1, n_ant]");
+  if (n_eig > n_beam) return fail(ctx, BB_ERR_INVALID_ARG, "n_eig %d > n_beam %d", n_eig, n_beam);
+  if (!W_bf) return fail(ctx, BB_ERR_INVALID_ARG, "W_bf is NULL");
+  st = run_prestep(h, n_ant, wavelength_m, ant_xyz, vis_bf, n_eig, intervals, 0.0, nullptr, W_bf, n_beam);
+  if (st != BB_OK) return st;
+  const Layout& L = h->lay;
+  InstDesc dsc = staging_desc(h, h->ws + L.apack, n_ant, n_eig, wavelength_m, slot);
+  dsc.ant = ant_xyz;
+  dsc.ant_ld = n_ant;
+  dsc.W = at<double>(h, L.U);  // U = W_bf alpha, n_ant x n_beam
   dsc.W_ld = n_ant;
   dsc.W_c128 = 1;
   dsc.wcol = at<int>(h, L.wcol);

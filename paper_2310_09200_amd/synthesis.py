@@ -107,6 +107,35 @@ class StandardSynthesis:
                                         ivp), self.ctx.handle)
         self._keep = [xc, Vc]
 
+    def collect_beamformed(self, slot, x, wavelength, W_bf, V_bf, n_eig, intervals):
+        """Full step with beamforming: W_bf (L, Kb) complex, V_bf (Kb, Kb) beamformed visibilities."""
+        dev = self.ctx.device
+        L, Kb = int(W_bf.shape[0]), int(W_bf.shape[1])
+        xc = _colmajor(torch.as_tensor(x), torch.float64, dev)
+        Wc = _colmajor(torch.as_tensor(W_bf), torch.complex128, dev)
+        Vc = _colmajor(torch.as_tensor(V_bf), torch.complex128, dev)
+        iv = np.ascontiguousarray(np.asarray(intervals, np.float64).reshape(self.n_levels, 2).T).ravel()
+        ivp = iv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self.ctx.bind_current_stream()
+        check(self.lib.bb_synth_collect_beamformed(self.handle, slot, L, Kb, float(wavelength), _ptr(xc), _ptr(Wc),
+                                                   _ptr(Vc), int(n_eig), ivp), self.ctx.handle)
+        self._keep = [xc, Wc, Vc]
+
+    def collect_energy(self, slot, x, wavelength, V, energy_fraction, intervals):
+        """Full step keeping the fewest eigenpairs that reach ``energy_fraction`` of the energy; returns K."""
+        dev = self.ctx.device
+        L = int(x.shape[0])
+        xc = _colmajor(torch.as_tensor(x), torch.float64, dev)
+        Vc = _colmajor(torch.as_tensor(V), torch.complex128, dev)
+        iv = np.ascontiguousarray(np.asarray(intervals, np.float64).reshape(self.n_levels, 2).T).ravel()
+        ivp = iv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        k = ctypes.c_int32()
+        self.ctx.bind_current_stream()
+        check(self.lib.bb_synth_collect_energy(self.handle, slot, L, float(wavelength), _ptr(xc), _ptr(Vc),
+                                               float(energy_fraction), ivp, ctypes.byref(k)), self.ctx.handle)
+        self._keep = [xc, Vc]
+        return k.value
+
     def prestep(self, x, wavelength, V, n_eig, intervals):
         """FP64 pre-step alone: returns (W (L,K) complex64, lam (K,) f64, d (K,) f32, level_of (K,) i32) on device."""
         dev = self.ctx.device

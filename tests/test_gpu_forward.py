@@ -157,6 +157,53 @@ def test_full_collect_truncated(ctx):
     assert np.all(level_errors(got, want)[:, 0] <= 1e-5)
 
 
+@pytest.mark.parametrize("fraction", [0.5, 0.9, 1.0])
+def test_energy_truncation(ctx, fraction):
+    """N_eig chosen on the GPU from the eigenvalues equals the oracle's choice; images match."""
+    from paper_2310_09200_amd import StandardSynthesis
+    say(f"case energy truncation {fraction}")
+    w = configs.c1(n_ant=48, n_side=40)
+    inst = w.instance(0)
+    lam_all, A = ref.geneig(inst.V, ref.gram(inst.x, inst.wl))
+    k = ref.n_eig_for_energy(lam_all, fraction)
+    lam, W = ref.select_top(lam_all, A, k)
+    iv = sims.kmeans1d_intervals(lam_all, 2, negative_level=True)
+    member = ref.level_membership(lam, iv)
+    want = ref.synthesize_blas(W, lam, member, inst.x, w.pix, inst.wl)
+    s = StandardSynthesis(ctx, w.pix, 3, 1, 48, 48, "fp32_3m")
+    k_gpu = s.collect_energy(0, inst.x, inst.wl, inst.V, fraction, iv)
+    s.sync()
+    got = s.images[0].double().cpu().numpy()
+    s.close()
+    assert k_gpu == k
+    assert np.all(level_errors(got, want)[:, 0] <= 1e-5)
+
+
+@pytest.mark.parametrize("n_beam", [20, 48])
+def test_beamformed_collect(ctx, n_beam):
+    """Beamforming (Section 2.7) on the GPU vs the oracle: G^W = W^H G W, U = W alpha."""
+    from paper_2310_09200_amd import StandardSynthesis
+    say(f"case beamformed n_beam={n_beam}")
+    w = configs.c1(n_ant=48, n_side=40)
+    inst = w.instance(0)
+    g = np.random.default_rng(n_beam)
+    Wbf = (g.standard_normal((48, n_beam)) + 1j * g.standard_normal((48, n_beam))) / np.sqrt(48)
+    Vw = Wbf.conj().T @ inst.V @ Wbf
+    Vw = 0.5 * (Vw + Vw.conj().T)
+    n_eig = n_beam // 2
+    lam_all, _ = ref.geneig(Vw, Wbf.conj().T @ ref.gram(inst.x, inst.wl) @ Wbf)
+    iv = sims.kmeans1d_intervals(np.sort(lam_all)[::-1][:n_eig], 2, negative_level=True)
+    want, lam, U, member = ref.collect_beamformed(Vw, Wbf, inst.x, inst.wl, w.pix, n_eig, iv)
+    s = StandardSynthesis(ctx, w.pix, 3, 1, 48, 48, "fp32_3m")
+    s.collect_beamformed(0, inst.x, inst.wl, Wbf, Vw, n_eig, iv)
+    s.sync()
+    got = s.images[0].double().cpu().numpy()
+    s.close()
+    err = level_errors(got, want)
+    say("beamformed max err per level", err[:, 0])
+    assert np.all(err[:, 0] <= 1e-5), err
+
+
 def test_identity_gram_gives_dirty_image(ctx):
     """gram='identity': the pipeline returns the back-projected image diag(Psi V Psi*) (Section 2.8)."""
     from paper_2310_09200_amd import StandardSynthesis

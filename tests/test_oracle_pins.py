@@ -341,3 +341,46 @@ def test_gradient_sampled_coordinates_c5_shape():
     coords += [("d", (int(g.integers(64)),)) for _ in range(16)]
     coords += [("x", (int(g.integers(256)), int(g.integers(3)))) for _ in range(16)]
     _check_grad(W, lam, x, member, wts, pix, wl, coords)
+
+
+def test_energy_truncation_definition():
+    """N_eig by energy: brute force over every K on random spectra (with negatives)."""
+    g = np.random.default_rng(8)
+    for _ in range(50):
+        lam = np.concatenate([np.exp(g.normal(0, 2, 30)), -np.abs(g.normal(0, 0.3, 6))])
+        frac = g.uniform(0.05, 1.0)
+        k = ref.n_eig_for_energy(lam, frac)
+        srt = np.sort(lam)[::-1]
+        tot = srt[srt > 0].sum()
+        ok = [kk for kk in range(1, lam.size + 1) if srt[:kk].sum() >= frac * tot]
+        assert k == min(ok)
+    assert ref.n_eig_for_energy(np.array([-1.0, -2.0]), 0.5) == 1
+
+
+def test_beamforming_identity_and_invertible_invariance():
+    """Beamforming (Section 2.7): Wbf = I reproduces the plain step; for an invertible square Wbf
+    the summed LSQ image is unchanged (G^W and V^W transform congruently), closed form by solves."""
+    x, wl, pix, V, _ = tiny_case(L=14, seed=71)
+    one = np.array([[-np.inf, np.inf]])
+    a, *_ = ref.collect(V, x, wl, pix, 14, one)
+    b, *_ = ref.collect_beamformed(V, np.eye(14), x, wl, pix, 14, one)
+    assert rel(b, a) < 1e-10
+    g = np.random.default_rng(72)
+    Wbf = g.standard_normal((14, 14)) + 1j * g.standard_normal((14, 14))
+    Vw = Wbf.conj().T @ V @ Wbf
+    c, *_ = ref.collect_beamformed(Vw, Wbf, x, wl, pix, 14, one)
+    assert rel(c[0], ref.lsq_image(V, ref.gram(x, wl), x, pix, wl)) < 1e-8
+
+
+def test_beamforming_fewer_beams_is_lsq_of_beamformed_operator():
+    """With Kb < L beams the image is diag(Phi (G^W)^-1 V^W (G^W)^-1 Phi*), Phi* = Wbf^H Psi* (no eigensolve)."""
+    x, wl, pix, V, _ = tiny_case(L=16, seed=73)
+    g = np.random.default_rng(74)
+    Wbf = (g.standard_normal((16, 6)) + 1j * g.standard_normal((16, 6))) / 4
+    Vw = Wbf.conj().T @ V @ Wbf
+    img, *_ = ref.collect_beamformed(Vw, Wbf, x, wl, pix, 6, np.array([[-np.inf, np.inf]]))
+    Gw = Wbf.conj().T @ ref.gram(x, wl) @ Wbf
+    Vp = np.linalg.solve(Gw, np.linalg.solve(Gw, Vw).conj().T).conj().T
+    Phi_star = Wbf.conj().T @ ref.phases(x, pix, wl)          # (Kb, N_pix)
+    want = np.real(np.einsum("kp,kq,qp->p", Phi_star.conj(), Vp, Phi_star))
+    assert rel(img[0], want) < 1e-9
