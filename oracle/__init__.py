@@ -14,11 +14,16 @@ bluebild_ref
 grad_ref
     Analytic FP64 gradient of a weighted image loss w.r.t. (W, lambda, x),
     and central finite differences of the same loss.
+levels_ref
+    Exact one-dimensional k-means of the eigenvalues and the level intervals
+    it gives.
+weighting_ref
+    Uniform image weighting: uv cell densities and the weighted visibilities.
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test in
-``tests/test_oracle_pins.py`` (closed forms, invariants, special cases, brute
+``tests/test_oracle_pins.py`` and ``tests/test_oracle_levels_weighting.py`` (closed forms, invariants, special cases, brute
 force); none is "parity unpinned".
 """
 
 from .bluebild_ref import *  # noqa: F401,F403
-from . import grad_ref  # noqa: F401
+from . import grad_ref, levels_ref, weighting_ref  # noqa: F401

@@ -21,6 +21,7 @@ from .geometry import (  # noqa: F401
     hour_angles,
     pixel_grid,
     pixel_index_direction,
+    tangent_basis,
 )
 from .sky import point_sources, gaussian_blobs, grid_sources  # noqa: F401
 from .visibilities import (  # noqa: F401

@@ -91,7 +91,8 @@ def hour_angles(n_steps, span_hours=6.0):
     return np.linspace(-0.5 * span, 0.5 * span, n_steps)
 
 
-def _tangent_basis(dec0_deg):
+def tangent_basis(dec0_deg):
+    """Orthonormal (e1, e2, p0) at the phase centre of declination dec0 (p0 the centre)."""
     d = np.deg2rad(dec0_deg)
     p0 = np.array([np.cos(d), 0.0, np.sin(d)])
     e1 = np.array([0.0, 1.0, 0.0])
@@ -112,7 +113,7 @@ def pixel_grid(n, fov_deg, dec0_deg=90.0):
     direction-cosine grid; ``dec0_deg = 90`` puts the phase centre on +z.
     Returned as an (n*n, 3) float64 array.
     """
-    e1, e2, p0 = _tangent_basis(dec0_deg)
+    e1, e2, p0 = tangent_basis(dec0_deg)
     lc = direction_cosines(n, fov_deg)
     ll, mm = np.meshgrid(lc, lc, indexing="xy")
     ll = ll.ravel()
@@ -123,7 +124,7 @@ def pixel_grid(n, fov_deg, dec0_deg=90.0):
 
 def pixel_index_direction(n, fov_deg, dec0_deg, ix, iy):
     """Unit vector of pixel centre (ix, iy) of :func:`pixel_grid`."""
-    e1, e2, p0 = _tangent_basis(dec0_deg)
+    e1, e2, p0 = tangent_basis(dec0_deg)
     lc = direction_cosines(n, fov_deg)
     ix = np.asarray(ix)
     iy = np.asarray(iy)

@@ -6,13 +6,13 @@ and, for sources placed on pixel centres, their (ix, iy) pixel indices.
 
 import numpy as np
 
-from .geometry import _tangent_basis, direction_cosines, pixel_index_direction
+from .geometry import tangent_basis, direction_cosines, pixel_index_direction
 
 ARCMIN = np.pi / (180.0 * 60.0)
 
 
 def _lm_to_dir(l_, m_, dec0_deg):
-    e1, e2, p0 = _tangent_basis(dec0_deg)
+    e1, e2, p0 = tangent_basis(dec0_deg)
     n_ = np.sqrt(1.0 - l_ * l_ - m_ * m_)
     return l_[:, None] * e1 + m_[:, None] * e2 + n_[:, None] * p0
 
