@@ -19,11 +19,15 @@ levels_ref
     it gives.
 weighting_ref
     Uniform image weighting: uv cell densities and the weighted visibilities.
+nufft_ref
+    NUFFT synthesis: per-level Gram-corrected visibilities, the exact type-3
+    sum over baselines, and its NUFFT approximation step by step.
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test in
-``tests/test_oracle_pins.py`` and ``tests/test_oracle_levels_weighting.py`` (closed forms, invariants, special cases, brute
+``tests/test_oracle_pins.py``, ``tests/test_oracle_levels_weighting.py`` and
+``tests/test_oracle_nufft.py`` (closed forms, invariants, special cases, brute
 force); none is "parity unpinned".
 """
 
 from .bluebild_ref import *  # noqa: F401,F403
-from . import grad_ref, levels_ref, weighting_ref  # noqa: F401
+from . import grad_ref, levels_ref, nufft_ref, weighting_ref  # noqa: F401
