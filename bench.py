@@ -32,8 +32,8 @@ BF16_PEAK_TFLOPS = 2516.6     # MI355X dense BF16 matrix
 # 256 MiB device copy; valid only for the kernel source they were taken on
 # (sha256 of csrc/synth_kernels.hip), reported as null otherwise.
 MEASURED_TRAFFIC = {
-    "fp32_3m": {"bytes": 4.3229e11,
-                "kernel_source_sha256": "144d5241ffd4ea391f5dc8d2c61e126ff7929ec7dc395eea28f1dc5b4b7d680f"},
+    "fp32_3m": {"bytes": 9.0019e10,
+                "kernel_source_sha256": "3edc1d3a97f6c3bdd8c6dc5515cb7c8143b1e2402abb4a18591375a195b61d22"},
 }
 
 

@@ -27,7 +27,8 @@
  *    bb_synth_create until bb_synth_destroy; it keeps no other pointer.
  *  - Work is enqueued on the context's HIP stream, in call order.  Inputs
  *    must stay valid and unmodified until the stream has reached the work;
- *    inputs are never written.  bb_synth_sync waits for the stream.
+ *    inputs are never written (except the visibilities given to
+ *    bb_synth_uniform_weighting).  bb_synth_sync waits for the stream.
  *  - Arguments are validated on the host before anything is enqueued; a call
  *    that returns an error has enqueued nothing and left the images as they
  *    were.  Asynchronous device faults surface as BB_ERR_DEVICE from
@@ -188,6 +189,49 @@ bb_status bb_synth_prestep(bb_synth h, int32_t n_ant, double wavelength_m, const
                            const double* vis, int32_t n_eig, const double* intervals, void* W_out,
                            double* lam_out, float* d_out, int32_t* level_out);
 
+/* Energy levels by k-means on the eigenvalues (Section 2.6; the split of the
+ * positive eigenvalues into levels plus one level for every negative
+ * eigenvalue follows Section 4.2).  The positive eigenvalues are cut into
+ * k = n_levels - negative_level groups by exact one-dimensional k-means (the
+ * partition into contiguous runs of the sorted values with the least total
+ * within-group sum of squared deviations; on equal cost the highest cut is
+ * the lowest possible).  Level 0 holds the largest group; the bound between
+ * two groups is the midpoint of the gap between them, the top bound +inf,
+ * the lowest positive bound b the midpoint between the smallest positive and
+ * the largest non-positive eigenvalue (0 if none); with negative_level = 1
+ * the last level is [-inf, nextafter(b, -inf)].
+ *  n           number of eigenvalues, 1 <= n <= 1024
+ *  lam         device, float64 n eigenvalues, any order
+ *  intervals   device out, float64 n_levels x 2 column-major [min, max]
+ *              (the layout bb_synth_collect takes on the host)
+ *  level_of    device out, int32 n: first interval holding lam[i], else -1
+ * Stream-ordered; images untouched.  Fewer positive eigenvalues than k is
+ * found on the device: intervals become NaN, level_of -1, and the next
+ * bb_synth_sync returns BB_ERR_INVALID_ARG. */
+bb_status bb_synth_levels_kmeans(bb_synth h, int32_t n, const double* lam, int32_t negative_level,
+                                 double* intervals, int32_t* level_of);
+
+/* Uniform image weighting of a visibility matrix, in place (Section 3.5),
+ * for use before bb_synth_collect.  The uv coordinate of baseline (p, q) is
+ * a_pq = <x_p - x_q, e> / lambda_w * fov_rad for e = e_u, e_v, evaluated as
+ * ((d0 e0 + d1 e1) + d2 e2) * (fov_rad / wavelength_m) with no fused
+ * multiply-add; its cell is round(a) with halves away from zero, so cells
+ * are 1/FoV wide and (p, q), (q, p) fall in mirrored cells.  Every V_pq is
+ * divided (real and imaginary parts separately) by the number of ordered
+ * pairs (p', q'), autocorrelations included, in the cell of (p, q).
+ *  ant_xyz     device, float64 n_ant x 3 column-major, metres
+ *  e_u, e_v    host, float64 3 each: image-plane axes at the phase centre
+ *              (same frame as ant_xyz)
+ *  fov_rad     field of view, radians
+ *  vis         device, complex128 n_ant x n_ant column-major, read and
+ *              overwritten (the one input this library writes)
+ * Uses the handle's pre-step workspace (free between calls), so it is
+ * stream-ordered with the handle's other calls.  A cell index beyond +-2^30
+ * (or not finite) leaves that visibility unweighted and makes the next
+ * bb_synth_sync return BB_ERR_INVALID_ARG. */
+bb_status bb_synth_uniform_weighting(bb_synth h, int32_t n_ant, double wavelength_m, const double* ant_xyz,
+                                     const double* e_u, const double* e_v, double fov_rad, double* vis);
+
 /* Hot path only (Section 2.4 and Algorithm 2, given the eigenpairs):
  *  W          device, complex64 n_ant x n_eig column-major (interleaved re, im float32)
  *  d          device, float32 n_eig filter weights (lambda_k for the LSQ filter)
@@ -226,7 +270,10 @@ bb_status bb_synth_eig_backward(bb_synth h, int32_t n_ant, int32_t n_eig, double
                                 const int32_t* level_of, const float* grad_images,
                                 void* dW, float* dd, double* dx, void* workspace, size_t ws_bytes);
 
-/* Wait for all enqueued work; BB_ERR_DEVICE on an asynchronous device error. */
+/* Wait for all enqueued work; BB_ERR_DEVICE on an asynchronous device error,
+ * BB_ERR_INVALID_ARG (and clear it) when a kernel found an input error: a level
+ * id out of range, too few positive eigenvalues for k-means, a uv cell out of
+ * range; bb_last_error names which. */
 bb_status bb_synth_sync(bb_synth h);
 /* Zero every image (stream-ordered) and set the instance count to 0. */
 bb_status bb_synth_reset(bb_synth h);

@@ -15,24 +15,18 @@
 #include <string>
 #include <vector>
 
+#include "api_common.h"
 #include "bb_internal.h"
 #include "bluebild.h"
 
 using bb::InstDesc;
 using bb::InstDyn;
 
-struct bb_context_ {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  rocblas_handle rb = nullptr;
-  std::string err;
-  int live = 0;
-};
 
 namespace {
 
-constexpr size_t kAlign = 256;
-inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+using bb_host::align_up;
+using bb_host::kAlign;
 
 // Device metadata block for single-instance calls (written by a kernel from
 // its arguments, so no host buffer has to outlive the call).
@@ -131,25 +125,8 @@ struct bb_synth_ {
 
 namespace {
 
-bb_status fail(bb_context ctx, bb_status s, const char* fmt, ...) {
-  if (ctx) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    ctx->err = buf;
-  }
-  return s;
-}
-
-#define BB_HIP(ctx, call)                                                                       \
-  do {                                                                                          \
-    hipError_t e_ = (call);                                                                     \
-    if (e_ != hipSuccess) return fail((ctx), BB_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
-
-bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+using bb_host::fail;
+using bb_host::finite_pos;
 
 bb_status check_options(bb_context ctx, const bb_options* o) {
   if (!o) return fail(ctx, BB_ERR_INVALID_ARG, "options is NULL");
@@ -203,7 +180,7 @@ InstDesc staging_desc(bb_synth h, char* base, int L, int K, double wl, int slot)
   d.K = K;
   d.L_pad = bb::round_up(L, bb::kAntChunk);
   d.K_alloc = bb::round_up(K, 32);
-  d.scale = 4.0 / wl;
+  d.scale = 1.0 / wl;
   d.slot = slot;
   size_t xs, wts, levs, kbr, perm;
   staging_bytes(d.L_pad, d.K_alloc, &xs, &wts, &levs, &kbr, &perm);
@@ -595,6 +572,48 @@ bb_status bb_synth_prestep(bb_synth h, int32_t n_ant, double wavelength_m, const
   return BB_OK;
 }
 
+// ---- level determination and weighting ---------------------------------------
+bb_status bb_synth_levels_kmeans(bb_synth h, int32_t n, const double* lam, int32_t negative_level,
+                                 double* intervals, int32_t* level_of) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  if (n < 1 || n > bb::kMaxEig) return fail(ctx, BB_ERR_SHAPE, "n %d outside [1, %d]", n, bb::kMaxEig);
+  if (negative_level != 0 && negative_level != 1) return fail(ctx, BB_ERR_INVALID_ARG, "negative_level must be 0 or 1");
+  const int k = h->opt.n_levels - negative_level;
+  if (k < 1) return fail(ctx, BB_ERR_INVALID_ARG, "no positive level left (n_levels %d)", h->opt.n_levels);
+  if (!lam || !intervals || !level_of) return fail(ctx, BB_ERR_INVALID_ARG, "null device pointer");
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  BB_HIP(ctx, bb::launch_kmeans_levels(lam, n, k, negative_level, intervals, level_of, at<int>(h, h->lay.err),
+                                       ctx->stream));
+  return BB_OK;
+}
+
+bb_status bb_synth_uniform_weighting(bb_synth h, int32_t n_ant, double wavelength_m, const double* ant_xyz,
+                                     const double* e_u, const double* e_v, double fov_rad, double* vis) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  if (n_ant < 1) return fail(ctx, BB_ERR_INVALID_ARG, "n_ant must be >= 1");
+  if (n_ant > h->opt.n_ant_max) return fail(ctx, BB_ERR_SHAPE, "n_ant %d > n_ant_max %d", n_ant, h->opt.n_ant_max);
+  if (!finite_pos(wavelength_m)) return fail(ctx, BB_ERR_INVALID_ARG, "wavelength must be finite and > 0");
+  if (!finite_pos(fov_rad)) return fail(ctx, BB_ERR_INVALID_ARG, "fov must be finite and > 0");
+  if (!ant_xyz || !vis) return fail(ctx, BB_ERR_INVALID_ARG, "null device pointer");
+  if (!e_u || !e_v) return fail(ctx, BB_ERR_INVALID_ARG, "null uv axis");
+  bb::UvFrame f{};
+  for (int i = 0; i < 3; ++i) {
+    if (!std::isfinite(e_u[i]) || !std::isfinite(e_v[i])) return fail(ctx, BB_ERR_INVALID_ARG, "uv axes must be finite");
+    f.eu[i] = e_u[i];
+    f.ev[i] = e_v[i];
+  }
+  f.scale = fov_rad / wavelength_m;
+  // the hash table lives in the pre-step matrices' region (free between calls)
+  const size_t need = (size_t)bb::uv_table_slots(n_ant) * 12;
+  if (need > h->lay.evals - h->lay.A) return fail(ctx, BB_ERR_WORKSPACE, "uv table does not fit");
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  BB_HIP(ctx, bb::launch_uniform_weighting(ant_xyz, n_ant, n_ant, f, h->ws + h->lay.A, vis, at<int>(h, h->lay.err),
+                                           ctx->stream));
+  return BB_OK;
+}
+
 // ---- batched ----------------------------------------------------------------
 namespace {
 
@@ -896,7 +915,12 @@ bb_status bb_synth_sync(bb_synth h) {
   if (err) {
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, ctx->stream, at<int>(h, h->lay.err));
     BB_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    return fail(ctx, BB_ERR_INVALID_ARG, "a level id outside [-1, n_levels) was treated as -1");
+    std::string msg;
+    if (err & bb::kErrLevelId) msg += "a level id outside [-1, n_levels) was treated as -1; ";
+    if (err & bb::kErrKmeansTooFew) msg += "k-means: fewer positive eigenvalues than positive levels; ";
+    if (err & bb::kErrUvRange) msg += "uniform weighting: a uv cell index out of range or not finite; ";
+    msg.resize(msg.size() - 2);
+    return fail(ctx, BB_ERR_INVALID_ARG, "%s", msg.c_str());
   }
   return BB_OK;
 }

@@ -1,0 +1,48 @@
+// Host-side pieces shared by the translation units of the C ABI: the context
+// object, workspace alignment, error reporting and the HIP status check.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "bluebild.h"
+
+struct bb_context_ {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  rocblas_handle rb = nullptr;
+  std::string err;
+  int live = 0;
+};
+
+namespace bb_host {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+inline bb_status fail(bb_context ctx, bb_status s, const char* fmt, ...) {
+  if (ctx) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    ctx->err = buf;
+  }
+  return s;
+}
+
+inline bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace bb_host
+
+#define BB_HIP(ctx, call)                                                                                      \
+  do {                                                                                                         \
+    hipError_t e_ = (call);                                                                                    \
+    if (e_ != hipSuccess) return bb_host::fail((ctx), BB_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)

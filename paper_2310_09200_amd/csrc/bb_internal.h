@@ -14,6 +14,11 @@ constexpr int kMaxLevels = 16;
 constexpr int kMaxAnt = 1024;
 constexpr int kMaxEig = 1024;
 
+// Bits of a handle's device error word (read and cleared by bb_synth_sync).
+constexpr int kErrLevelId = 1;        // a level id outside [-1, n_levels) was treated as -1
+constexpr int kErrKmeansTooFew = 2;   // k-means: fewer positive eigenvalues than positive levels
+constexpr int kErrUvRange = 4;        // uniform weighting: a uv cell index beyond +-2^30 or not finite
+
 __host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 // One instance as seen by the staging and synthesis kernels.  Built on the
@@ -26,7 +31,7 @@ struct InstDesc {
   const int* wcol;       // optional column map (nullptr = identity)
   const float* d;        // filter weights, one per eigenpair
   const int* lev_in;     // level id per eigenpair, -1 = unused
-  double scale;          // 4 / wavelength: positions in quarter turns per unit direction
+  double scale;          // 1 / wavelength: positions in turns per unit direction
   int L, K, L_pad, K_alloc;
   int slot, W_c128, pad0, pad1;
   // workspace regions owned by this instance
@@ -89,6 +94,17 @@ hipError_t launch_select(const double* evals, int L, int K, Intervals iv, int n_
 hipError_t launch_export_eig(const double* A_c128, const double* evals, int L, int K, const int* wcol,
                              const float* dsel, const int* lsel, float* W_out_c64, double* lam_out, float* d_out,
                              int* lev_out, hipStream_t s);
+
+// Level determination and weighting (levels_weighting.hip).
+hipError_t launch_kmeans_levels(const double* lam, int n, int k, int negative_level, double* intervals,
+                                int* level_of, int* err, hipStream_t s);
+struct UvFrame {
+  double eu[3], ev[3];  // image-plane axes at the phase centre
+  double scale;         // FoV / wavelength: cells per metre of baseline
+};
+int64_t uv_table_slots(int L);  // hash slots for L^2 pairs (power of two >= 2 L^2); 12 bytes each
+hipError_t launch_uniform_weighting(const double* ant, int64_t ld, int L, const UvFrame& f, void* table,
+                                    double* vis, int* err, hipStream_t s);
 
 // Backward.
 // E recompute (FP32 MFMA, one instance) into two planes [2][K_alloc][n_pix].

@@ -21,32 +21,14 @@
 
 namespace bb {
 
-__device__ __forceinline__ void cis_quarter_b(float f, int q, float& c, float& s) {
-  // Same phase evaluation as the forward kernels: Taylor series of sin/cos on
-  // |theta| <= pi/4 and a rotation by q quarter turns.
-  const float th = f * 1.57079632679489662f;
-  const float t2 = th * th;
-  float sp = fmaf(t2, 2.7557319224e-6f, -1.9841269841e-4f);
-  sp = fmaf(t2, sp, 8.3333333333e-3f);
-  sp = fmaf(t2, sp, -1.6666666667e-1f);
-  const float sn = fmaf(th * t2, sp, th);
-  float cp = fmaf(t2, -2.7557319224e-7f, 2.4801587302e-5f);
-  cp = fmaf(t2, cp, -1.3888888889e-3f);
-  cp = fmaf(t2, cp, 4.1666666667e-2f);
-  cp = fmaf(t2, cp, -0.5f);
-  const float cs = fmaf(t2, cp, 1.0f);
-  const bool swap = (q & 1) != 0;
-  const float cc = swap ? sn : cs;
-  const float ss = swap ? cs : sn;
-  c = ((q + 1) & 2) ? -cc : cc;
-  s = (q & 2) ? -ss : ss;
-}
-
+// Same phase evaluation as the forward kernels: xs = position / wavelength,
+// exact FP64 reduction to [-1/2, 1/2] turns, hardware sine and cosine in turns.
 __device__ __forceinline__ void phase_b(const double* __restrict__ xs, double px, double py, double pz, float& c,
                                         float& s) {
   const double t = fma(xs[2], pz, fma(xs[1], py, xs[0] * px));
-  const double q = rint(t);
-  cis_quarter_b((float)(t - q), (int)q, c, s);
+  const float f = (float)(t - rint(t));
+  s = __builtin_amdgcn_sinf(f);
+  c = __builtin_amdgcn_cosf(f);
 }
 
 template <int N>

@@ -9,11 +9,12 @@
 //
 // Kernel structure (one workgroup = one pixel tile of one image slot):
 //   for each instance of the slot, for each K pass, for each 32-antenna chunk:
-//     phase generation: FP64 <x_l, p> in quarter turns, exact FP64 reduction to
-//       [-1/2, 1/2] plus a quadrant, FP32 sin/cos series -> B chunk in LDS
+//     phase generation: FP64 <x_l, p> in turns, exact FP64 reduction to
+//       [-1/2, 1/2], hardware FP32 sin/cos in turns -> B chunk in LDS
 //       (double-buffered: the next chunk is generated while this one is used)
-//     MFMA: real-embedded W^H operand streamed from HBM/L2 in operand order,
-//       B operand from LDS, accumulators for [Er; Ei] in registers
+//     MFMA: real-embedded W^H operand streamed from HBM/L2 in operand order
+//       and prefetched one MFMA group ahead, B operand from LDS, accumulators
+//       for [Er; Ei] in registers
 //   epilogue of a pass: d_k (Er^2 + Ei^2) reduced over k in-lane, across the
 //     two half-waves, and into per-level partial sums in LDS
 //   end of the tile: sum over waves in a fixed order, one read-modify-write of
@@ -33,36 +34,26 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
-// Phase: (cos, sin) of (q + f) * pi/2 for f in [-1/2, 1/2], q any integer.
-// Taylor series of sin and cos about 0 (terms to theta^9 and theta^10; the
-// truncation error on |theta| <= pi/4 is below 2e-9), then a rotation by q
-// quarter turns.
-__device__ __forceinline__ void cis_quarter(float f, int q, float& c, float& s) {
-  const float th = f * 1.57079632679489662f;
-  const float t2 = th * th;
-  float sp = fmaf(t2, 2.7557319224e-6f, -1.9841269841e-4f);
-  sp = fmaf(t2, sp, 8.3333333333e-3f);
-  sp = fmaf(t2, sp, -1.6666666667e-1f);
-  const float sn = fmaf(th * t2, sp, th);
-  float cp = fmaf(t2, -2.7557319224e-7f, 2.4801587302e-5f);
-  cp = fmaf(t2, cp, -1.3888888889e-3f);
-  cp = fmaf(t2, cp, 4.1666666667e-2f);
-  cp = fmaf(t2, cp, -0.5f);
-  const float cs = fmaf(t2, cp, 1.0f);
-  const bool swap = (q & 1) != 0;
-  const float cc = swap ? sn : cs;
-  const float ss = swap ? cs : sn;
-  c = ((q + 1) & 2) ? -cc : cc;
-  s = (q & 2) ? -ss : ss;
+// Pointers read out of an instance descriptor are generic to the compiler, and
+// generic (flat) loads count against the LDS wait counter too, so every wait
+// for an LDS read would also wait for the prefetched W operand.  Casting them
+// to the global address space makes those loads vector-memory loads only.
+#define BB_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const BB_GLOBAL T* as_global(const void* p) {
+  return (const BB_GLOBAL T*)p;
 }
 
-// Phase of one (antenna, pixel) pair; xs = position * 4 / wavelength.
-__device__ __forceinline__ void phase_pair(const double* __restrict__ xs, double px, double py, double pz,
+// Phase of one (antenna, pixel) pair: xs = position / wavelength, so t is the
+// phase in turns.  The reduction t - rint(t) is exact in FP64 and leaves
+// f in [-1/2, 1/2]; gfx950's transcendental unit takes its sine and cosine
+// argument in turns (sin(2 pi f)), with an absolute error near 1.3e-7 there.
+__device__ __forceinline__ void phase_pair(const BB_GLOBAL double* __restrict__ xs, double px, double py, double pz,
                                            float& c, float& s) {
   const double t = fma(xs[2], pz, fma(xs[1], py, xs[0] * px));
-  const double q = rint(t);
-  const float f = (float)(t - q);
-  cis_quarter(f, (int)q, c, s);
+  const float f = (float)(t - rint(t));
+  s = __builtin_amdgcn_sinf(f);
+  c = __builtin_amdgcn_cosf(f);
 }
 
 // ---------------------------------------------------------------------------
@@ -81,7 +72,7 @@ __global__ __launch_bounds__(256) void stage_meta_kernel(const InstDesc* __restr
   for (int k = tid; k < D.K; k += blockDim.x) {
     int lv = D.lev_in[k];
     if (lv < -1 || lv >= n_levels) {
-      atomicOr(err, 1);
+      atomicOr(err, kErrLevelId);
       lv = -1;
     }
     s_lev[k] = lv;
@@ -348,7 +339,7 @@ struct ChunkVec {  // 16-byte vectors per LDS phase chunk
 };
 
 template <class C, int PREC>
-__device__ __forceinline__ void gen_chunk(f32x4* __restrict__ buf, const double* __restrict__ xs_chunk,
+__device__ __forceinline__ void gen_chunk(f32x4* __restrict__ buf, const BB_GLOBAL double* __restrict__ xs_chunk,
                                           double px, double py, double pz, int tid) {
 #pragma unroll
   for (int j = 0; j < C::JT; ++j) {
@@ -421,111 +412,145 @@ __device__ __forceinline__ void gen_chunk(f32x4* __restrict__ buf, const double*
   }
 }
 
-// MFMA over one LDS chunk for the first M (<= MB) k-blocks of this wave.
-template <class C, int PREC, int M, int MB, int NB>
-__device__ __forceinline__ void mfma_chunk(f32x16 (&acc)[Acc<PREC>::N * MB][NB], const f32x4* __restrict__ buf,
-                                           const void* __restrict__ apack, int64_t a_rt_stride_vec,
-                                           int64_t a_base_vec, int cb0, int lane) {
-  if (PREC == 3) {
-    // a_rt_stride_vec: vectors per (k-block, plane); hi at +0, lo at +64 of each group
-    const bf16x8* A = (const bf16x8*)apack;
-    const bf16x8* Bb = (const bf16x8*)buf;
+// A operand (the W^H side) of one MFMA group: 4 contraction steps of the
+// wave's k-block.  It is loaded from L2 / HBM one group ahead of its use, so
+// the load latency is covered by the previous group's MFMAs.
+template <int PREC>
+struct AFrag;
+template <>
+struct AFrag<0> {  // Er / Ei rows, 4 antennas
+  f32x4 v[2];
+};
+template <>
+struct AFrag<1> {  // Er / Ei rows, hi / lo, 8 antennas
+  bf16x8 h[2], l[2];
+};
+template <>
+struct AFrag<2> {  // three planes, 8 antennas
+  f32x4 v[3];
+};
+template <>
+struct AFrag<3> {  // three planes, hi / lo, 16 antennas
+  bf16x8 h[3], l[3];
+};
+
+template <class C, int PREC>
+struct NGroups {  // MFMA groups per LDS chunk
+  static constexpr int N = PREC == 0 ? C::G4 : (PREC == 3 ? C::G16 : C::G8);
+};
+
+// base: first vector of this wave's k-block; stride: vectors per row tile (PREC 0/1)
+// or per plane (PREC 2/3); group g of chunk c.
+template <class C, int PREC>
+__device__ __forceinline__ void load_a(AFrag<PREC>& a, const void* apack, int64_t base, int64_t stride,
+                                       int c, int g, int lane) {
+  if constexpr (PREC == 0) {
+    const BB_GLOBAL f32x4* __restrict__ A = as_global<f32x4>(apack);
+    const int64_t o = base + (int64_t)(c * C::G4 + g) * 64 + lane;
+    a.v[0] = A[o];
+    a.v[1] = A[o + stride];
+  } else if constexpr (PREC == 1) {
+    const BB_GLOBAL bf16x8* __restrict__ A = as_global<bf16x8>(apack);
+    const int64_t o = base + (int64_t)(c * C::G8 + g) * 128 + lane;
 #pragma unroll
-    for (int g = 0; g < C::G16; ++g) {
-      bf16x8 ah[3 * M], al[3 * M], bh[3 * NB], bl[3 * NB];
+    for (int rt = 0; rt < 2; ++rt) {
+      a.h[rt] = A[o + rt * stride];
+      a.l[rt] = A[o + rt * stride + 64];
+    }
+  } else if constexpr (PREC == 2) {
+    const BB_GLOBAL f32x4* __restrict__ A = as_global<f32x4>(apack);
+    const int64_t o = base + (int64_t)(c * C::G8 + g) * 64 + lane;
 #pragma unroll
-      for (int t = 0; t < 3 * M; ++t) {
-        const int64_t o = a_base_vec + t * a_rt_stride_vec + (int64_t)g * 128 + lane;
-        ah[t] = A[o];
-        al[t] = A[o + 64];
-      }
+    for (int q = 0; q < 3; ++q) a.v[q] = A[o + q * stride];
+  } else {
+    const BB_GLOBAL bf16x8* __restrict__ A = as_global<bf16x8>(apack);
+    const int64_t o = base + (int64_t)(c * C::G16 + g) * 128 + lane;
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
+    for (int q = 0; q < 3; ++q) {
+      a.h[q] = A[o + q * stride];
+      a.l[q] = A[o + q * stride + 64];
+    }
+  }
+}
+
+// MFMAs of group g of an LDS chunk for this wave's k-block and NB pixel blocks.
+template <class C, int PREC, int NB>
+__device__ __forceinline__ void mma_group(f32x16 (&acc)[Acc<PREC>::N][NB], const AFrag<PREC>& a,
+                                          const f32x4* __restrict__ buf, int g, int cb0, int lane) {
+  if constexpr (PREC == 0) {
+    f32x4 b[NB];
 #pragma unroll
-        for (int n = 0; n < NB; ++n) {
-          const int o = (((g * 3 + q) * C::NCB + cb0 + n) * 2) * 64 + lane;
-          bh[3 * n + q] = Bb[o];
-          bl[3 * n + q] = Bb[o + 64];
-        }
+    for (int n = 0; n < NB; ++n) b[n] = buf[(g * C::NCB + cb0 + n) * 64 + lane];
 #pragma unroll
-      for (int m = 0; m < M; ++m)
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
         for (int n = 0; n < NB; ++n)
-#pragma unroll
-          for (int q = 0; q < 3; ++q) {
-            f32x16& c = acc[3 * m + q][n];
-            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[3 * m + q], bh[3 * n + q], c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[3 * m + q], bl[3 * n + q], c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[3 * m + q], bh[3 * n + q], c, 0, 0, 0);
-          }
-    }
-  } else if (PREC == 2) {
-    // a_rt_stride_vec: vectors per (k-block, plane); planes q = 0, 1, 2 pair with Br, Bi - Br, Br + Bi
-    const f32x4* A = (const f32x4*)apack;
-#pragma unroll
-    for (int g = 0; g < C::G8; ++g) {
-      f32x4 a[3 * M], b[3 * NB];
-#pragma unroll
-      for (int t = 0; t < 3 * M; ++t) a[t] = A[a_base_vec + t * a_rt_stride_vec + (int64_t)g * 64 + lane];
-#pragma unroll
-      for (int q = 0; q < 3; ++q)
-#pragma unroll
-        for (int n = 0; n < NB; ++n) b[3 * n + q] = buf[((g * 3 + q) * C::NCB + cb0 + n) * 64 + lane];
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int m = 0; m < M; ++m)
-#pragma unroll
-          for (int n = 0; n < NB; ++n)
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-              acc[3 * m + q][n] =
-                  __builtin_amdgcn_mfma_f32_32x32x2f32(a[3 * m + q][s], b[3 * n + q][s], acc[3 * m + q][n], 0, 0, 0);
-    }
-  } else if (PREC == 0) {
-    const f32x4* A = (const f32x4*)apack;
-#pragma unroll
-    for (int g = 0; g < C::G4; ++g) {
-      f32x4 a[2 * M], b[NB];
-#pragma unroll
-      for (int rt = 0; rt < 2 * M; ++rt) a[rt] = A[a_base_vec + rt * a_rt_stride_vec + (int64_t)g * 64 + lane];
-#pragma unroll
-      for (int n = 0; n < NB; ++n) b[n] = buf[(g * C::NCB + cb0 + n) * 64 + lane];
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int rt = 0; rt < 2 * M; ++rt)
-#pragma unroll
-          for (int n = 0; n < NB; ++n)
-            acc[rt][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[rt][s], b[n][s], acc[rt][n], 0, 0, 0);
-    }
-  } else {
-    const bf16x8* A = (const bf16x8*)apack;
+          acc[rt][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[rt][s], b[n][s], acc[rt][n], 0, 0, 0);
+  } else if constexpr (PREC == 1) {
     const bf16x8* Bb = (const bf16x8*)buf;
+    bf16x8 bh[NB], bl[NB];
 #pragma unroll
-    for (int g = 0; g < C::G8; ++g) {
-      bf16x8 ah[2 * M], al[2 * M], bh[NB], bl[NB];
+    for (int n = 0; n < NB; ++n) {
+      const int o = ((g * C::NCB + cb0 + n) * 2) * 64 + lane;
+      bh[n] = Bb[o];
+      bl[n] = Bb[o + 64];
+    }
 #pragma unroll
-      for (int rt = 0; rt < 2 * M; ++rt) {
-        const int64_t o = a_base_vec + rt * a_rt_stride_vec + (int64_t)g * 128 + lane;
-        ah[rt] = A[o];
-        al[rt] = A[o + 64];
-      }
+    for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
       for (int n = 0; n < NB; ++n) {
-        const int o = ((g * C::NCB + cb0 + n) * 2) * 64 + lane;
-        bh[n] = Bb[o];
-        bl[n] = Bb[o + 64];
+        acc[rt][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.l[rt], bh[n], acc[rt][n], 0, 0, 0);
+        acc[rt][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.h[rt], bl[n], acc[rt][n], 0, 0, 0);
+        acc[rt][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.h[rt], bh[n], acc[rt][n], 0, 0, 0);
+      }
+  } else if constexpr (PREC == 2) {
+    // planes q = 0, 1, 2 pair with Br, Bi - Br, Br + Bi
+    f32x4 b[3 * NB];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int n = 0; n < NB; ++n) b[3 * n + q] = buf[((g * 3 + q) * C::NCB + cb0 + n) * 64 + lane];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int n = 0; n < NB; ++n)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          acc[q][n] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.v[q][s], b[3 * n + q][s], acc[q][n], 0, 0, 0);
+  } else {
+    const bf16x8* Bb = (const bf16x8*)buf;
+    bf16x8 bh[3 * NB], bl[3 * NB];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int n = 0; n < NB; ++n) {
+        const int o = (((g * 3 + q) * C::NCB + cb0 + n) * 2) * 64 + lane;
+        bh[3 * n + q] = Bb[o];
+        bl[3 * n + q] = Bb[o + 64];
       }
 #pragma unroll
-      for (int rt = 0; rt < 2 * M; ++rt)
+    for (int n = 0; n < NB; ++n)
 #pragma unroll
-        for (int n = 0; n < NB; ++n) {
-          acc[rt][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[rt], bh[n], acc[rt][n], 0, 0, 0);
-          acc[rt][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rt], bl[n], acc[rt][n], 0, 0, 0);
-          acc[rt][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[rt], bh[n], acc[rt][n], 0, 0, 0);
-        }
-    }
+      for (int q = 0; q < 3; ++q) {
+        f32x16& c = acc[q][n];
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.l[q], bh[3 * n + q], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.h[q], bl[3 * n + q], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.h[q], bh[3 * n + q], c, 0, 0, 0);
+      }
+  }
+}
+
+// (Er, Ei) of accumulator register r of pixel block n.
+template <int PREC, int NB>
+__device__ __forceinline__ void fields(const f32x16 (&acc)[Acc<PREC>::N][NB], int n, int r, float& er, float& ei) {
+  if constexpr (PREC >= 2) {
+    er = acc[0][n][r] - acc[2][n][r];
+    ei = acc[0][n][r] + acc[1][n][r];
+  } else {
+    er = acc[0][n][r];
+    ei = acc[1][n][r];
   }
 }
 
@@ -533,9 +558,11 @@ __device__ __forceinline__ void mfma_chunk(f32x16 (&acc)[Acc<PREC>::N * MB][NB],
 // re and im, [K_alloc][n_pix] each) for the backward pass; one instance only.
 template <int MB, int NB, int WK, int WN, int PREC, int MODE>
 __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams P) {
+  static_assert(MB == 1, "one k-block of 32 eigenpairs per wave");
   using C = TileCfg<MB, NB, WK, WN>;
   __shared__ f32x4 s_buf[2][ChunkVec<C, PREC>::N];
   constexpr int NA = Acc<PREC>::N;
+  constexpr int NG = NGroups<C, PREC>::N;
   __shared__ float s_part[WK][kMaxLevels][C::NT];
 
   const int tid = threadIdx.x;
@@ -545,78 +572,90 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
   const int wn = wave / WK;
   const int cb0 = wn * NB;
   const int n_levels = P.n_levels;
+  // Ping-pong: the first half of the waves generates the next phase chunk and
+  // then multiplies, the second half multiplies first.  Waves are laid out
+  // round-robin over the four SIMDs, so each SIMD holds one wave of each half
+  // and its VALU (phases) and matrix core (MFMA) work at the same time.
+  const bool gen_first = wave < C::WAVES / 2;
 
   // Persistent grid: workgroup b owns pixel tiles b, b + gridDim.x, ...; every
   // workgroup walks the groups (slots) and their instances in the same order,
   // so the workgroups running at one time stream the same instance's W operand
   // through L2.  Each image tile has exactly one writer (its owner).
   for (int grp = 0; grp < P.n_groups; ++grp) {
-   const int slot = P.group_slot[grp];
-   for (int ii = P.group_begin[grp]; ii < P.group_begin[grp + 1]; ++ii) {
-    const int inst = P.inst_list[ii];
-    for (int64_t tile = blockIdx.x; tile < P.n_tiles; tile += gridDim.x) {
-      const int64_t p0 = tile * C::NT;
-      for (int i = tid; i < WK * kMaxLevels * C::NT; i += C::THREADS) (&s_part[0][0][0])[i] = 0.0f;
-      // this thread's pixel (phase generation); clamp the ragged tail
-      int64_t pg = p0 + (tid % C::NT);
-      if (pg >= P.n_pix) pg = P.n_pix - 1;
-      const double px = P.pix[pg], py = P.pix[pg + P.pix_ld], pz = P.pix[pg + 2 * P.pix_ld];
-      const InstDesc& D = P.descs[inst];
-      const int K_pad = P.dyn[inst].K_pad;
-      const int L_pad = D.L_pad;
+    const int slot = __builtin_amdgcn_readfirstlane(P.group_slot[grp]);
+    for (int ii = P.group_begin[grp]; ii < P.group_begin[grp + 1]; ++ii) {
+      // Instance fields are copied into (wave-uniform) locals once: read
+      // through the descriptor pointer they would be reloaded after every LDS
+      // store, which the compiler cannot prove does not alias them.
+      const int inst = __builtin_amdgcn_readfirstlane(P.inst_list[ii]);
+      const InstDesc& Dg = P.descs[inst];
+      const void* const apack = Dg.apack;
+      const BB_GLOBAL double* const xs = as_global<double>(Dg.xs);
+      const BB_GLOBAL float* const wts = as_global<float>(Dg.wts);
+      const BB_GLOBAL int* const levs = as_global<int>(Dg.levs);
+      const BB_GLOBAL int* const kbr = as_global<int>(Dg.kbr);  // (lo, hi) pairs
+      const int K_pad = __builtin_amdgcn_readfirstlane(P.dyn[inst].K_pad);
+      const int L_pad = __builtin_amdgcn_readfirstlane(Dg.L_pad);
       const int n_chunks = L_pad / C::LCH;
       const int n_pass = (K_pad + C::KC - 1) / C::KC;
-      const double* xs = D.xs;
-      // 16-byte vectors per A row tile (per k-block plane for PREC 2)
-      const int64_t a_rt_stride = PREC >= 2 ? (int64_t)(L_pad / 8) * 64 : (int64_t)(L_pad / 4) * 64;
-      for (int pass = 0; pass < n_pass; ++pass) {
-        const int kb0 = pass * (C::KC / 32) + wk * MB;
-        int mact = K_pad / 32 - kb0;
-        mact = mact < 0 ? 0 : (mact > MB ? MB : mact);
-        f32x16 acc[NA * MB][NB];
+      // 16-byte vectors per A row tile (PREC 0/1) or per plane (PREC 2/3)
+      const int64_t a_stride = PREC >= 2 ? (int64_t)(L_pad / 8) * 64 : (int64_t)(L_pad / 4) * 64;
+      for (int64_t tile = blockIdx.x; tile < P.n_tiles; tile += gridDim.x) {
+        const int64_t p0 = tile * C::NT;
+        for (int i = tid; i < WK * kMaxLevels * C::NT; i += C::THREADS) (&s_part[0][0][0])[i] = 0.0f;
+        // this thread's pixel (phase generation); clamp the ragged tail
+        int64_t pg = p0 + (tid % C::NT);
+        if (pg >= P.n_pix) pg = P.n_pix - 1;
+        const double px = P.pix[pg], py = P.pix[pg + P.pix_ld], pz = P.pix[pg + 2 * P.pix_ld];
+        for (int pass = 0; pass < n_pass; ++pass) {
+          const int kb = pass * (C::KC / 32) + wk;   // this wave's k-block
+          const bool active = kb < K_pad / 32;        // wave-uniform
+          const int64_t a_base = (int64_t)kb * (PREC >= 2 ? 3 : 2) * a_stride;
+          f32x16 acc[NA][NB];
 #pragma unroll
-        for (int rt = 0; rt < NA * MB; ++rt)
+          for (int t = 0; t < NA; ++t)
 #pragma unroll
-          for (int n = 0; n < NB; ++n)
+            for (int n = 0; n < NB; ++n)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[rt][n][r] = 0.0f;
+              for (int r = 0; r < 16; ++r) acc[t][n][r] = 0.0f;
+          AFrag<PREC> a_cur;
+          if (active) load_a<C, PREC>(a_cur, apack, a_base, a_stride, 0, 0, lane);
 
-        __syncthreads();  // previous users of s_buf are done
-        gen_chunk<C, PREC>(s_buf[0], xs, px, py, pz, tid);
-        __syncthreads();
-        // Ping-pong: the first half of the waves generates the next chunk and
-        // then multiplies, the second half multiplies first.  Waves are laid
-        // out round-robin over the four SIMDs, so each SIMD holds one wave of
-        // each half and its VALU (phases) and matrix core (MFMA) overlap.
-        const bool gen_first = wave < C::WAVES / 2;
-        for (int c = 0; c < n_chunks; ++c) {
-          const int64_t a_base = PREC >= 2 ? (int64_t)(kb0 * 3) * a_rt_stride + (int64_t)c * (C::LCH / 8) * 64
-                                           : (int64_t)(kb0 * 2) * a_rt_stride + (int64_t)c * (C::LCH / 4) * 64;
-          auto gen = [&]() {
-            if (c + 1 < n_chunks)
-              gen_chunk<C, PREC>(s_buf[(c + 1) & 1], xs + 4 * (c + 1) * C::LCH, px, py, pz, tid);
-          };
-          auto mma = [&]() {
-            if (mact == MB)
-              mfma_chunk<C, PREC, MB, MB, NB>(acc, s_buf[c & 1], D.apack, a_rt_stride, a_base, cb0, lane);
-            else if (MB > 1 && mact == 1)
-              mfma_chunk<C, PREC, 1, MB, NB>(acc, s_buf[c & 1], D.apack, a_rt_stride, a_base, cb0, lane);
-          };
-          if (gen_first) {
-            gen();
-            mma();
-          } else {
-            mma();
-            gen();
-          }
+          __syncthreads();  // previous users of s_buf are done
+          gen_chunk<C, PREC>(s_buf[0], xs, px, py, pz, tid);
           __syncthreads();
-        }
-
-        if (MODE == 1) {
+          for (int c = 0; c < n_chunks; ++c) {
+            auto gen = [&]() {
+              if (c + 1 < n_chunks)
+                gen_chunk<C, PREC>(s_buf[(c + 1) & 1], xs + 4 * (c + 1) * C::LCH, px, py, pz, tid);
+            };
+            auto mma = [&]() {
+              if (!active) return;
 #pragma unroll
-          for (int m = 0; m < MB; ++m) {
-            if (m >= mact) break;
-            const int kb = kb0 + m;
+              for (int g = 0; g < NG; ++g) {
+                AFrag<PREC> a_nxt;
+                const bool more = g + 1 < NG || c + 1 < n_chunks;
+                if (g + 1 < NG)
+                  load_a<C, PREC>(a_nxt, apack, a_base, a_stride, c, g + 1, lane);
+                else if (c + 1 < n_chunks)
+                  load_a<C, PREC>(a_nxt, apack, a_base, a_stride, c + 1, 0, lane);
+                mma_group<C, PREC, NB>(acc, a_cur, s_buf[c & 1], g, cb0, lane);
+                if (more) a_cur = a_nxt;
+              }
+            };
+            if (gen_first) {
+              gen();
+              mma();
+            } else {
+              mma();
+              gen();
+            }
+            __syncthreads();
+          }
+          if (!active) continue;
+
+          if (MODE == 1) {
 #pragma unroll
             for (int n = 0; n < NB; ++n) {
               const int64_t p = p0 + (cb0 + n) * 32 + (lane & 31);
@@ -625,35 +664,24 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
                 for (int r = 0; r < 16; ++r) {
                   const int k = kb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                   float er, ei;
-                  if (PREC >= 2) {
-                    er = acc[3 * m][n][r] - acc[3 * m + 2][n][r];
-                    ei = acc[3 * m][n][r] + acc[3 * m + 1][n][r];
-                  } else {
-                    er = acc[2 * m][n][r];
-                    ei = acc[2 * m + 1][n][r];
-                  }
+                  fields<PREC, NB>(acc, n, r, er, ei);
                   P.e_out[(int64_t)k * P.e_ld + p] = er;
                   P.e_out[(int64_t)(P.e_rows + k) * P.e_ld + p] = ei;
                 }
               }
             }
+            continue;
           }
-          continue;
-        }
-        // epilogue: weighted |E|^2 into per-level partial sums
-#pragma unroll
-        for (int m = 0; m < MB; ++m) {
-          if (m >= mact) break;
-          const int kb = kb0 + m;
-          const int2 lr = D.kbr[kb];
-          if (lr.x > lr.y) continue;
+          // epilogue: weighted |E|^2 into per-level partial sums
+          const int lev_lo = kbr[2 * kb], lev_hi = kbr[2 * kb + 1];
+          if (lev_lo > lev_hi) continue;  // no kept eigenvalue in this k-block
           float w[16];
           int lv[16];
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
             const int k = kb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            w[r] = D.wts[k];
-            lv[r] = D.levs[k];
+            w[r] = wts[k];
+            lv[r] = levs[k];
           }
 #pragma unroll
           for (int n = 0; n < NB; ++n) {
@@ -661,16 +689,10 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
               float er, ei;
-              if (PREC >= 2) {
-                er = acc[3 * m][n][r] - acc[3 * m + 2][n][r];
-                ei = acc[3 * m][n][r] + acc[3 * m + 1][n][r];
-              } else {
-                er = acc[2 * m][n][r];
-                ei = acc[2 * m + 1][n][r];
-              }
+              fields<PREC, NB>(acc, n, r, er, ei);
               e2[r] = w[r] * fmaf(er, er, ei * ei);
             }
-            for (int l = lr.x; l <= lr.y; ++l) {
+            for (int l = lev_lo; l <= lev_hi; ++l) {
               float sum = 0.0f;
 #pragma unroll
               for (int r = 0; r < 16; ++r) sum += (lv[r] == l) ? e2[r] : 0.0f;
@@ -679,23 +701,22 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
             }
           }
         }
-      }
-      __syncthreads();
-      if (MODE == 1) continue;
-      for (int i = tid; i < n_levels * C::NT; i += C::THREADS) {
-        const int l = i / C::NT, pl = i % C::NT;
-        const int64_t p = p0 + pl;
-        if (p < P.n_pix) {
-          float s = 0.0f;
+        __syncthreads();
+        if (MODE == 1) continue;
+        for (int i = tid; i < n_levels * C::NT; i += C::THREADS) {
+          const int l = i / C::NT, pl = i % C::NT;
+          const int64_t p = p0 + pl;
+          if (p < P.n_pix) {
+            float sum = 0.0f;
 #pragma unroll
-          for (int q = 0; q < WK; ++q) s += s_part[q][l][pl];
-          float* dst = P.img + ((int64_t)slot * n_levels + l) * P.img_ld + p;
-          *dst += s;
+            for (int q = 0; q < WK; ++q) sum += s_part[q][l][pl];
+            float* dst = P.img + ((int64_t)slot * n_levels + l) * P.img_ld + p;
+            *dst += sum;
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
-   }
   }
 }
 
@@ -796,14 +817,12 @@ hipError_t launch_synth(const FwdParams& p, int max_K_alloc, int precision, int 
 }
 
 int fields_tile_pixels(int K_alloc) {
-  if (K_alloc > 256) return TileCfg<2, 2, 8, 1>::NT;
   if (K_alloc > 128) return TileCfg<1, 4, 8, 1>::NT;
   return TileCfg<1, 4, 4, 2>::NT;
 }
 
 hipError_t launch_fields(const FwdParams& p, int K_alloc, hipStream_t s) {
   // FP32 recompute of E for the backward pass (the handle's precision does not apply)
-  if (K_alloc > 256) return launch_cfg<2, 2, 8, 1, 0, 1>(p, s);
   if (K_alloc > 128) return launch_cfg<1, 4, 8, 1, 0, 1>(p, s);
   return launch_cfg<1, 4, 4, 2, 0, 1>(p, s);
 }

@@ -155,6 +155,40 @@ class StandardSynthesis:
         self._keep = [xc, Vc]
         return Wt.transpose(0, 1), lam, d, lev
 
+    def levels_kmeans(self, lam, negative_level=True):
+        """Level intervals by exact k-means of the eigenvalues ``lam`` (n,), on the device.
+
+        n_levels - negative_level positive levels (level 0 the largest), plus one
+        level for the non-positive eigenvalues when ``negative_level``.  Returns
+        (intervals (n_levels, 2) float64, level_of (n,) int32), both on the device;
+        too few positive eigenvalues raises at the next ``sync``.
+        """
+        dev = self.ctx.device
+        lam_d = torch.as_tensor(lam).to(device=dev, dtype=torch.float64).contiguous().reshape(-1)
+        n = int(lam_d.numel())
+        iv = torch.empty((2, self.n_levels), dtype=torch.float64, device=dev)   # column-major (n_levels, 2)
+        lev = torch.empty(n, dtype=torch.int32, device=dev)
+        self.ctx.bind_current_stream()
+        check(self.lib.bb_synth_levels_kmeans(self.handle, n, _ptr(lam_d), int(bool(negative_level)), _ptr(iv),
+                                              _ptr(lev)), self.ctx.handle)
+        self._keep = [lam_d]
+        return iv.transpose(0, 1), lev
+
+    def uniform_weighting(self, x, wavelength, V, e_u, e_v, fov_rad):
+        """Uniformly weighted copy of V (L, L) on the device (complex128); V itself is not written."""
+        dev = self.ctx.device
+        L = int(x.shape[0])
+        xc = _colmajor(torch.as_tensor(x), torch.float64, dev)
+        Vc = _colmajor(torch.as_tensor(V), torch.complex128, dev).clone()   # the library overwrites this copy
+        eu = np.ascontiguousarray(np.asarray(e_u, np.float64).reshape(3))
+        ev = np.ascontiguousarray(np.asarray(e_v, np.float64).reshape(3))
+        dp = ctypes.POINTER(ctypes.c_double)
+        self.ctx.bind_current_stream()
+        check(self.lib.bb_synth_uniform_weighting(self.handle, L, float(wavelength), _ptr(xc), eu.ctypes.data_as(dp),
+                                                  ev.ctypes.data_as(dp), float(fov_rad), _ptr(Vc)), self.ctx.handle)
+        self._keep = [xc]
+        return Vc.transpose(0, 1)
+
     def collect_eig(self, slot, x, wavelength, W, d, level_of):
         """Hot path: x (L,3) f64, W (L,K) complex, d (K,) weights, level_of (K,) int (-1 = unused)."""
         dev = self.ctx.device
