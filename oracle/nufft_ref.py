@@ -35,6 +35,13 @@ Readings (the paper gives the steps, not the constants):
     sources do not wrap around; the type-2 grid has M_d = sigma N_d points;
   * w is evaluated as ceil(log10(1 / eps) - 1e-9) + 1, so that a tolerance
     that is a power of ten does not gain a point from rounding;
+  * grid coordinates are formed as x * (1 / h) for sources and
+    (s - D) * (h * M) for targets, and the w points used are
+    ceil(xi - w/2) .. ceil(xi - w/2) + w - 1.  The kernel is e^{-beta}, not 0,
+    at the ends of its support, so when a coordinate lands exactly on a grid
+    point (the extreme pixels do: they sit at +-S, i.e. at +-M/4) the choice
+    of the dropped end changes the result by about e^{-beta} of a grid value;
+    the arithmetic above fixes that choice;
   * "smooth" is the least even integer >= n with no prime factor above 5;
   * kernel Fourier transforms are evaluated by 100-node Gauss-Legendre
     quadrature of the (even) kernel.
@@ -156,7 +163,7 @@ def nufft3(c, x, s, eps, X=None):
         raise ValueError("a source lies outside the planned extent")
 
     # 1. rescale: sources in spread-grid units; pre-phase so the targets are centred at D
-    xi = x / h[None, :]
+    xi = x * (1.0 / h)[None, :]
     pre = np.exp(2j * np.pi * (x @ D - np.rint(x @ D)))
     cs = c * pre[:, None]
 
@@ -192,7 +199,7 @@ def nufft3(c, x, s, eps, X=None):
     u = np.fft.ifftn(big, axes=(1, 2, 3)) * float(np.prod(M))
 
     st = s - D[None, :]
-    eta = st * h[None, :] * M[None, :]            # targets in type-2 grid units (2 pi s h M / (2 pi))
+    eta = st * (h * M)[None, :]                   # targets in type-2 grid units (2 pi s h M / (2 pi))
     gi, ki = [], []
     for d in range(3):
         g, z = _neighbours(eta[:, d], w)
