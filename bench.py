@@ -180,6 +180,93 @@ def measure_c5_backward(args, torch, ctx):
             "backward_vector_fp32_fraction": 3 * 8.0 * prods / (b_ms / 1e3) / (FP32_PEAK_TFLOPS / 2 * 1e12)}
 
 
+def measure_nufft(args, torch, ctx):
+    """NUFFT synthesis next to standard synthesis on the paper's performance setup.
+
+    SKA-Low-like array (C3: 512 stations, 65 km), 50 epochs over 6 h, 4 arcsec
+    pixels, 8 + 1 k-means levels, every eigenpair kept; eigenpairs from the GPU
+    FP64 pre-step.  Both syntheses image the same eigenpairs; the NUFFT image
+    is compared with the standard one level by level.
+    """
+    from paper_2310_09200_amd import Batch, NufftSynthesis, StandardSynthesis
+    from sims import configs, tangent_basis
+    from sims.levels import kmeans1d_intervals
+    side = args.nufft_side
+    fov = side * 4.0 / 3600.0
+    w = configs.c3(n_steps=50, n_side=side, fov_deg=fov)
+    insts = [w.instance(i) for i in range(w.n_steps)]
+    probe = StandardSynthesis(ctx, w.pix[:1], 1, 1, 512, 512)
+    _, lam0, _, _ = probe.prestep(insts[0].x, insts[0].wl, insts[0].V, 512, np.array([[-np.inf, np.inf]]))
+    probe.close()
+    iv = kmeans1d_intervals(lam0.cpu().numpy(), 8, negative_level=True)
+    n_levels = iv.shape[0]
+    pre = StandardSynthesis(ctx, w.pix[:1], n_levels, 1, 512, 512)
+    items = []
+    for inst in insts:
+        W, lam, d, lev = pre.prestep(inst.x, inst.wl, inst.V, 512, iv)
+        items.append((0, inst.x, inst.wl, W.clone(), d.clone(), lev.clone()))
+    pre.close()
+    batch = Batch(items, ctx.device)
+    frame = np.array(tangent_basis(w.dec0_deg))
+    uvw = np.zeros(3)
+    for inst in insts:
+        li, mi = np.triu_indices(inst.x.shape[0], k=1)
+        b = (inst.x[li] - inst.x[mi]) @ frame.T / inst.wl
+        uvw = np.maximum(uvw, np.max(np.abs(b), axis=0))
+    uvw = uvw * 1.001
+
+    s = StandardSynthesis(ctx, w.pix, n_levels, 1, 512, 512, args.precision)
+    plan = NufftSynthesis(ctx, w.pix, n_levels, 512, 512, args.nufft_eps, frame, uvw)
+    N, M, kw = plan.shape
+    s.collect_eig_batched(batch)
+    plan.collect_eig_batched(batch)
+    plan.emit()
+    torch.cuda.synchronize()
+    s.reset()
+    plan.images.zero_()
+    std_ms, nu_ms, spread_ms, emit_ms = [], [], [], []
+    for _ in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.collect_eig_batched(batch)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plan.collect_eig_batched(batch)
+        plan.emit()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        std_ms.append((t1 - t0) * 1e3)
+        nu_ms.append((t2 - t1) * 1e3)
+        a, b = plan.timings()
+        spread_ms.append(a)
+        emit_ms.append(b)
+    plan.sync()
+    s.sync()
+    std_img = s.images[0].double()
+    nu_img = plan.images.double()
+    errs = []
+    for lv in range(n_levels):
+        peak = float(std_img[lv].abs().max())
+        if peak > 0:
+            errs.append(float((nu_img[lv] - std_img[lv]).abs().max()) / peak)
+    s.close()
+    plan.close()
+    prods = batch.products * w.n_pix
+    m_cells = M[0] * M[1] * M[2]
+    log(f"NUFFT {side}^2: standard {np.mean(std_ms):.1f} ms, NUFFT {np.mean(nu_ms):.1f} ms "
+        f"(spread {np.mean(spread_ms):.1f}, emit {np.mean(emit_ms):.1f}), grid {N} fft {M} w={kw}, "
+        f"max level diff {max(errs):.2e}")
+    return {"workload": f"SKA-Low-like 512 stations (65 km), 50 epochs over 6 h, {side}x{side} pixels of 4 arcsec "
+                        f"({fov * 60:.1f} arcmin), 8+1 k-means levels, all 512 eigenpairs (GPU FP64 pre-step)",
+            "epsilon": args.nufft_eps, "spread_grid": list(N), "fft_grid": list(M), "kernel_width": kw,
+            "standard_ms": float(np.mean(std_ms)), "standard_contraction": args.precision,
+            "nufft_ms": float(np.mean(nu_ms)), "nufft_spread_ms": float(np.mean(spread_ms)),
+            "nufft_emit_ms": float(np.mean(emit_ms)), "speedup_nufft_over_standard": float(np.mean(std_ms) / np.mean(nu_ms)),
+            "products": prods, "standard_products_per_s": prods / (np.mean(std_ms) / 1e3),
+            "fft_cells_per_level": m_cells,
+            "max_level_diff_nufft_vs_standard": max(errs)}
+
+
 def spot_error(args, torch, ctx, w, items, precision, n_levels, sel, ref_img):
     """Per-level max error (peak-normalised) of one epoch on the oracle's sample pixels."""
     from paper_2310_09200_amd import StandardSynthesis
@@ -236,7 +323,12 @@ def main():
     ap.add_argument("--cpu-stride", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="time only the headline contraction mode")
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched (C4) and backward (C5) measurements")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched (C4), backward (C5) and NUFFT-synthesis measurements")
+    ap.add_argument("--nufft-side", type=int, default=1024, help="image side of the NUFFT comparison (4 arcsec pixels)")
+    ap.add_argument("--nufft-eps", type=float, default=1e-5)
+    ap.add_argument("--only-nufft", action="store_true",
+                    help="print only the NUFFT-vs-standard measurement (for profiling it alone)")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="before timing, copy this many MiB device-to-device once (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -259,6 +351,10 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {args.calibration_copy_mb} MiB read + {args.calibration_copy_mb} MiB written")
         del src, dst
+    if args.only_nufft:
+        from paper_2310_09200_amd import Context
+        print(json.dumps({"nufft_vs_standard": measure_nufft(args, torch, Context(0))}), flush=True)
+        return
     ctx, w, intervals, items, insts = build_inputs(args, torch, dev)
     n_levels = intervals.shape[0]
     modes = [args.precision] + ([] if args.no_compare else [m for m in MODES if m != args.precision])
@@ -326,6 +422,7 @@ def main():
     if not args.no_extra:
         out["batched_c4"] = measure_c4(args, torch, ctx)
         out["backward_c5"] = measure_c5_backward(args, torch, ctx)
+        out["nufft_vs_standard"] = measure_nufft(args, torch, ctx)
     if cpu is not None:
         out["cpu_baseline"] = cpu
         out["max_level_error_vs_oracle"] = {

@@ -270,6 +270,69 @@ bb_status bb_synth_eig_backward(bb_synth h, int32_t n_ant, int32_t n_eig, double
                                 const int32_t* level_of, const float* grad_images,
                                 void* dW, float* dd, double* dx, void* workspace, size_t ws_bytes);
 
+/* ---- NUFFT synthesis ------------------------------------------------------
+ * The level images again, evaluated as the type-3 Fourier sum over baselines
+ * (Section 2.5; Section 3.4 and Algorithm 3):
+ *   I_l(p) = sum_q V'_l[q, q] + 2 Re sum_{q < r} V'_l[r, q] exp(+2 pi i <b_qr, p>),
+ *   V'_l = W_l diag(d_l) W_l^H (the eigenpairs of level l),  b_qr = (x_q - x_r) / lambda_w,
+ * which equals standard synthesis of the same eigenpairs up to the NUFFT
+ * tolerance.  In the image frame (e_u, e_v, p0) each baseline is spread onto a
+ * periodic N0 x N1 x N2 grid with the exponential-of-semicircle kernel
+ * phi(z) = exp(beta (sqrt(1 - z^2) - 1)), w = ceil(log10(1 / epsilon) - 1e-9) + 1
+ * points of support, beta = 2.30 w; the grid is deconvolved, zero-padded to
+ * M = 2 N, transformed (rocFFT, e^{+i}), interpolated at the pixels and
+ * divided by the kernel's transform.  Per frame axis d, with pixel half-width
+ * S_d (floored at 1e-12) about the centre D_d and baseline bound X_d = uvw_max[d]:
+ *   spacing h_d = 1 / (4 S_d) turns, N_d = the least even 2^a 3^b 5^c
+ *   >= max(2 w, ceil(8 X_d S_d) + w).
+ * Instances collected before one bb_nufft_emit share the grid: the transform,
+ * interpolation and correction run once per emit and level.  The grid is
+ * accumulated with FP32 atomics, so the last bits of a result vary between
+ * runs.  Memory: n_levels N0 N1 N2 + M0 M1 M2 complex64 cells plus rocFFT's
+ * work area (bb_nufft_workspace_size). */
+typedef struct bb_nufft_* bb_nufft;
+typedef struct {
+  int32_t n_levels;   /* images, 1..16 */
+  int32_t n_ant_max;  /* largest antenna count of an instance, 2..1024 */
+  int32_t k_max;      /* largest eigenpair count of an instance, 1..1024 */
+  int32_t reserved;   /* must be 0 */
+  double epsilon;     /* requested accuracy, 1e-7 .. 1e-2 */
+  double frame[9];    /* rows e_u, e_v, p0: orthonormal, in the frame of ant_xyz and pix_xyz */
+  double uvw_max[3];  /* bound on |<x_q - x_r, frame row d>| / lambda_w over every baseline
+                         to be collected (wavelengths); a baseline beyond it is skipped and
+                         reported by bb_nufft_sync */
+} bb_nufft_options;
+
+/* Workspace bytes of a plan.  pix_host: host, n_pix x 3 float64 column-major,
+ * the pixels the plan will be created with (their extents fix the grid). */
+bb_status bb_nufft_workspace_size(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix, const double* pix_host,
+                                  size_t* bytes);
+/* Create a plan.  pix_host as above (read during the call only); pix_xyz: the
+ * same pixels on the device (kept); images: device, float32 [n_levels][n_pix],
+ * accumulated into by bb_nufft_emit; workspace: device, 256-byte aligned,
+ * ws_bytes >= bb_nufft_workspace_size(...).  Waits for its set-up work. */
+bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix, const double* pix_host,
+                          const double* pix_xyz, float* images, void* workspace, size_t ws_bytes, bb_nufft* out);
+/* Grid sizes (N, M, 3 values each) and kernel support of a plan; NULL outputs are skipped. */
+bb_status bb_nufft_shape(bb_nufft h, int32_t* spread_grid, int32_t* fft_grid, int32_t* kernel_width);
+/* Spread instances onto the grid; packed arrays and descriptors as for
+ * bb_synth_collect_eig_batched (slot must be 0, n_ant >= 2).  workspace:
+ * device, 256-byte aligned, >= bb_nufft_batched_workspace_size(...) bytes,
+ * in use until the stream reaches the work. */
+bb_status bb_nufft_batched_workspace_size(bb_nufft h, int32_t n_inst, const bb_instance* inst, size_t* bytes);
+bb_status bb_nufft_collect_eig_batched(bb_nufft h, int32_t n_inst, const bb_instance* inst, int64_t n_ant_rows,
+                                       const double* ant_xyz_packed, const void* W_packed, const float* d_packed,
+                                       const int32_t* level_packed, void* workspace, size_t ws_bytes);
+/* Transform what has been spread since the last emit, add it to the images,
+ * and clear the grid. */
+bb_status bb_nufft_emit(bb_nufft h);
+/* Wait; BB_ERR_INVALID_ARG (cleared) if a kernel skipped a baseline beyond
+ * uvw_max or treated an out-of-range level id as -1. */
+bb_status bb_nufft_sync(bb_nufft h);
+/* Device ms of the last spread call [0] and the last emit [1]; waits. */
+bb_status bb_nufft_timings(bb_nufft h, double* ms_out, int32_t n);
+bb_status bb_nufft_destroy(bb_nufft h);
+
 /* Wait for all enqueued work; BB_ERR_DEVICE on an asynchronous device error,
  * BB_ERR_INVALID_ARG (and clear it) when a kernel found an input error: a level
  * id out of range, too few positive eigenvalues for k-means, a uv cell out of

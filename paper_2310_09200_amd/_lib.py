@@ -30,6 +30,11 @@ class bb_options(ctypes.Structure):
                 ("precision", c_int32), ("filter", c_int32), ("gram", c_int32), ("reserved", c_int32)]
 
 
+class bb_nufft_options(ctypes.Structure):
+    _fields_ = [("n_levels", c_int32), ("n_ant_max", c_int32), ("k_max", c_int32), ("reserved", c_int32),
+                ("epsilon", c_double), ("frame", c_double * 9), ("uvw_max", c_double * 3)]
+
+
 class bb_instance(ctypes.Structure):
     _fields_ = [("n_ant", c_int32), ("n_eig", c_int32), ("slot", c_int32), ("reserved", c_int32),
                 ("wavelength_m", c_double), ("ant_off", c_int64), ("w_off", c_int64), ("eig_off", c_int64)]
@@ -64,6 +69,17 @@ PROTOS = {
     "bb_synth_levels_kmeans": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p]),
     "bb_synth_uniform_weighting": (c_int32, [c_void_p, c_int32, c_double, c_void_p, POINTER(c_double),
                                              POINTER(c_double), c_double, c_void_p]),
+    "bb_nufft_workspace_size": (c_int32, [c_void_p, POINTER(bb_nufft_options), c_int64, c_void_p, POINTER(c_size_t)]),
+    "bb_nufft_create": (c_int32, [c_void_p, POINTER(bb_nufft_options), c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                  c_size_t, POINTER(c_void_p)]),
+    "bb_nufft_shape": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]),
+    "bb_nufft_batched_workspace_size": (c_int32, [c_void_p, c_int32, c_void_p, POINTER(c_size_t)]),
+    "bb_nufft_collect_eig_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p,
+                                               c_void_p, c_void_p, c_size_t]),
+    "bb_nufft_emit": (c_int32, [c_void_p]),
+    "bb_nufft_sync": (c_int32, [c_void_p]),
+    "bb_nufft_timings": (c_int32, [c_void_p, POINTER(c_double), c_int32]),
+    "bb_nufft_destroy": (c_int32, [c_void_p]),
     "bb_synth_sync": (c_int32, [c_void_p]),
     "bb_synth_reset": (c_int32, [c_void_p]),
     "bb_synth_get_count": (c_int32, [c_void_p, POINTER(c_int64)]),

@@ -3,7 +3,7 @@
     python -m paper_2310_09200_amd.build        # or build() from Python
 
 Every HIP source is compiled with hipcc for gfx950 only, with packed FP32
-instructions disabled, and linked against rocSOLVER / rocBLAS.
+instructions disabled, and linked against rocSOLVER / rocBLAS / rocFFT.
 """
 
 import concurrent.futures as cf
@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbluebild.so")
 
-SOURCES = ["api.cpp", "synth_kernels.hip", "prestep.hip", "synth_bwd.hip", "levels_weighting.hip"]
+SOURCES = ["api.cpp", "synth_kernels.hip", "prestep.hip", "synth_bwd.hip", "levels_weighting.hip", "nufft.hip",
+           "nufft_api.cpp"]
 ARCH = "gfx950"
 
 
@@ -55,7 +56,7 @@ def build(verbose=False):
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + [
-        "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+        "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-lrocfft", "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -18,6 +18,7 @@ constexpr int kMaxEig = 1024;
 constexpr int kErrLevelId = 1;        // a level id outside [-1, n_levels) was treated as -1
 constexpr int kErrKmeansTooFew = 2;   // k-means: fewer positive eigenvalues than positive levels
 constexpr int kErrUvRange = 4;        // uniform weighting: a uv cell index beyond +-2^30 or not finite
+constexpr int kErrNufftExtent = 8;    // NUFFT synthesis: a baseline beyond the planned extent (skipped)
 
 __host__ __device__ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
@@ -105,6 +106,49 @@ struct UvFrame {
 int64_t uv_table_slots(int L);  // hash slots for L^2 pairs (power of two >= 2 L^2); 12 bytes each
 hipError_t launch_uniform_weighting(const double* ant, int64_t ld, int L, const UvFrame& f, void* table,
                                     double* vis, int* err, hipStream_t s);
+
+// NUFFT synthesis (nufft.hip).
+struct NufftGeom {
+  double R[3][3];   // image frame, rows e_u, e_v, p0
+  double D[3];      // centre of the pixels in the frame
+  double X[3];      // bound on |baseline| per frame axis, wavelengths
+  double h[3];      // spread-grid spacing, turns
+  double inv_h[3];  // 1 / h
+  double hM[3];     // h * M: type-2 grid points per unit of pixel offset
+  int N[3];         // spread grid
+  int M[3];         // type-2 (FFT) grid, 2 N
+  int w;            // kernel support in grid points
+  float beta;       // kernel shape
+};
+struct NufftInst {
+  int n_ant, n_eig;
+  double wavelength_m;
+  int64_t ant_off, w_off, eig_off;
+  int64_t ord_off, ls_off;  // this instance's level-grouped order and level starts
+  int64_t vp_off;           // this instance's V' block (n_levels x n_ant^2 complex64)
+};
+hipError_t launch_nufft_prep(const NufftInst* insts, int n_inst, const void* W, const float* d, const int* lev,
+                             int n_levels, int* order, int* lstart, double* diag, int* err, hipStream_t s);
+hipError_t launch_nufft_spread(const NufftGeom& g, const NufftInst* insts, int n_inst, int max_ant,
+                               const double* ant, int64_t ant_ld, const void* Wmat, const float* d, const int* order,
+                               const int* lstart, int n_levels, float* grid, int64_t n_cell, int* err, hipStream_t s);
+hipError_t launch_nufft_pad(const NufftGeom& g, const float* grid_level, const float* inv_psi0, const float* inv_psi1,
+                            const float* inv_psi2, float* out, hipStream_t s);
+hipError_t launch_nufft_interp(const NufftGeom& g, const double* pix, int64_t pix_ld, int64_t n_pix, const float* u,
+                               const double* corr, const double* diag, int lv, float* image, hipStream_t s);
+hipError_t launch_nufft_corr(const NufftGeom& g, const double* pix, int64_t pix_ld, int64_t n_pix, const double* quad_t,
+                             const double* quad_wphi, int n_quad, double* corr, hipStream_t s);
+hipError_t launch_fill_zero_f64(double* p, int n, hipStream_t s);
+hipError_t launch_nufft_vprime(const NufftInst* insts, int n_inst, int max_ant, const void* Wmat, const float* d,
+                               const int* order, const int* lstart, int n_levels, void* vp, hipStream_t s);
+int nufft_tile_size(const NufftGeom& g);  // 16 or 8 grid points per tile side, 0 = no tiled path
+hipError_t launch_nufft_bin(const NufftGeom& g, const NufftInst* insts, int n_inst, int max_ant, const double* ant,
+                            int64_t ld, int bin, int* count, int* offset, int* cursor, uint64_t* list, int* err,
+                            hipStream_t s);
+// nch, choff: n_tiles and n_tiles + 1 ints of scratch (chunks per tile and their offsets).
+hipError_t launch_nufft_spread_tiles(const NufftGeom& g, const NufftInst* insts, const double* ant, int64_t ld,
+                                     const void* vp, const int* offset, const uint64_t* list, int bin, int n_levels,
+                                     int* nch, int* choff, float* grid, int64_t n_cell, hipStream_t s);
 
 // Backward.
 // E recompute (FP32 MFMA, one instance) into two planes [2][K_alloc][n_pix].

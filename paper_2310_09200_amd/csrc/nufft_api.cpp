@@ -1,0 +1,539 @@
+// Host side of NUFFT synthesis (Section 2.5; Section 3.4, Algorithm 3): plan
+// geometry from the options and the pixels, workspace carving, rocFFT plan,
+// and the spread / emit calls declared in include/bluebild.h.
+
+#include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "api_common.h"
+#include "bb_internal.h"
+#include "bluebild.h"
+
+using bb_host::align_up;
+using bb_host::fail;
+using bb_host::finite_pos;
+
+namespace {
+
+constexpr int kSigma = 2;        // type-2 grid upsampling
+constexpr int kQuadNodes = 100;  // Gauss-Legendre nodes for kernel transforms
+
+struct NufftLayout {  // byte offsets into a plan's workspace
+  size_t grid, fft, work, psi0, psi1, psi2, corr, quad_t, quad_wphi, diag, err, total;
+  size_t work_bytes;
+};
+
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton's method on P_n,
+// evaluated by the three-term recurrence.
+void gauss_legendre(int n, std::vector<double>& t, std::vector<double>& wt) {
+  t.assign(n, 0.0);
+  wt.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (x * p1 - p0) / (x * x - 1.0);
+    t[i] = -x;
+    t[n - 1 - i] = x;
+    wt[i] = wt[n - 1 - i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+}
+
+double es_kernel_host(double z, double beta) {
+  return std::fabs(z) <= 1.0 ? std::exp(beta * (std::sqrt(1.0 - z * z) - 1.0)) : 0.0;
+}
+
+int kernel_width(double eps) { return (int)std::ceil(std::log10(1.0 / eps) - 1e-9) + 1; }
+
+int smooth_size(int64_t n) {
+  n = std::max<int64_t>(n, 2);
+  for (;; ++n) {
+    if (n % 2) continue;
+    int64_t m = n;
+    for (int p : {2, 3, 5})
+      while (m % p == 0) m /= p;
+    if (m == 1) return (int)n;
+  }
+}
+
+// Plan geometry (the same rules, in the same arithmetic order, as the
+// grid-size rules documented in the header).
+bb_status nufft_geometry(bb_context ctx, const bb_nufft_options* o, int64_t n_pix, const double* pix_host,
+                         bb::NufftGeom& g) {
+#pragma clang fp contract(off)
+  if (!o) return fail(ctx, BB_ERR_INVALID_ARG, "options is NULL");
+  if (o->n_levels < 1 || o->n_levels > bb::kMaxLevels)
+    return fail(ctx, BB_ERR_INVALID_ARG, "n_levels must be in [1, %d]", bb::kMaxLevels);
+  if (o->n_ant_max < 2 || o->n_ant_max > bb::kMaxAnt)
+    return fail(ctx, BB_ERR_INVALID_ARG, "n_ant_max must be in [2, %d]", bb::kMaxAnt);
+  if (o->k_max < 1 || o->k_max > bb::kMaxEig) return fail(ctx, BB_ERR_INVALID_ARG, "k_max must be in [1, %d]", bb::kMaxEig);
+  if (o->reserved != 0) return fail(ctx, BB_ERR_INVALID_ARG, "reserved must be 0");
+  if (!(o->epsilon >= 1e-7 && o->epsilon <= 1e-2)) return fail(ctx, BB_ERR_INVALID_ARG, "epsilon must be in [1e-7, 1e-2]");
+  for (int i = 0; i < 3; ++i)
+    if (!finite_pos(o->uvw_max[i])) return fail(ctx, BB_ERR_INVALID_ARG, "uvw_max must be finite and > 0");
+  for (int i = 0; i < 9; ++i)
+    if (!std::isfinite(o->frame[i])) return fail(ctx, BB_ERR_INVALID_ARG, "frame must be finite");
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      const double dot = o->frame[3 * a] * o->frame[3 * b] + o->frame[3 * a + 1] * o->frame[3 * b + 1] +
+                         o->frame[3 * a + 2] * o->frame[3 * b + 2];
+      if (std::fabs(dot - (a == b ? 1.0 : 0.0)) > 1e-9) return fail(ctx, BB_ERR_INVALID_ARG, "frame rows must be orthonormal");
+    }
+  if (n_pix < 1 || !pix_host) return fail(ctx, BB_ERR_INVALID_ARG, "need pixels (host copy) for planning");
+  std::memset(&g, 0, sizeof g);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) g.R[a][b] = o->frame[3 * a + b];
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t p = 0; p < n_pix; ++p) {
+    const double a0 = pix_host[p], a1 = pix_host[p + n_pix], a2 = pix_host[p + 2 * n_pix];
+    if (!std::isfinite(a0) || !std::isfinite(a1) || !std::isfinite(a2))
+      return fail(ctx, BB_ERR_INVALID_ARG, "pixel %lld is not finite", (long long)p);
+    for (int d = 0; d < 3; ++d) {
+      const double r = (a0 * g.R[d][0] + a1 * g.R[d][1]) + a2 * g.R[d][2];
+      lo[d] = std::min(lo[d], r);
+      hi[d] = std::max(hi[d], r);
+    }
+  }
+  g.w = kernel_width(o->epsilon);
+  g.beta = (float)(2.30 * g.w);
+  for (int d = 0; d < 3; ++d) {
+    g.D[d] = 0.5 * (lo[d] + hi[d]);
+    const double S = std::max(0.5 * (hi[d] - lo[d]), 1e-12);
+    g.X[d] = o->uvw_max[d];
+    g.h[d] = 1.0 / (2.0 * kSigma * S);
+    g.inv_h[d] = 1.0 / g.h[d];
+    const double need = std::ceil(8.0 * g.X[d] * S) + g.w;
+    if (!(need < 1.0e6)) return fail(ctx, BB_ERR_SHAPE, "grid axis %d would need %.3g points", d, need);
+    g.N[d] = smooth_size(std::max<int64_t>(2 * g.w, (int64_t)need));
+    g.M[d] = kSigma * g.N[d];
+    g.hM[d] = g.h[d] * g.M[d];
+  }
+  return BB_OK;
+}
+
+size_t rocfft_work_bytes(const bb::NufftGeom& g, rocfft_plan* keep) {
+  size_t lengths[3] = {(size_t)g.M[2], (size_t)g.M[1], (size_t)g.M[0]};  // fastest first
+  rocfft_plan plan = nullptr;
+  if (rocfft_plan_create(&plan, rocfft_placement_inplace, rocfft_transform_type_complex_inverse,
+                         rocfft_precision_single, 3, lengths, 1, nullptr) != rocfft_status_success)
+    return (size_t)-1;
+  size_t bytes = 0;
+  rocfft_plan_get_work_buffer_size(plan, &bytes);
+  if (keep)
+    *keep = plan;
+  else
+    rocfft_plan_destroy(plan);
+  return bytes;
+}
+
+NufftLayout nufft_layout(const bb::NufftGeom& g, int n_levels, int64_t n_pix, size_t work_bytes) {
+  NufftLayout l{};
+  const size_t n_cell = (size_t)g.N[0] * g.N[1] * g.N[2];
+  const size_t m_cell = (size_t)g.M[0] * g.M[1] * g.M[2];
+  size_t p = 0;
+  l.grid = p;
+  p += align_up(8 * n_cell * (size_t)n_levels);
+  l.fft = p;
+  p += align_up(8 * m_cell);
+  l.work = p;
+  l.work_bytes = work_bytes;
+  p += align_up(std::max<size_t>(work_bytes, 1));
+  l.psi0 = p;
+  p += align_up(4 * (size_t)g.N[0]);
+  l.psi1 = p;
+  p += align_up(4 * (size_t)g.N[1]);
+  l.psi2 = p;
+  p += align_up(4 * (size_t)g.N[2]);
+  l.corr = p;
+  p += align_up(8 * (size_t)n_pix);
+  l.quad_t = p;
+  p += align_up(8 * kQuadNodes);
+  l.quad_wphi = p;
+  p += align_up(8 * kQuadNodes);
+  l.diag = p;
+  p += align_up(8 * bb::kMaxLevels);
+  l.err = p;
+  p += bb_host::kAlign;
+  l.total = p;
+  return l;
+}
+
+std::once_flag g_rocfft_once;
+rocfft_status g_rocfft_setup = rocfft_status_success;
+
+}  // namespace
+
+struct bb_nufft_ {
+  bb_context ctx = nullptr;
+  bb_nufft_options opt{};
+  bb::NufftGeom g{};
+  int64_t n_pix = 0;
+  const double* pix = nullptr;
+  float* images = nullptr;
+  char* ws = nullptr;
+  NufftLayout lay{};
+  rocfft_plan plan = nullptr;
+  rocfft_execution_info info = nullptr;
+  int64_t count = 0;  // instances spread since the last emit
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool spread_timed = false, emit_timed = false;
+};
+
+namespace {
+
+template <class T>
+T* nat(bb_nufft h, size_t off) {
+  return reinterpret_cast<T*>(h->ws + off);
+}
+
+}  // namespace
+
+extern "C" {
+
+bb_status bb_nufft_workspace_size(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix, const double* pix_host,
+                                  size_t* bytes) {
+  if (!ctx || !bytes) return BB_ERR_INVALID_ARG;
+  bb::NufftGeom g;
+  bb_status st = nufft_geometry(ctx, opt, n_pix, pix_host, g);
+  if (st != BB_OK) return st;
+  std::call_once(g_rocfft_once, [] { g_rocfft_setup = rocfft_setup(); });
+  if (g_rocfft_setup != rocfft_status_success) return fail(ctx, BB_ERR_DEVICE, "rocfft_setup failed");
+  const size_t work = rocfft_work_bytes(g, nullptr);
+  if (work == (size_t)-1) return fail(ctx, BB_ERR_DEVICE, "rocfft_plan_create failed");
+  *bytes = nufft_layout(g, opt->n_levels, n_pix, work).total;
+  return BB_OK;
+}
+
+bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix, const double* pix_host,
+                          const double* pix_xyz, float* images, void* workspace, size_t ws_bytes, bb_nufft* out) {
+  if (!ctx || !out) return BB_ERR_INVALID_ARG;
+  *out = nullptr;
+  bb::NufftGeom g;
+  bb_status st = nufft_geometry(ctx, opt, n_pix, pix_host, g);
+  if (st != BB_OK) return st;
+  if (!pix_xyz || !images || !workspace) return fail(ctx, BB_ERR_INVALID_ARG, "null device pointer");
+  if (reinterpret_cast<uintptr_t>(workspace) % bb_host::kAlign)
+    return fail(ctx, BB_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  std::call_once(g_rocfft_once, [] { g_rocfft_setup = rocfft_setup(); });
+  if (g_rocfft_setup != rocfft_status_success) return fail(ctx, BB_ERR_DEVICE, "rocfft_setup failed");
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  rocfft_plan plan = nullptr;
+  const size_t work = rocfft_work_bytes(g, &plan);
+  if (work == (size_t)-1) return fail(ctx, BB_ERR_DEVICE, "rocfft_plan_create failed");
+  const NufftLayout lay = nufft_layout(g, opt->n_levels, n_pix, work);
+  if (ws_bytes < lay.total) {
+    rocfft_plan_destroy(plan);
+    return fail(ctx, BB_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, lay.total);
+  }
+  bb_nufft h = new (std::nothrow) bb_nufft_;
+  if (!h) {
+    rocfft_plan_destroy(plan);
+    return fail(ctx, BB_ERR_DEVICE, "out of host memory");
+  }
+  h->ctx = ctx;
+  h->opt = *opt;
+  h->g = g;
+  h->n_pix = n_pix;
+  h->pix = pix_xyz;
+  h->images = images;
+  h->ws = static_cast<char*>(workspace);
+  h->lay = lay;
+  h->plan = plan;
+  auto bail = [&](const char* what) {
+    if (h->info) rocfft_execution_info_destroy(h->info);
+    rocfft_plan_destroy(h->plan);
+    for (hipEvent_t& e : h->ev)
+      if (e) hipEventDestroy(e);
+    delete h;
+    return fail(ctx, BB_ERR_DEVICE, "%s", what);
+  };
+  if (rocfft_execution_info_create(&h->info) != rocfft_status_success) return bail("rocfft_execution_info_create failed");
+  if (work > 0 && rocfft_execution_info_set_work_buffer(h->info, h->ws + lay.work, work) != rocfft_status_success)
+    return bail("rocfft_execution_info_set_work_buffer failed");
+  if (rocfft_execution_info_set_stream(h->info, ctx->stream) != rocfft_status_success)
+    return bail("rocfft_execution_info_set_stream failed");
+  for (hipEvent_t& e : h->ev)
+    if (hipEventCreate(&e) != hipSuccess) return bail("hipEventCreate failed");
+
+  // host tables: 1 / type-2 kernel transform per stored grid index, quadrature
+  std::vector<double> qt, qw;
+  gauss_legendre(kQuadNodes, qt, qw);
+  std::vector<double> wphi(kQuadNodes);
+  for (int j = 0; j < kQuadNodes; ++j) wphi[j] = qw[j] * es_kernel_host(qt[j], (double)g.beta);
+  std::vector<float> psi[3];
+  for (int d = 0; d < 3; ++d) {
+    psi[d].resize(g.N[d]);
+    const double a = 0.5 * g.w;
+    for (int i = 0; i < g.N[d]; ++i) {
+      const int freq = i < g.N[d] / 2 ? i : i - g.N[d];
+      const double k = freq * (2.0 * M_PI / g.M[d]);
+      double acc = 0.0;
+      for (int j = 0; j < kQuadNodes; ++j) acc += wphi[j] * std::cos(k * a * qt[j]);
+      psi[d][i] = (float)(1.0 / (a * acc));  // psi_hat(g) M / (2 pi), inverted
+    }
+  }
+  hipStream_t s = ctx->stream;
+  // pageable sources: each copy is staged before the call returns
+  if (hipMemcpyAsync(nat<float>(h, lay.psi0), psi[0].data(), 4 * psi[0].size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(nat<float>(h, lay.psi1), psi[1].data(), 4 * psi[1].size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(nat<float>(h, lay.psi2), psi[2].data(), 4 * psi[2].size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(nat<double>(h, lay.quad_t), qt.data(), 8 * kQuadNodes, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(nat<double>(h, lay.quad_wphi), wphi.data(), 8 * kQuadNodes, hipMemcpyHostToDevice, s) != hipSuccess)
+    return bail("table upload failed");
+  if (bb::launch_nufft_corr(g, pix_xyz, n_pix, n_pix, nat<double>(h, lay.quad_t), nat<double>(h, lay.quad_wphi),
+                            kQuadNodes, nat<double>(h, lay.corr), s) != hipSuccess ||
+      bb::launch_fill_zero(nat<float>(h, lay.grid), (int64_t)2 * g.N[0] * g.N[1] * g.N[2] * opt->n_levels, s) !=
+          hipSuccess ||
+      bb::launch_fill_zero_f64(nat<double>(h, lay.diag), bb::kMaxLevels, s) != hipSuccess ||
+      bb::launch_fill_zero(nat<float>(h, lay.err), 1, s) != hipSuccess)
+    return bail("plan set-up launch failed");
+  if (hipStreamSynchronize(s) != hipSuccess) return bail("plan set-up failed on the device");
+  ctx->live += 1;
+  *out = h;
+  return BB_OK;
+}
+
+bb_status bb_nufft_shape(bb_nufft h, int32_t* spread_grid, int32_t* fft_grid, int32_t* kernel_width_out) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  for (int d = 0; d < 3; ++d) {
+    if (spread_grid) spread_grid[d] = h->g.N[d];
+    if (fft_grid) fft_grid[d] = h->g.M[d];
+  }
+  if (kernel_width_out) *kernel_width_out = h->g.w;
+  return BB_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Per-call workspace of a spread call (byte offsets).
+struct CallLayout {
+  size_t inst, order, lstart, vp, count, offset, cursor, list, nch, choff, total;
+  int bin = 0, n_bins = 0;
+};
+
+CallLayout call_layout(bb_nufft h, int32_t n_inst, const bb_instance* inst) {
+  CallLayout c{};
+  size_t n_eig = 0, vp = 0, pairs = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    const size_t L = (size_t)std::max(inst[i].n_ant, 0);
+    n_eig += (size_t)std::max(inst[i].n_eig, 0);
+    vp += (size_t)h->opt.n_levels * L * L;
+    pairs += L * (L > 0 ? L - 1 : 0) / 2;
+  }
+  c.bin = bb::nufft_tile_size(h->g);
+  size_t p = 0;
+  c.inst = p;
+  p += align_up(sizeof(bb::NufftInst) * n_inst);
+  c.order = p;
+  p += align_up(4 * n_eig);
+  c.lstart = p;
+  p += align_up(4 * (size_t)n_inst * (h->opt.n_levels + 1));
+  if (c.bin > 0) {
+    c.n_bins = ((h->g.N[0] + c.bin - 1) / c.bin) * ((h->g.N[1] + c.bin - 1) / c.bin);
+    c.vp = p;
+    p += align_up(8 * vp);
+    c.count = p;
+    p += align_up(4 * (size_t)c.n_bins);
+    c.offset = p;
+    p += align_up(4 * ((size_t)c.n_bins + 1));
+    c.cursor = p;
+    p += align_up(4 * (size_t)c.n_bins);
+    c.list = p;
+    p += align_up(8 * std::max<size_t>(pairs, 1));
+    c.nch = p;  // tiles and bins share one grid
+    p += align_up(4 * (size_t)c.n_bins);
+    c.choff = p;
+    p += align_up(4 * ((size_t)c.n_bins + 1));
+  }
+  c.total = p;
+  return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+bb_status bb_nufft_batched_workspace_size(bb_nufft h, int32_t n_inst, const bb_instance* inst, size_t* bytes) {
+  if (!h || !bytes || n_inst < 1 || !inst) return BB_ERR_INVALID_ARG;
+  *bytes = call_layout(h, n_inst, inst).total;
+  return BB_OK;
+}
+
+bb_status bb_nufft_collect_eig_batched(bb_nufft h, int32_t n_inst, const bb_instance* inst, int64_t n_ant_rows,
+                                       const double* ant_xyz_packed, const void* W_packed, const float* d_packed,
+                                       const int32_t* level_packed, void* workspace, size_t ws_bytes) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  if (n_inst < 1 || n_inst > 65535 || !inst) return fail(ctx, BB_ERR_INVALID_ARG, "n_inst must be in [1, 65535]");
+  if (!ant_xyz_packed || !W_packed || !d_packed || !level_packed || !workspace)
+    return fail(ctx, BB_ERR_INVALID_ARG, "null device pointer");
+  if (reinterpret_cast<uintptr_t>(workspace) % bb_host::kAlign)
+    return fail(ctx, BB_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  const int n_levels = h->opt.n_levels;
+  std::vector<bb::NufftInst> ni(n_inst);
+  int64_t ord_off = 0, vp_off = 0;
+  int max_ant = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    const bb_instance& b = inst[i];
+    if (b.n_ant < 2 || b.n_ant > h->opt.n_ant_max)
+      return fail(ctx, BB_ERR_SHAPE, "instance %d: n_ant %d outside [2, %d]", i, b.n_ant, h->opt.n_ant_max);
+    if (b.n_eig < 1 || b.n_eig > h->opt.k_max)
+      return fail(ctx, BB_ERR_SHAPE, "instance %d: n_eig %d outside [1, %d]", i, b.n_eig, h->opt.k_max);
+    if (b.slot != 0) return fail(ctx, BB_ERR_INVALID_ARG, "instance %d: slot must be 0", i);
+    if (!finite_pos(b.wavelength_m)) return fail(ctx, BB_ERR_INVALID_ARG, "instance %d: bad wavelength", i);
+    if (b.ant_off < 0 || b.ant_off + b.n_ant > n_ant_rows || b.w_off < 0 || b.eig_off < 0)
+      return fail(ctx, BB_ERR_INVALID_ARG, "instance %d: offsets out of range", i);
+    bb::NufftInst& d = ni[i];
+    d.n_ant = b.n_ant;
+    d.n_eig = b.n_eig;
+    d.wavelength_m = b.wavelength_m;
+    d.ant_off = b.ant_off;
+    d.w_off = b.w_off;
+    d.eig_off = b.eig_off;
+    d.ord_off = ord_off;
+    d.ls_off = (int64_t)i * (n_levels + 1);
+    d.vp_off = vp_off;
+    ord_off += b.n_eig;
+    vp_off += (int64_t)n_levels * b.n_ant * b.n_ant;
+    max_ant = std::max(max_ant, b.n_ant);
+  }
+  const CallLayout cl = call_layout(h, n_inst, inst);
+  if (ws_bytes < cl.total) return fail(ctx, BB_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, cl.total);
+  char* ws = static_cast<char*>(workspace);
+  bb::NufftInst* d_inst = reinterpret_cast<bb::NufftInst*>(ws + cl.inst);
+  int* d_order = reinterpret_cast<int*>(ws + cl.order);
+  int* d_lstart = reinterpret_cast<int*>(ws + cl.lstart);
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  BB_HIP(ctx, hipEventRecord(h->ev[0], s));
+  // pageable source: the copy is staged before the call returns
+  BB_HIP(ctx, hipMemcpyAsync(d_inst, ni.data(), sizeof(bb::NufftInst) * n_inst, hipMemcpyHostToDevice, s));
+  BB_HIP(ctx, bb::launch_nufft_prep(d_inst, n_inst, W_packed, d_packed, level_packed, n_levels, d_order, d_lstart,
+                                    nat<double>(h, h->lay.diag), nat<int>(h, h->lay.err), s));
+  const int64_t n_cell = (int64_t)h->g.N[0] * h->g.N[1] * h->g.N[2];
+  if (cl.bin > 0) {
+    BB_HIP(ctx, bb::launch_nufft_vprime(d_inst, n_inst, max_ant, W_packed, d_packed, d_order, d_lstart, n_levels,
+                                        ws + cl.vp, s));
+    int* count = reinterpret_cast<int*>(ws + cl.count);
+    int* offset = reinterpret_cast<int*>(ws + cl.offset);
+    int* cursor = reinterpret_cast<int*>(ws + cl.cursor);
+    uint64_t* list = reinterpret_cast<uint64_t*>(ws + cl.list);
+    BB_HIP(ctx, bb::launch_nufft_bin(h->g, d_inst, n_inst, max_ant, ant_xyz_packed, n_ant_rows, cl.bin, count, offset,
+                                     cursor, list, nat<int>(h, h->lay.err), s));
+    BB_HIP(ctx, bb::launch_nufft_spread_tiles(h->g, d_inst, ant_xyz_packed, n_ant_rows, ws + cl.vp, offset, list,
+                                              cl.bin, n_levels, reinterpret_cast<int*>(ws + cl.nch),
+                                              reinterpret_cast<int*>(ws + cl.choff), nat<float>(h, h->lay.grid), n_cell,
+                                              s));
+  } else {
+    BB_HIP(ctx, bb::launch_nufft_spread(h->g, d_inst, n_inst, max_ant, ant_xyz_packed, n_ant_rows, W_packed, d_packed,
+                                        d_order, d_lstart, n_levels, nat<float>(h, h->lay.grid), n_cell,
+                                        nat<int>(h, h->lay.err), s));
+  }
+  BB_HIP(ctx, hipEventRecord(h->ev[1], s));
+  h->spread_timed = true;
+  h->count += n_inst;
+  return BB_OK;
+}
+
+bb_status bb_nufft_emit(bb_nufft h) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const bb::NufftGeom& g = h->g;
+  const int64_t n_cell = (int64_t)g.N[0] * g.N[1] * g.N[2];
+  float* fft = nat<float>(h, h->lay.fft);
+  // the context's stream may have been rebound since the plan was made
+  if (rocfft_execution_info_set_stream(h->info, s) != rocfft_status_success)
+    return fail(ctx, BB_ERR_DEVICE, "rocfft_execution_info_set_stream failed");
+  BB_HIP(ctx, hipEventRecord(h->ev[2], s));
+  for (int lv = 0; lv < h->opt.n_levels; ++lv) {
+    BB_HIP(ctx, bb::launch_nufft_pad(g, nat<float>(h, h->lay.grid) + 2 * (int64_t)lv * n_cell, nat<float>(h, h->lay.psi0),
+                                     nat<float>(h, h->lay.psi1), nat<float>(h, h->lay.psi2), fft, s));
+    void* buf[1] = {fft};
+    if (rocfft_execute(h->plan, buf, nullptr, h->info) != rocfft_status_success)
+      return fail(ctx, BB_ERR_DEVICE, "rocfft_execute failed");
+    BB_HIP(ctx, bb::launch_nufft_interp(g, h->pix, h->n_pix, h->n_pix, fft, nat<double>(h, h->lay.corr),
+                                        nat<double>(h, h->lay.diag), lv, h->images + (int64_t)lv * h->n_pix, s));
+  }
+  BB_HIP(ctx, bb::launch_fill_zero(nat<float>(h, h->lay.grid), 2 * n_cell * h->opt.n_levels, s));
+  BB_HIP(ctx, bb::launch_fill_zero_f64(nat<double>(h, h->lay.diag), bb::kMaxLevels, s));
+  BB_HIP(ctx, hipEventRecord(h->ev[3], s));
+  h->emit_timed = true;
+  h->count = 0;
+  return BB_OK;
+}
+
+bb_status bb_nufft_sync(bb_nufft h) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  BB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  int err = 0;
+  BB_HIP(ctx, hipMemcpy(&err, nat<int>(h, h->lay.err), sizeof err, hipMemcpyDeviceToHost));
+  if (err) {
+    BB_HIP(ctx, bb::launch_fill_zero(nat<float>(h, h->lay.err), 1, ctx->stream));
+    BB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    std::string msg;
+    if (err & bb::kErrLevelId) msg += "a level id outside [-1, n_levels) was treated as -1; ";
+    if (err & bb::kErrNufftExtent) msg += "a baseline beyond uvw_max was skipped; ";
+    if (msg.size() >= 2) msg.resize(msg.size() - 2);
+    return fail(ctx, BB_ERR_INVALID_ARG, "%s", msg.c_str());
+  }
+  return BB_OK;
+}
+
+bb_status bb_nufft_timings(bb_nufft h, double* ms_out, int32_t n) {
+  if (!h || !ms_out || n < 1) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  BB_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  float a = 0.0f, b = 0.0f;
+  if (h->spread_timed) BB_HIP(ctx, hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
+  if (h->emit_timed) BB_HIP(ctx, hipEventElapsedTime(&b, h->ev[2], h->ev[3]));
+  ms_out[0] = a;
+  if (n > 1) ms_out[1] = b;
+  return BB_OK;
+}
+
+bb_status bb_nufft_destroy(bb_nufft h) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  if (h->info) rocfft_execution_info_destroy(h->info);
+  if (h->plan) rocfft_plan_destroy(h->plan);
+  for (hipEvent_t& e : h->ev)
+    if (e) hipEventDestroy(e);
+  ctx->live -= 1;
+  delete h;
+  return BB_OK;
+}
+
+}  // extern "C"

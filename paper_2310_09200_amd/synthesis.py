@@ -278,6 +278,94 @@ class StandardSynthesis:
             pass
 
 
+class NufftSynthesis:
+    """NUFFT synthesis plan (Section 2.5; Section 3.4, Algorithm 3) over the C ABI.
+
+    ``pix`` (n_pix, 3) float64 unit vectors; ``frame`` rows e_u, e_v, p0 (orthonormal,
+    same frame as the antenna positions); ``uvw_max`` (3,) bound on |baseline| / wavelength
+    along the frame rows over every instance to be collected; ``eps`` the requested accuracy.
+    Instances go in with :meth:`collect_eig_batched` (a :class:`Batch` with slot 0
+    everywhere); :meth:`emit` transforms what was collected into ``images`` (n_levels, n_pix).
+    """
+
+    def __init__(self, ctx, pix, n_levels, n_ant_max, k_max, eps, frame, uvw_max):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        dev = ctx.device
+        pix_np = np.ascontiguousarray(np.asarray(pix, np.float64).T)        # host, column-major (n_pix, 3)
+        self.n_pix = int(pix_np.shape[1])
+        self.n_levels = int(n_levels)
+        self.pix_cm = torch.as_tensor(pix_np).to(dev)
+        self.opt = _lib.bb_nufft_options(n_levels=int(n_levels), n_ant_max=int(n_ant_max), k_max=int(k_max),
+                                         reserved=0, epsilon=float(eps))
+        fr = np.asarray(frame, np.float64).reshape(9)
+        um = np.asarray(uvw_max, np.float64).reshape(3)
+        for i in range(9):
+            self.opt.frame[i] = float(fr[i])
+        for i in range(3):
+            self.opt.uvw_max[i] = float(um[i])
+        hp = ctypes.c_void_p(pix_np.ctypes.data)
+        sz = ctypes.c_size_t()
+        check(self.lib.bb_nufft_workspace_size(ctx.handle, ctypes.byref(self.opt), self.n_pix, hp, ctypes.byref(sz)),
+              ctx.handle)
+        self.workspace = torch.empty(sz.value + 256, dtype=torch.uint8, device=dev)
+        ws_ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.images = torch.zeros((self.n_levels, self.n_pix), dtype=torch.float32, device=dev)
+        h = ctypes.c_void_p()
+        ctx.bind_current_stream()
+        check(self.lib.bb_nufft_create(ctx.handle, ctypes.byref(self.opt), self.n_pix, hp, _ptr(self.pix_cm),
+                                       _ptr(self.images), ctypes.c_void_p(ws_ptr), sz.value, ctypes.byref(h)),
+              ctx.handle)
+        self.handle = h
+        self._keep = []
+
+    @property
+    def shape(self):
+        """(spread grid N (3,), FFT grid M (3,), kernel width w)."""
+        n = (ctypes.c_int32 * 3)()
+        m = (ctypes.c_int32 * 3)()
+        w = ctypes.c_int32()
+        check(self.lib.bb_nufft_shape(self.handle, n, m, ctypes.byref(w)), self.ctx.handle)
+        return tuple(n), tuple(m), w.value
+
+    def collect_eig_batched(self, batch):
+        arr = (_lib.bb_instance * len(batch.inst))(*batch.inst)
+        sz = ctypes.c_size_t()
+        check(self.lib.bb_nufft_batched_workspace_size(self.handle, len(batch.inst), arr, ctypes.byref(sz)),
+              self.ctx.handle)
+        ws = torch.empty(sz.value + 256, dtype=torch.uint8, device=self.ctx.device)
+        ws_ptr = (ws.data_ptr() + 255) // 256 * 256
+        self.ctx.bind_current_stream()
+        check(self.lib.bb_nufft_collect_eig_batched(
+            self.handle, len(batch.inst), arr, batch.n_ant_rows, _ptr(batch.ant), _ptr(batch.W), _ptr(batch.d),
+            _ptr(batch.lev), ctypes.c_void_p(ws_ptr), sz.value), self.ctx.handle)
+        self._keep = [batch, ws]
+
+    def emit(self):
+        self.ctx.bind_current_stream()
+        check(self.lib.bb_nufft_emit(self.handle), self.ctx.handle)
+
+    def sync(self):
+        check(self.lib.bb_nufft_sync(self.handle), self.ctx.handle)
+
+    def timings(self):
+        """(spread, emit) device milliseconds of the last calls."""
+        out = (ctypes.c_double * 2)()
+        check(self.lib.bb_nufft_timings(self.handle, out, 2), self.ctx.handle)
+        return tuple(out)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(self.lib.bb_nufft_destroy(self.handle), self.ctx.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Batch:
     """Packed device arrays + instance table for :meth:`StandardSynthesis.collect_eig_batched`.
 

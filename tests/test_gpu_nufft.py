@@ -1,0 +1,156 @@
+"""GPU NUFFT synthesis against the oracle (through the C ABI).
+
+Two references: the oracle's NUFFT (the same steps and constants in FP64:
+the GPU's FP32 grid and transform must agree to about 1e-5 of each level's
+peak), and standard synthesis of the same eigenpairs (the exact image, which
+the NUFFT reaches within its tolerance).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as ref
+import sims
+from oracle import levels_ref as lv
+from oracle import nufft_ref as nf
+from sims import configs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    from paper_2310_09200_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _instances(n_inst, n_ant, n_side, n_pos, seed, fov_deg=5.0):
+    """Eigenpairs of C1-like instances (array rotated per instance), all positive levels + 1 negative."""
+    w = configs.c1(n_ant=max(n_ant), n_side=n_side, fov_deg=fov_deg)
+    g = sims.rng(95, seed)
+    out = []
+    for i in range(n_inst):
+        inst = w.instance(0)
+        L = n_ant[i % len(n_ant)]
+        x = sims.earth_rotate(inst.x[:L], 0.3 * i)
+        V = inst.V[:L, :L]
+        wl = inst.wl * (1.0 + 0.1 * i)
+        lam, A = ref.geneig(V, ref.gram(x, wl))
+        K = min(L, 40)
+        lam, W = ref.select_top(lam, A, K)
+        out.append((x, wl, W, lam))
+    lam_all = np.concatenate([o[3] for o in out])
+    iv = lv.kmeans_intervals(lam_all, n_pos)
+    items = []
+    for x, wl, W, lam in out:
+        items.append((x, wl, W, ref.lsq_filter(lam), ref.level_membership(lam, iv), lv.level_of(lam, iv)))
+    return w.pix, items, iv.shape[0]
+
+
+def _uvw_bound(items, frame):
+    b = np.zeros(3)
+    for x, wl, *_ in items:
+        li, mi = np.triu_indices(x.shape[0], k=1)
+        b = np.maximum(b, np.max(np.abs(nf.rotate(x[li] - x[mi], frame) / wl), axis=0))
+    return b * 1.01
+
+
+def _run(ctx, pix, items, n_levels, eps, frame, uvw, n_ant_max=64, k_max=64, emits=1):
+    from paper_2310_09200_amd import Batch, NufftSynthesis
+    plan = NufftSynthesis(ctx, pix, n_levels, n_ant_max, k_max, eps, frame, uvw)
+    chunks = np.array_split(np.arange(len(items)), emits)
+    for ch in chunks:
+        b = Batch([(0, items[i][0], items[i][1], items[i][2], items[i][3], items[i][5]) for i in ch], ctx.device)
+        plan.collect_eig_batched(b)
+        plan.emit()
+    plan.sync()
+    got = plan.images.double().cpu().numpy()
+    shape = plan.shape
+    plan.close()
+    return got, shape
+
+
+def _check(got, want, tol):
+    for a, b in zip(got, want):
+        peak = np.max(np.abs(b))
+        assert np.max(np.abs(a - b)) <= tol * peak, (np.max(np.abs(a - b)) / peak, tol)
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-5, 1e-6])
+def test_nufft_single_instance(ctx, eps):
+    say(f"case nufft single instance eps={eps}")
+    pix, items, n_levels = _instances(1, [48], 40, 3, 0)
+    frame = np.array(sims.tangent_basis(90.0))
+    uvw = _uvw_bound(items, frame)
+    got, (N, M, w) = _run(ctx, pix, items, n_levels, eps, frame, uvw)
+    P = nf.plan_params(eps, uvw, nf.rotate(pix, frame))
+    assert list(N) == list(P["N"]) and list(M) == list(P["M"]) and w == P["w"]
+    want_nufft = nf.nufft_images([(x, wl, W, d, mem) for x, wl, W, d, mem, _ in items], pix, eps, X=uvw, frame=frame)
+    _check(got, want_nufft, 1e-5)
+    x, wl, W, d, mem, _ = items[0]
+    want = ref.synthesize_blas(W, d, mem, x, pix, wl)
+    _check(got, want, 3 * eps + 1e-5)
+
+
+def test_nufft_batched_ragged_instances(ctx):
+    say("case nufft three instances, L = 48 / 37 / 64, two emits")
+    pix, items, n_levels = _instances(3, [48, 37, 64], 32, 4, 1)
+    frame = np.array(sims.tangent_basis(90.0))
+    uvw = _uvw_bound(items, frame)
+    got, _ = _run(ctx, pix, items, n_levels, 1e-5, frame, uvw, emits=2)
+    want = sum(ref.synthesize_blas(W, d, mem, x, pix, wl) for x, wl, W, d, mem, _ in items)
+    _check(got, want, 4e-5)
+    want_nufft = nf.nufft_images([(x, wl, W, d, mem) for x, wl, W, d, mem, _ in items], pix, 1e-5, X=uvw, frame=frame)
+    _check(got, want_nufft, 1e-5)
+
+
+def test_nufft_tilted_frame(ctx):
+    """Pixels around a phase centre at declination +50 deg; the grid is thin along p0."""
+    say("case nufft tilted frame")
+    w = configs.c1(n_ant=40, n_side=24)
+    inst = w.instance(0)
+    pix = sims.pixel_grid(24, 4.0, 50.0)
+    frame = np.array(sims.tangent_basis(50.0))
+    lam, A = ref.geneig(inst.V, ref.gram(inst.x, inst.wl))
+    lam, W = ref.select_top(lam, A, 40)
+    iv = lv.kmeans_intervals(lam, 2)
+    items = [(inst.x, inst.wl, W, ref.lsq_filter(lam), ref.level_membership(lam, iv), lv.level_of(lam, iv))]
+    uvw = _uvw_bound(items, frame)
+    got, (N, M, wk) = _run(ctx, pix, items, iv.shape[0], 1e-5, frame, uvw)
+    assert N[2] < N[0]
+    want = ref.synthesize_blas(W, ref.lsq_filter(lam), items[0][4], inst.x, pix, inst.wl)
+    _check(got, want, 4e-5)
+
+
+def test_nufft_baseline_beyond_bound_reported(ctx):
+    from paper_2310_09200_amd import Batch, BluebildError, NufftSynthesis
+    say("case nufft baseline beyond uvw_max")
+    pix, items, n_levels = _instances(1, [16], 16, 2, 2)
+    frame = np.eye(3)
+    uvw = np.maximum(_uvw_bound(items, frame) * 0.5, 1.0)   # the flat array has no extent along z
+    plan = NufftSynthesis(ctx, pix, n_levels, 16, 16, 1e-4, frame, uvw)
+    x, wl, W, d, mem, lev = items[0]
+    plan.collect_eig_batched(Batch([(0, x, wl, W, d, lev)], ctx.device))
+    plan.emit()
+    with pytest.raises(BluebildError, match="uvw_max"):
+        plan.sync()
+    assert np.all(np.isfinite(plan.images.cpu().numpy()))
+    plan.close()
+
+
+def test_nufft_rejects_bad_options(ctx):
+    from paper_2310_09200_amd import BluebildError, NufftSynthesis
+    pix = sims.pixel_grid(8, 2.0)
+    with pytest.raises(BluebildError):
+        NufftSynthesis(ctx, pix, 2, 16, 16, 1e-9, np.eye(3), [10.0, 10.0, 10.0])
+    with pytest.raises(BluebildError):
+        NufftSynthesis(ctx, pix, 2, 16, 16, 1e-4, np.diag([1.0, 1.0, 2.0]), [10.0, 10.0, 10.0])
