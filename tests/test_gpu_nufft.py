@@ -85,6 +85,19 @@ def _check(got, want, tol):
         assert np.max(np.abs(a - b)) <= tol * peak, (np.max(np.abs(a - b)) / peak, tol)
 
 
+def _check_contract(got, want, insts, eps):
+    """The NUFFT's accuracy contract: per level, |I - I_exact| <= 2 eps sum_{q<r} |V'[r, q]|
+    (the image is 2 Re of the transformed sum), plus FP32 slack of 1e-5 of the peak."""
+    l1 = 0.0
+    for x, wl, W, d, member in insts:
+        Vp = nf.level_visibilities(W, d, member)
+        li, mi = np.triu_indices(x.shape[0], k=1)
+        l1 = l1 + np.abs(Vp[:, mi, li]).sum(axis=1)
+    for lv, (a, b) in enumerate(zip(got, want)):
+        err = np.max(np.abs(a - b))
+        assert err <= 2 * eps * l1[lv] + 1e-5 * np.max(np.abs(b)), (lv, err, 2 * eps * l1[lv])
+
+
 @pytest.mark.parametrize("eps", [1e-3, 1e-5, 1e-6])
 def test_nufft_single_instance(ctx, eps):
     say(f"case nufft single instance eps={eps}")
@@ -154,3 +167,38 @@ def test_nufft_rejects_bad_options(ctx):
         NufftSynthesis(ctx, pix, 2, 16, 16, 1e-9, np.eye(3), [10.0, 10.0, 10.0])
     with pytest.raises(BluebildError):
         NufftSynthesis(ctx, pix, 2, 16, 16, 1e-4, np.diag([1.0, 1.0, 2.0]), [10.0, 10.0, 10.0])
+
+
+@pytest.mark.parametrize("fov_deg,path", [(30.0, "tiles of 8 grid points"), (60.0, "global atomics")])
+def test_nufft_thick_grids(ctx, fov_deg, path):
+    """A 3-D antenna cloud and a wide field make the grid thick along p0: the
+    spread runs on smaller LDS tiles (32 < N2 <= 128) or, past 128 points,
+    with global atomics; both against standard synthesis."""
+    from paper_2310_09200_amd import Batch, NufftSynthesis
+    say(f"case nufft thick grid, field {fov_deg} deg ({path})")
+    g = sims.rng(96, int(fov_deg))
+    L, K = 40, 20
+    x = g.uniform(-150.0, 150.0, (L, 3))
+    wl = 2.0
+    pix = sims.pixel_grid(16, fov_deg, 90.0)
+    W = (g.normal(size=(L, K)) + 1j * g.normal(size=(L, K))) / np.sqrt(2 * L)
+    d = np.exp(g.normal(size=K)) * np.where(np.arange(K) < 15, 1.0, -1.0)
+    lev = np.minimum(np.arange(K) // 6, 2).astype(np.int32)
+    member = ref.membership_from_level_of(lev, 3)
+    frame = np.array(sims.tangent_basis(90.0))
+    items = [(x, wl, W, d, member, lev)]
+    uvw = _uvw_bound(items, frame)
+    eps = 1e-4
+    plan = NufftSynthesis(ctx, pix, 3, L, K, eps, frame, uvw)
+    N, M, wk = plan.shape
+    assert (32 < N[2] <= 128) if fov_deg == 30.0 else (N[2] > 128), N
+    plan.collect_eig_batched(Batch([(0, x, wl, W, d, lev)], ctx.device))
+    plan.emit()
+    plan.sync()
+    got = plan.images.double().cpu().numpy()
+    plan.close()
+    want = ref.synthesize_blas(W, d, member, x, pix, wl)
+    _check_contract(got, want, [(x, wl, W, d, member)], eps)
+    if fov_deg == 30.0:  # small enough for the FP64 NUFFT oracle on the host
+        want_nufft = nf.nufft_images([(x, wl, W, d, member)], pix, eps, X=uvw, frame=frame)
+        _check(got, want_nufft, 1e-5)
