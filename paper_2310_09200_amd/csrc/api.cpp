@@ -412,6 +412,8 @@ static bb_status run_prestep(bb_synth h, int32_t n_ant, double wavelength_m, con
   BB_HIP(ctx, hipEventRecord(h->ev[0], s));
   BB_HIP(ctx, bb::launch_gram(ant_xyz, n_ant, n_ant, wavelength_m, G, n_ant, h->opt.gram == BB_GRAM_IDENTITY, s));
   BB_HIP(ctx, bb::launch_copy_c128(vis, n_sys, A, n_sys, s));
+  double* herm = reinterpret_cast<double*>(h->ws + L.info + 16);  // two doubles beside the solver status
+  BB_HIP(ctx, bb::launch_herm_check(vis, n_sys, herm, s));
   rocblas_set_stream(ctx->rb, s);
   if (L.solver_bytes > 0 && rocblas_set_workspace(ctx->rb, h->ws + L.solver, L.solver_bytes) != rocblas_status_success)
     return fail(ctx, BB_ERR_DEVICE, "rocblas_set_workspace failed");
@@ -444,13 +446,19 @@ static bb_status run_prestep(bb_synth h, int32_t n_ant, double wavelength_m, con
   if (rs != rocblas_status_success) return fail(ctx, BB_ERR_DEVICE, "rocsolver_zhegvd / zgemm status %d", (int)rs);
   BB_HIP(ctx, hipEventRecord(h->ev[1], s));
   rocblas_int info = 0;
+  double herm_host[2] = {0.0, 0.0};
   std::vector<double> ev;
   BB_HIP(ctx, hipMemcpyAsync(&info, at<rocblas_int>(h, L.info), sizeof info, hipMemcpyDeviceToHost, s));
+  BB_HIP(ctx, hipMemcpyAsync(herm_host, herm, sizeof herm_host, hipMemcpyDeviceToHost, s));
   if (energy_fraction > 0.0) {
     ev.resize(n_sys);
     BB_HIP(ctx, hipMemcpyAsync(ev.data(), at<double>(h, L.evals), sizeof(double) * n_sys, hipMemcpyDeviceToHost, s));
   }
   BB_HIP(ctx, hipStreamSynchronize(s));
+  // ||V - V^H||_F <= 1e-12 ||V||_F, squared; NaN fails too
+  if (!(herm_host[0] <= 1e-24 * herm_host[1]))
+    return fail(ctx, BB_ERR_INVALID_ARG, "visibility matrix is not Hermitian (||V - V^H|| / ||V|| = %.3g)",
+                std::sqrt(herm_host[0] / herm_host[1]));
   if (info > n_sys) return fail(ctx, BB_ERR_NOT_POSDEF, "Gram matrix not positive definite (leading minor %d)", info - n_sys);
   if (info != 0) return fail(ctx, BB_ERR_EIGEN, "eigensolver did not converge (info %d)", info);
   if (energy_fraction > 0.0) {

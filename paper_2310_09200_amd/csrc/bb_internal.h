@@ -86,6 +86,8 @@ hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
 hipError_t launch_gram(const double* ant, int64_t ant_ld, int L, double wl, double* G_c128, int ldg, bool identity,
                        hipStream_t s);
 hipError_t launch_copy_c128(const double* src, int L, double* dst, int ldd, hipStream_t s);
+// out[0] = ||V - V^H||_F^2, out[1] = ||V||_F^2 of an L x L complex128 matrix.
+hipError_t launch_herm_check(const double* V, int L, double* out, hipStream_t s);
 struct Intervals {
   double lo[kMaxLevels];
   double hi[kMaxLevels];

@@ -47,6 +47,43 @@ __global__ __launch_bounds__(256) void copy_c128_kernel(const double* __restrict
   d[1] = s[1];
 }
 
+// Hermiticity of the visibility matrix (Section 2.1: V is a correlation
+// matrix): out[0] = ||V - V^H||_F^2, out[1] = ||V||_F^2, one workgroup, fixed
+// summation order.  The eigensolver reads one triangle only, so without this
+// check a non-Hermitian V would be imaged as if symmetrised.
+__global__ __launch_bounds__(256) void herm_check_kernel(const double* __restrict__ V, int L, double* __restrict__ out) {
+  __shared__ double s_d[256], s_n[256];
+  const int tid = threadIdx.x;
+  double dsum = 0.0, nsum = 0.0;
+  for (int64_t i = tid; i < (int64_t)L * L; i += 256) {
+    const int p = (int)(i % L), q = (int)(i / L);
+    const double* a = V + 2 * ((int64_t)q * L + p);  // V_pq
+    const double* b = V + 2 * ((int64_t)p * L + q);  // V_qp
+    const double dr = a[0] - b[0], di = a[1] + b[1];  // V_pq - conj(V_qp)
+    dsum += dr * dr + di * di;
+    nsum += a[0] * a[0] + a[1] * a[1];
+  }
+  s_d[tid] = dsum;
+  s_n[tid] = nsum;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      s_d[tid] += s_d[tid + w];
+      s_n[tid] += s_n[tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = s_d[0];
+    out[1] = s_n[0];
+  }
+}
+
+hipError_t launch_herm_check(const double* V, int L, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(herm_check_kernel, dim3(1), dim3(256), 0, s, V, L, out);
+  return hipGetLastError();
+}
+
 // zhegvd returns eigenvalues ascending; keep the K largest, descending
 // (Section 2.6 truncation; Algorithm 1 selection).  Weight: lambda (LSQ
 // filter) or 1 (standardized filter).  Level: first closed interval that

@@ -339,6 +339,13 @@ def test_error_codes_from_host(ctx):
     assert _status(lambda: s.collect(0, x, 2.0, V, 4, np.array([[2.0, 1.0], [-1.0, 0.0]]))) == _lib.BB_ERR_INVALID_ARG
     assert _status(lambda: s.collect(0, x, 2.0, V, 4, np.array([[0.0, 2.0], [1.0, 3.0]]))) == _lib.BB_ERR_INVALID_ARG
     assert _status(lambda: s.collect(0, x, 2.0, V, 4, np.array([[np.nan, 2.0], [-1.0, 0.0]]))) == _lib.BB_ERR_INVALID_ARG
+    # non-Hermitian or NaN visibilities (V is a correlation matrix, Section 2.1)
+    Vb = V.copy()
+    Vb[0, 5] += 1e-3 * np.abs(V).max()
+    assert _status(lambda: s.collect(0, x, 2.0, Vb, 4, iv)) == _lib.BB_ERR_INVALID_ARG
+    Vn = V.copy()
+    Vn[2, 2] = np.nan
+    assert _status(lambda: s.collect(0, x, 2.0, Vn, 4, iv)) == _lib.BB_ERR_INVALID_ARG
     # coincident antennas: G is singular, the Cholesky factorisation fails
     x2 = x.copy()
     x2[3] = x2[2]
