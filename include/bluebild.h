@@ -308,7 +308,9 @@ typedef struct {
 bb_status bb_nufft_workspace_size(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix, const double* pix_host,
                                   size_t* bytes);
 /* Create a plan.  pix_host as above (read during the call only); pix_xyz: the
- * same pixels on the device (kept); images: device, float32 [n_levels][n_pix],
+ * same pixels on the device (kept; the transform keeps only the grid points
+ * that the planned pixels reach, and treats any other point a differing
+ * device pixel would read as zero); images: device, float32 [n_levels][n_pix],
  * accumulated into by bb_nufft_emit; workspace: device, 256-byte aligned,
  * ws_bytes >= bb_nufft_workspace_size(...).  Waits for its set-up work. */
 bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix, const double* pix_host,

@@ -119,6 +119,8 @@ struct NufftGeom {
   double hM[3];     // h * M: type-2 grid points per unit of pixel offset
   int N[3];         // spread grid
   int M[3];         // type-2 (FFT) grid, 2 N
+  int win_lo[3];    // first type-2 grid point the pixels need per axis (mod M)
+  int win_len[3];   // number of type-2 grid points the pixels need per axis
   int w;            // kernel support in grid points
   float beta;       // kernel shape
 };
@@ -134,8 +136,9 @@ hipError_t launch_nufft_prep(const NufftInst* insts, int n_inst, const void* W, 
 hipError_t launch_nufft_spread(const NufftGeom& g, const NufftInst* insts, int n_inst, int max_ant,
                                const double* ant, int64_t ant_ld, const void* Wmat, const float* d, const int* order,
                                const int* lstart, int n_levels, float* grid, int64_t n_cell, int* err, hipStream_t s);
-hipError_t launch_nufft_pad(const NufftGeom& g, const float* grid_level, const float* inv_psi0, const float* inv_psi1,
-                            const float* inv_psi2, float* out, hipStream_t s);
+// One gather of the pruned type-2 transform: axis 2 (grid -> A), 1 (A -> B) or 0 (B -> C).
+hipError_t launch_nufft_gather(int axis, const NufftGeom& g, const void* src, const float* inv_psi, void* dst,
+                               hipStream_t s);
 hipError_t launch_nufft_interp(const NufftGeom& g, const double* pix, int64_t pix_ld, int64_t n_pix, const float* u,
                                const double* corr, const double* diag, int lv, float* image, hipStream_t s);
 hipError_t launch_nufft_corr(const NufftGeom& g, const double* pix, int64_t pix_ld, int64_t n_pix, const double* quad_t,

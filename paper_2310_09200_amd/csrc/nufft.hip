@@ -465,42 +465,83 @@ __global__ __launch_bounds__(256) void nufft_spread_tile_kernel(NufftGeom g, con
 }
 
 // ---------------------------------------------------------------------------
-// Deconvolve one level's grid by the type-2 kernel's transform and place it
-// in the centre of the M grid (frequencies -N/2 .. N/2-1), zeros elsewhere.
-__global__ __launch_bounds__(256) void nufft_pad_kernel(NufftGeom g, const float* __restrict__ grid,
-                                                        const float* __restrict__ inv_psi0,
-                                                        const float* __restrict__ inv_psi1,
-                                                        const float* __restrict__ inv_psi2, float* __restrict__ out,
-                                                        int64_t n_out) {
+// The type-2 transform of one level's grid, pruned: an inverse 3-D FFT of the
+// grid zero-padded from N to M points per axis, done as three batched 1-D
+// FFTs (rocFFT) so that only lines holding data are transformed and only the
+// outputs the pixels need (a window of win_len points per axis) are kept.
+// Each gather places one axis's frequencies -N/2 .. N/2-1 at m = g mod M,
+// divides by that axis's kernel transform and zero-fills the rest:
+//   A [i0][i1][m2]   (N0 x N1 x M2)   from the grid        -> FFT along m2
+//   B [i0][w2][m1]   (N0 x W2 x M1)   from A, m2 in window -> FFT along m1
+//   C [w1][w2][m0]   (W1 x W2 x M0)   from B, m1 in window -> FFT along m0
+
+// stored index of the frequency at position m of an M-point axis (-1 = zero padding)
+__device__ __forceinline__ int freq_index(int m, int n, int M) {
+  const int half = n / 2;
+  if (m < half) return m;
+  if (m >= M - half) return m - M + n;
+  return -1;
+}
+
+__global__ __launch_bounds__(256) void nufft_gather_a_kernel(NufftGeom g, const float2* __restrict__ grid,
+                                                             const float* __restrict__ inv_psi2,
+                                                             float2* __restrict__ A, int64_t n_out) {
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n_out;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int m2 = (int)(idx % g.M[2]);
-    const int64_t rest = idx / g.M[2];
-    const int m1 = (int)(rest % g.M[1]);
-    const int m0 = (int)(rest / g.M[1]);
-    const int mm[3] = {m0, m1, m2};
-    int ii[3];
-    bool inside = true;
-    for (int d = 0; d < 3; ++d) {
-      const int half = g.N[d] / 2;
-      if (mm[d] < half) {
-        ii[d] = mm[d];
-      } else if (mm[d] >= g.M[d] - half) {
-        ii[d] = mm[d] - g.M[d] + g.N[d];  // g = m - M < 0, stored at g + N
-      } else {
-        inside = false;
-        ii[d] = 0;
-      }
+    const int64_t line = idx / g.M[2];  // i0 N1 + i1
+    const int i2 = freq_index(m2, g.N[2], g.M[2]);
+    float2 v = make_float2(0.0f, 0.0f);
+    if (i2 >= 0) {
+      const float2 x = grid[line * g.N[2] + i2];
+      const float s = inv_psi2[i2];
+      v = make_float2(x.x * s, x.y * s);
     }
-    float vr = 0.0f, vi = 0.0f;
-    if (inside) {
-      const int64_t src = ((int64_t)ii[0] * g.N[1] + ii[1]) * g.N[2] + ii[2];
-      const float s = inv_psi0[ii[0]] * inv_psi1[ii[1]] * inv_psi2[ii[2]];
-      vr = grid[2 * src] * s;
-      vi = grid[2 * src + 1] * s;
+    A[idx] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void nufft_gather_b_kernel(NufftGeom g, const float2* __restrict__ A,
+                                                             const float* __restrict__ inv_psi1,
+                                                             float2* __restrict__ B, int64_t n_out) {
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n_out;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int m1 = (int)(idx % g.M[1]);
+    const int64_t rest = idx / g.M[1];
+    const int w2 = (int)(rest % g.win_len[2]);
+    const int i0 = (int)(rest / g.win_len[2]);
+    int m2 = g.win_lo[2] + w2;
+    if (m2 >= g.M[2]) m2 -= g.M[2];
+    const int i1 = freq_index(m1, g.N[1], g.M[1]);
+    float2 v = make_float2(0.0f, 0.0f);
+    if (i1 >= 0) {
+      const float2 x = A[((int64_t)i0 * g.N[1] + i1) * g.M[2] + m2];
+      const float s = inv_psi1[i1];
+      v = make_float2(x.x * s, x.y * s);
     }
-    out[2 * idx] = vr;
-    out[2 * idx + 1] = vi;
+    B[idx] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void nufft_gather_c_kernel(NufftGeom g, const float2* __restrict__ B,
+                                                             const float* __restrict__ inv_psi0,
+                                                             float2* __restrict__ C, int64_t n_out) {
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n_out;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int m0 = (int)(idx % g.M[0]);
+    const int64_t rest = idx / g.M[0];
+    const int w2 = (int)(rest % g.win_len[2]);
+    const int w1 = (int)(rest / g.win_len[2]);
+    int m1 = g.win_lo[1] + w1;
+    if (m1 >= g.M[1]) m1 -= g.M[1];
+    const int i0 = freq_index(m0, g.N[0], g.M[0]);
+    float2 v = make_float2(0.0f, 0.0f);
+    if (i0 >= 0) {
+      const float2 x = B[((int64_t)i0 * g.win_len[2] + w2) * g.M[1] + m1];
+      const float s = inv_psi0[i0];
+      v = make_float2(x.x * s, x.y * s);
+    }
+    C[idx] = v;
   }
 }
 
@@ -520,18 +561,28 @@ __global__ __launch_bounds__(256) void nufft_interp_kernel(NufftGeom g, const do
   kernel_row<W>((frame_coord(g, 0, a0, a1, a2) - g.D[0]) * g.hM[0], g.M[0], g.beta, k0, i0);
   kernel_row<W>((frame_coord(g, 1, a0, a1, a2) - g.D[1]) * g.hM[1], g.M[1], g.beta, k1, i1);
   kernel_row<W>((frame_coord(g, 2, a0, a1, a2) - g.D[2]) * g.hM[2], g.M[2], g.beta, k2, i2);
-  const int64_t m12 = (int64_t)g.M[1] * g.M[2];
+  // u is the windowed transform C[w1][w2][m0]; points outside the windows
+  // (pixels other than the ones planned for) contribute nothing
+  int w1[W], w2[W];
+#pragma unroll
+  for (int t = 0; t < W; ++t) {
+    w1[t] = i1[t] - g.win_lo[1];
+    if (w1[t] < 0) w1[t] += g.M[1];
+    w2[t] = i2[t] - g.win_lo[2];
+    if (w2[t] < 0) w2[t] += g.M[2];
+  }
   float fr = 0.0f;
 #pragma unroll
-  for (int a = 0; a < W; ++a) {
+  for (int c = 0; c < W; ++c) {
+    if (w1[c] >= g.win_len[1]) continue;
 #pragma unroll
-    for (int c = 0; c < W; ++c) {
-      const float k01 = k0[a] * k1[c];
-      const int64_t base = (int64_t)i0[a] * m12 + (int64_t)i1[c] * g.M[2];
+    for (int e = 0; e < W; ++e) {
+      if (w2[e] >= g.win_len[2]) continue;
+      const int64_t base = ((int64_t)w1[c] * g.win_len[2] + w2[e]) * g.M[0];
       float s = 0.0f;
 #pragma unroll
-      for (int e = 0; e < W; ++e) s += u[2 * (base + i2[e])] * k2[e];  // real part only: the image is 2 Re(.)
-      fr += s * k01;
+      for (int a = 0; a < W; ++a) s += u[2 * (base + i0[a])] * k0[a];  // real part only: the image is 2 Re(.)
+      fr += s * k1[c] * k2[e];
     }
   }
   image[p] += (float)(2.0 * (double)fr * corr[p] + diag[lv]);
@@ -650,12 +701,23 @@ hipError_t launch_nufft_spread_tiles(const NufftGeom& g, const NufftInst* insts,
   });
 }
 
-hipError_t launch_nufft_pad(const NufftGeom& g, const float* grid_level, const float* inv_psi0, const float* inv_psi1,
-                            const float* inv_psi2, float* out, hipStream_t s) {
-  const int64_t n_out = (int64_t)g.M[0] * g.M[1] * g.M[2];
-  const int64_t blocks = std::min<int64_t>((n_out + 255) / 256, 65536);
-  hipLaunchKernelGGL(nufft_pad_kernel, dim3((unsigned)blocks), dim3(256), 0, s, g, grid_level, inv_psi0, inv_psi1,
-                     inv_psi2, out, n_out);
+static unsigned grid_blocks(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 65536); }
+
+hipError_t launch_nufft_gather(int axis, const NufftGeom& g, const void* src, const float* inv_psi, void* dst,
+                               hipStream_t s) {
+  if (axis == 2) {
+    const int64_t n = (int64_t)g.N[0] * g.N[1] * g.M[2];
+    hipLaunchKernelGGL(nufft_gather_a_kernel, dim3(grid_blocks(n)), dim3(256), 0, s, g,
+                       static_cast<const float2*>(src), inv_psi, static_cast<float2*>(dst), n);
+  } else if (axis == 1) {
+    const int64_t n = (int64_t)g.N[0] * g.win_len[2] * g.M[1];
+    hipLaunchKernelGGL(nufft_gather_b_kernel, dim3(grid_blocks(n)), dim3(256), 0, s, g,
+                       static_cast<const float2*>(src), inv_psi, static_cast<float2*>(dst), n);
+  } else {
+    const int64_t n = (int64_t)g.win_len[1] * g.win_len[2] * g.M[0];
+    hipLaunchKernelGGL(nufft_gather_c_kernel, dim3(grid_blocks(n)), dim3(256), 0, s, g,
+                       static_cast<const float2*>(src), inv_psi, static_cast<float2*>(dst), n);
+  }
   return hipGetLastError();
 }
 

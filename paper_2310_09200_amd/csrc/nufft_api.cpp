@@ -26,9 +26,19 @@ constexpr int kSigma = 2;        // type-2 grid upsampling
 constexpr int kQuadNodes = 100;  // Gauss-Legendre nodes for kernel transforms
 
 struct NufftLayout {  // byte offsets into a plan's workspace
-  size_t grid, fft, work, psi0, psi1, psi2, corr, quad_t, quad_wphi, diag, err, total;
+  size_t grid, work, psi0, psi1, psi2, corr, quad_t, quad_wphi, diag, err, total;
   size_t work_bytes;
+  size_t stage_ac, stage_b;  // pruned transform: A and C share a region, B has its own
 };
+
+// Complex points of the three stages of the pruned type-2 transform.
+struct StageSizes {
+  size_t a, b, c;
+};
+StageSizes stage_sizes(const bb::NufftGeom& g) {
+  return {(size_t)g.N[0] * g.N[1] * g.M[2], (size_t)g.N[0] * g.win_len[2] * g.M[1],
+          (size_t)g.win_len[1] * g.win_len[2] * g.M[0]};
+}
 
 // Gauss-Legendre nodes and weights on [-1, 1]: Newton's method on P_n,
 // evaluated by the three-term recurrence.
@@ -131,34 +141,73 @@ bb_status nufft_geometry(bb_context ctx, const bb_nufft_options* o, int64_t n_pi
     g.N[d] = smooth_size(std::max<int64_t>(2 * g.w, (int64_t)need));
     g.M[d] = kSigma * g.N[d];
     g.hM[d] = g.h[d] * g.M[d];
+    // The pixels sit at |eta| <= M/4 type-2 grid points from the centre (eta =
+    // (s - D) h M, |s - D| <= S, h = 1/(4 S)); their kernels reach from
+    // ceil(eta - w/2) to that plus w - 1.  One point of slack each side covers
+    // the rounding of eta.
+    const int lo = (int)std::ceil(-0.25 * g.M[d] - 0.5 * g.w) - 1;
+    const int hi = (int)std::ceil(0.25 * g.M[d] - 0.5 * g.w) + g.w;
+    if (hi - lo + 1 >= g.M[d]) {
+      g.win_lo[d] = 0;
+      g.win_len[d] = g.M[d];
+    } else {
+      g.win_lo[d] = ((lo % g.M[d]) + g.M[d]) % g.M[d];
+      g.win_len[d] = hi - lo + 1;
+    }
   }
   return BB_OK;
 }
 
-size_t rocfft_work_bytes(const bb::NufftGeom& g, rocfft_plan* keep) {
-  size_t lengths[3] = {(size_t)g.M[2], (size_t)g.M[1], (size_t)g.M[0]};  // fastest first
-  rocfft_plan plan = nullptr;
-  if (rocfft_plan_create(&plan, rocfft_placement_inplace, rocfft_transform_type_complex_inverse,
-                         rocfft_precision_single, 3, lengths, 1, nullptr) != rocfft_status_success)
-    return (size_t)-1;
+// The three batched 1-D inverse transforms of the pruned type-2 transform,
+// in place on contiguous lines: A along axis 2, B along axis 1, C along axis 0.
+struct FftPlans {
+  rocfft_plan p[3] = {nullptr, nullptr, nullptr};
+  void destroy() {
+    for (rocfft_plan& q : p)
+      if (q) {
+        rocfft_plan_destroy(q);
+        q = nullptr;
+      }
+  }
+};
+
+// Work-buffer bytes of the plans (max over the three), or (size_t)-1 on failure.
+// With keep, the plans are handed over; otherwise destroyed.
+size_t rocfft_work_bytes(const bb::NufftGeom& g, FftPlans* keep) {
+  const StageSizes st = stage_sizes(g);
+  const size_t len[3] = {(size_t)g.M[2], (size_t)g.M[1], (size_t)g.M[0]};
+  const size_t batch[3] = {st.a / len[0], st.b / len[1], st.c / len[2]};
+  FftPlans plans;
   size_t bytes = 0;
-  rocfft_plan_get_work_buffer_size(plan, &bytes);
+  for (int i = 0; i < 3; ++i) {
+    if (rocfft_plan_create(&plans.p[i], rocfft_placement_inplace, rocfft_transform_type_complex_inverse,
+                           rocfft_precision_single, 1, &len[i], batch[i], nullptr) != rocfft_status_success) {
+      plans.p[i] = nullptr;
+      plans.destroy();
+      return (size_t)-1;
+    }
+    size_t b = 0;
+    rocfft_plan_get_work_buffer_size(plans.p[i], &b);
+    bytes = std::max(bytes, b);
+  }
   if (keep)
-    *keep = plan;
+    *keep = plans;
   else
-    rocfft_plan_destroy(plan);
+    plans.destroy();
   return bytes;
 }
 
 NufftLayout nufft_layout(const bb::NufftGeom& g, int n_levels, int64_t n_pix, size_t work_bytes) {
   NufftLayout l{};
   const size_t n_cell = (size_t)g.N[0] * g.N[1] * g.N[2];
-  const size_t m_cell = (size_t)g.M[0] * g.M[1] * g.M[2];
+  const StageSizes st = stage_sizes(g);
   size_t p = 0;
   l.grid = p;
   p += align_up(8 * n_cell * (size_t)n_levels);
-  l.fft = p;
-  p += align_up(8 * m_cell);
+  l.stage_ac = p;
+  p += align_up(8 * std::max(st.a, st.c));
+  l.stage_b = p;
+  p += align_up(8 * st.b);
   l.work = p;
   l.work_bytes = work_bytes;
   p += align_up(std::max<size_t>(work_bytes, 1));
@@ -196,7 +245,7 @@ struct bb_nufft_ {
   float* images = nullptr;
   char* ws = nullptr;
   NufftLayout lay{};
-  rocfft_plan plan = nullptr;
+  FftPlans plans;
   rocfft_execution_info info = nullptr;
   int64_t count = 0;  // instances spread since the last emit
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -241,17 +290,17 @@ bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n
   std::call_once(g_rocfft_once, [] { g_rocfft_setup = rocfft_setup(); });
   if (g_rocfft_setup != rocfft_status_success) return fail(ctx, BB_ERR_DEVICE, "rocfft_setup failed");
   BB_HIP(ctx, hipSetDevice(ctx->device));
-  rocfft_plan plan = nullptr;
-  const size_t work = rocfft_work_bytes(g, &plan);
+  FftPlans plans;
+  const size_t work = rocfft_work_bytes(g, &plans);
   if (work == (size_t)-1) return fail(ctx, BB_ERR_DEVICE, "rocfft_plan_create failed");
   const NufftLayout lay = nufft_layout(g, opt->n_levels, n_pix, work);
   if (ws_bytes < lay.total) {
-    rocfft_plan_destroy(plan);
+    plans.destroy();
     return fail(ctx, BB_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, lay.total);
   }
   bb_nufft h = new (std::nothrow) bb_nufft_;
   if (!h) {
-    rocfft_plan_destroy(plan);
+    plans.destroy();
     return fail(ctx, BB_ERR_DEVICE, "out of host memory");
   }
   h->ctx = ctx;
@@ -262,10 +311,10 @@ bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n
   h->images = images;
   h->ws = static_cast<char*>(workspace);
   h->lay = lay;
-  h->plan = plan;
+  h->plans = plans;
   auto bail = [&](const char* what) {
     if (h->info) rocfft_execution_info_destroy(h->info);
-    rocfft_plan_destroy(h->plan);
+    h->plans.destroy();
     for (hipEvent_t& e : h->ev)
       if (e) hipEventDestroy(e);
     delete h;
@@ -468,18 +517,26 @@ bb_status bb_nufft_emit(bb_nufft h) {
   hipStream_t s = ctx->stream;
   const bb::NufftGeom& g = h->g;
   const int64_t n_cell = (int64_t)g.N[0] * g.N[1] * g.N[2];
-  float* fft = nat<float>(h, h->lay.fft);
+  void* ac = h->ws + h->lay.stage_ac;
+  void* b = h->ws + h->lay.stage_b;
   // the context's stream may have been rebound since the plan was made
   if (rocfft_execution_info_set_stream(h->info, s) != rocfft_status_success)
     return fail(ctx, BB_ERR_DEVICE, "rocfft_execution_info_set_stream failed");
   BB_HIP(ctx, hipEventRecord(h->ev[2], s));
   for (int lv = 0; lv < h->opt.n_levels; ++lv) {
-    BB_HIP(ctx, bb::launch_nufft_pad(g, nat<float>(h, h->lay.grid) + 2 * (int64_t)lv * n_cell, nat<float>(h, h->lay.psi0),
-                                     nat<float>(h, h->lay.psi1), nat<float>(h, h->lay.psi2), fft, s));
-    void* buf[1] = {fft};
-    if (rocfft_execute(h->plan, buf, nullptr, h->info) != rocfft_status_success)
-      return fail(ctx, BB_ERR_DEVICE, "rocfft_execute failed");
-    BB_HIP(ctx, bb::launch_nufft_interp(g, h->pix, h->n_pix, h->n_pix, fft, nat<double>(h, h->lay.corr),
+    // pruned inverse transform: grid -> A (FFT along axis 2) -> B (axis 1) -> C (axis 0)
+    const float* level_grid = nat<float>(h, h->lay.grid) + 2 * (int64_t)lv * n_cell;
+    void* const stage_in[3] = {const_cast<float*>(level_grid), ac, b};
+    void* const stage_out[3] = {ac, b, ac};
+    const size_t psi[3] = {h->lay.psi2, h->lay.psi1, h->lay.psi0};
+    for (int st = 0; st < 3; ++st) {
+      BB_HIP(ctx, bb::launch_nufft_gather(2 - st, g, stage_in[st], nat<float>(h, psi[st]), stage_out[st], s));
+      void* buf[1] = {stage_out[st]};
+      if (rocfft_execute(h->plans.p[st], buf, nullptr, h->info) != rocfft_status_success)
+        return fail(ctx, BB_ERR_DEVICE, "rocfft_execute failed");
+    }
+    BB_HIP(ctx, bb::launch_nufft_interp(g, h->pix, h->n_pix, h->n_pix, static_cast<const float*>(ac),
+                                        nat<double>(h, h->lay.corr),
                                         nat<double>(h, h->lay.diag), lv, h->images + (int64_t)lv * h->n_pix, s));
   }
   BB_HIP(ctx, bb::launch_fill_zero(nat<float>(h, h->lay.grid), 2 * n_cell * h->opt.n_levels, s));
@@ -528,7 +585,7 @@ bb_status bb_nufft_destroy(bb_nufft h) {
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
   if (h->info) rocfft_execution_info_destroy(h->info);
-  if (h->plan) rocfft_plan_destroy(h->plan);
+  h->plans.destroy();
   for (hipEvent_t& e : h->ev)
     if (e) hipEventDestroy(e);
   ctx->live -= 1;
