@@ -216,7 +216,7 @@ def measure_nufft(args, torch, ctx):
     uvw = uvw * 1.001
 
     s = StandardSynthesis(ctx, w.pix, n_levels, 1, 512, 512, args.precision)
-    plan = NufftSynthesis(ctx, w.pix, n_levels, 512, 512, args.nufft_eps, frame, uvw)
+    plan = NufftSynthesis(ctx, w.pix, n_levels, 512, 512, args.nufft_eps, frame, uvw, transform=args.nufft_transform)
     N, M, kw = plan.shape
     s.collect_eig_batched(batch)
     plan.collect_eig_batched(batch)
@@ -252,7 +252,6 @@ def measure_nufft(args, torch, ctx):
     s.close()
     plan.close()
     prods = batch.products * w.n_pix
-    m_cells = M[0] * M[1] * M[2]
     log(f"NUFFT {side}^2: standard {np.mean(std_ms):.1f} ms, NUFFT {np.mean(nu_ms):.1f} ms "
         f"(spread {np.mean(spread_ms):.1f}, emit {np.mean(emit_ms):.1f}), grid {N} fft {M} w={kw}, "
         f"max level diff {max(errs):.2e}")
@@ -263,7 +262,8 @@ def measure_nufft(args, torch, ctx):
             "nufft_ms": float(np.mean(nu_ms)), "nufft_spread_ms": float(np.mean(spread_ms)),
             "nufft_emit_ms": float(np.mean(emit_ms)), "speedup_nufft_over_standard": float(np.mean(std_ms) / np.mean(nu_ms)),
             "products": prods, "standard_products_per_s": prods / (np.mean(std_ms) / 1e3),
-            "fft_cells_per_level": m_cells,
+            "transform": {"auto": "pruned, own LDS line FFTs where every axis fits, else rocFFT",
+                          "rocfft": "pruned, rocFFT"}[args.nufft_transform],
             "max_level_diff_nufft_vs_standard": max(errs)}
 
 
@@ -327,6 +327,8 @@ def main():
                     help="skip the batched (C4), backward (C5) and NUFFT-synthesis measurements")
     ap.add_argument("--nufft-side", type=int, default=1024, help="image side of the NUFFT comparison (4 arcsec pixels)")
     ap.add_argument("--nufft-eps", type=float, default=1e-5)
+    ap.add_argument("--nufft-transform", choices=["auto", "rocfft"], default="auto",
+                    help="type-2 transform of the NUFFT comparison")
     ap.add_argument("--only-nufft", action="store_true",
                     help="print only the NUFFT-vs-standard measurement (for profiling it alone)")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,

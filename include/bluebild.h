@@ -280,22 +280,24 @@ bb_status bb_synth_eig_backward(bb_synth h, int32_t n_ant, int32_t n_eig, double
  * periodic N0 x N1 x N2 grid with the exponential-of-semicircle kernel
  * phi(z) = exp(beta (sqrt(1 - z^2) - 1)), w = ceil(log10(1 / epsilon) - 1e-9) + 1
  * points of support, beta = 2.30 w; the grid is deconvolved, zero-padded to
- * M = 2 N, transformed (rocFFT, e^{+i}), interpolated at the pixels and
- * divided by the kernel's transform.  Per frame axis d, with pixel half-width
+ * M = 2 N, transformed (e^{+i}) one axis at a time over only the lines that
+ * hold data and only the outputs the pixels reach, interpolated at the pixels
+ * and divided by the kernel's transform.  Per frame axis d, with pixel half-width
  * S_d (floored at 1e-12) about the centre D_d and baseline bound X_d = uvw_max[d]:
  *   spacing h_d = 1 / (4 S_d) turns, N_d = the least even 2^a 3^b 5^c
  *   >= max(2 w, ceil(8 X_d S_d) + w).
  * Instances collected before one bb_nufft_emit share the grid: the transform,
  * interpolation and correction run once per emit and level.  The grid is
  * accumulated with FP32 atomics, so the last bits of a result vary between
- * runs.  Memory: n_levels N0 N1 N2 + M0 M1 M2 complex64 cells plus rocFFT's
- * work area (bb_nufft_workspace_size). */
+ * runs.  Memory: n_levels N0 N1 N2 complex64 grid cells plus two stage
+ * buffers of about N0 M1 M2 / 2 cells each (bb_nufft_workspace_size). */
 typedef struct bb_nufft_* bb_nufft;
 typedef struct {
   int32_t n_levels;   /* images, 1..16 */
   int32_t n_ant_max;  /* largest antenna count of an instance, 2..1024 */
   int32_t k_max;      /* largest eigenpair count of an instance, 1..1024 */
-  int32_t reserved;   /* must be 0 */
+  int32_t transform;  /* type-2 transform: 0 = automatic (the library's own LDS line
+                         FFTs when every M_d <= 8192, else rocFFT), 1 = rocFFT */
   double epsilon;     /* requested accuracy, 1e-7 .. 1e-2 */
   double frame[9];    /* rows e_u, e_v, p0: orthonormal, in the frame of ant_xyz and pix_xyz */
   double uvw_max[3];  /* bound on |<x_q - x_r, frame row d>| / lambda_w over every baseline

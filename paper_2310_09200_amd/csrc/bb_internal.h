@@ -139,8 +139,39 @@ hipError_t launch_nufft_spread(const NufftGeom& g, const NufftInst* insts, int n
 // One gather of the pruned type-2 transform: axis 2 (grid -> A), 1 (A -> B) or 0 (B -> C).
 hipError_t launch_nufft_gather(int axis, const NufftGeom& g, const void* src, const float* inv_psi, void* dst,
                                hipStream_t s);
-hipError_t launch_nufft_interp(const NufftGeom& g, const double* pix, int64_t pix_ld, int64_t n_pix, const float* u,
-                               const double* corr, const double* diag, int lv, float* image, hipStream_t s);
+// Where the interpolation finds type-2 point (m0, m1, m2): at w1 s1 + w2 s2 + w0
+// (complex64 elements), w_d = (m_d - win_lo[d]) mod M_d; axis 0 is windowed
+// by (lo0, len0) (0 and M0 for an unwindowed axis).  Points outside read as 0.
+struct InterpLayout {
+  int64_t s1, s2;
+  int lo0, len0;
+};
+hipError_t launch_nufft_interp(const NufftGeom& g, const InterpLayout& lay, const double* pix, int64_t pix_ld,
+                               int64_t n_pix, const float* u, const double* corr, const double* diag, int lv,
+                               float* image, hipStream_t s);
+// Line FFTs of the pruned transform (nufft_fft.hip).
+constexpr int kLineFftMax = 8192;  // longest line held in LDS
+struct LineFft {
+  int L;                 // transform length (M of the axis)
+  int n_in;              // stored inputs per line (N of the axis)
+  int win_lo, win_len;   // outputs kept: positions (win_lo + w) mod L, w < win_len
+  int n_pass, nl;        // Stockham passes; lines per workgroup
+  uint64_t radix_codes;  // radix of pass i in bits [4i, 4i + 4)
+  int64_t n_lines, in_stride, out_stride;
+  int64_t t_inner;       // out_mode 1: line = outer * t_inner + inner, stored at [outer][w][inner]
+  int out_mode;          // 0: out[line * out_stride + w]
+};
+// Fills L, n_pass, radix_codes and nl; -1 if L is not 2,3,5-smooth or exceeds kLineFftMax.
+int line_fft_plan(int L, LineFft& p);
+size_t line_fft_lds_bytes(const LineFft& p);  // dynamic LDS of a launch
+// Load position of each input index of a planned length (p.L ints): the digit
+// reversal the in-place passes need.
+void line_fft_perm(const LineFft& p, int* perm);
+// The passes' twiddles of a planned length (2 (p.L - 1) floats, complex64).
+void line_fft_twiddles(const LineFft& p, float* tw);
+hipError_t launch_line_fft(const LineFft& p, const void* in, const float* inv_psi, const int* perm, const float2* tw,
+                           void* out, hipStream_t s);
+hipError_t launch_transpose_c64(const void* in, int64_t rows, int64_t cols, void* out, hipStream_t s);
 hipError_t launch_nufft_corr(const NufftGeom& g, const double* pix, int64_t pix_ld, int64_t n_pix, const double* quad_t,
                              const double* quad_wphi, int n_quad, double* corr, hipStream_t s);
 hipError_t launch_fill_zero_f64(double* p, int n, hipStream_t s);

@@ -548,7 +548,8 @@ __global__ __launch_bounds__(256) void nufft_gather_c_kernel(NufftGeom g, const 
 // ---------------------------------------------------------------------------
 // Interpolation at the pixels, correction and accumulation into one level's image.
 template <int W>
-__global__ __launch_bounds__(256) void nufft_interp_kernel(NufftGeom g, const double* __restrict__ pix, int64_t pix_ld,
+__global__ __launch_bounds__(256) void nufft_interp_kernel(NufftGeom g, InterpLayout lay,
+                                                           const double* __restrict__ pix, int64_t pix_ld,
                                                            int64_t n_pix, const float* __restrict__ u,
                                                            const double* __restrict__ corr,
                                                            const double* __restrict__ diag, int lv,
@@ -561,11 +562,13 @@ __global__ __launch_bounds__(256) void nufft_interp_kernel(NufftGeom g, const do
   kernel_row<W>((frame_coord(g, 0, a0, a1, a2) - g.D[0]) * g.hM[0], g.M[0], g.beta, k0, i0);
   kernel_row<W>((frame_coord(g, 1, a0, a1, a2) - g.D[1]) * g.hM[1], g.M[1], g.beta, k1, i1);
   kernel_row<W>((frame_coord(g, 2, a0, a1, a2) - g.D[2]) * g.hM[2], g.M[2], g.beta, k2, i2);
-  // u is the windowed transform C[w1][w2][m0]; points outside the windows
-  // (pixels other than the ones planned for) contribute nothing
-  int w1[W], w2[W];
+  // window offsets; points outside the windows (pixels other than the ones
+  // planned for) contribute nothing
+  int w0[W], w1[W], w2[W];
 #pragma unroll
   for (int t = 0; t < W; ++t) {
+    w0[t] = i0[t] - lay.lo0;
+    if (w0[t] < 0) w0[t] += g.M[0];
     w1[t] = i1[t] - g.win_lo[1];
     if (w1[t] < 0) w1[t] += g.M[1];
     w2[t] = i2[t] - g.win_lo[2];
@@ -578,10 +581,11 @@ __global__ __launch_bounds__(256) void nufft_interp_kernel(NufftGeom g, const do
 #pragma unroll
     for (int e = 0; e < W; ++e) {
       if (w2[e] >= g.win_len[2]) continue;
-      const int64_t base = ((int64_t)w1[c] * g.win_len[2] + w2[e]) * g.M[0];
+      const int64_t base = (int64_t)w1[c] * lay.s1 + (int64_t)w2[e] * lay.s2;
       float s = 0.0f;
 #pragma unroll
-      for (int a = 0; a < W; ++a) s += u[2 * (base + i0[a])] * k0[a];  // real part only: the image is 2 Re(.)
+      for (int a = 0; a < W; ++a)
+        if (w0[a] < lay.len0) s += u[2 * (base + w0[a])] * k0[a];  // real part only: the image is 2 Re(.)
       fr += s * k1[c] * k2[e];
     }
   }
@@ -721,12 +725,14 @@ hipError_t launch_nufft_gather(int axis, const NufftGeom& g, const void* src, co
   return hipGetLastError();
 }
 
-hipError_t launch_nufft_interp(const NufftGeom& g, const double* pix, int64_t pix_ld, int64_t n_pix, const float* u,
-                               const double* corr, const double* diag, int lv, float* image, hipStream_t s) {
+hipError_t launch_nufft_interp(const NufftGeom& g, const InterpLayout& lay, const double* pix, int64_t pix_ld,
+                               int64_t n_pix, const float* u, const double* corr, const double* diag, int lv,
+                               float* image, hipStream_t s) {
   const dim3 grd((unsigned)((n_pix + 255) / 256));
   return with_width(g.w, [&](auto wc) {
     constexpr int KW = decltype(wc)::value;
-    hipLaunchKernelGGL(nufft_interp_kernel<KW>, grd, dim3(256), 0, s, g, pix, pix_ld, n_pix, u, corr, diag, lv, image);
+    hipLaunchKernelGGL(nufft_interp_kernel<KW>, grd, dim3(256), 0, s, g, lay, pix, pix_ld, n_pix, u, corr, diag, lv,
+                       image);
     return hipGetLastError();
   });
 }

@@ -28,16 +28,39 @@ constexpr int kQuadNodes = 100;  // Gauss-Legendre nodes for kernel transforms
 struct NufftLayout {  // byte offsets into a plan's workspace
   size_t grid, work, psi0, psi1, psi2, corr, quad_t, quad_wphi, diag, err, total;
   size_t work_bytes;
-  size_t stage_ac, stage_b;  // pruned transform: A and C share a region, B has its own
+  size_t stage_ac, stage_b;  // the pruned transform's two stage regions
+  size_t perm[3];            // line FFTs: digit-reversed load position per input index (int32, M_d)
+  size_t tw[3];              // line FFTs: the passes' twiddles (complex64, M_d - 1)
 };
 
-// Complex points of the three stages of the pruned type-2 transform.
+// The pruned type-2 transform runs as the library's own LDS line FFTs when
+// every axis fits one workgroup's LDS on this device (and the caller did not
+// ask for rocFFT).
+bool use_line_fft(const bb::NufftGeom& g, int transform, int device) {
+  if (transform != 0) return false;
+  int lds_limit = 0;
+  if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) return false;
+  for (int d = 0; d < 3; ++d) {
+    bb::LineFft p{};
+    if (bb::line_fft_plan(g.M[d], p) != 0 || bb::line_fft_lds_bytes(p) > (size_t)lds_limit) return false;
+  }
+  return true;
+}
+
+// Complex points of the stages of the pruned type-2 transform.
+//   rocFFT:     A [i0][i1][m2], B [i0][w2][m1], C [w1][w2][m0] (A and C share a region)
+//   line FFTs:  A'[i0][w2][i1], B [i0][w2][w1], B'[w2][w1][i0], C [w2][w1][w0]
+//               (A' and B' share one region, B and C the other)
 struct StageSizes {
   size_t a, b, c;
 };
 StageSizes stage_sizes(const bb::NufftGeom& g) {
   return {(size_t)g.N[0] * g.N[1] * g.M[2], (size_t)g.N[0] * g.win_len[2] * g.M[1],
           (size_t)g.win_len[1] * g.win_len[2] * g.M[0]};
+}
+StageSizes line_stage_sizes(const bb::NufftGeom& g) {
+  const size_t w0 = g.win_len[0], w1 = g.win_len[1], w2 = g.win_len[2];
+  return {(size_t)g.N[0] * w2 * g.N[1], (size_t)g.N[0] * w2 * w1, w2 * w1 * w0};
 }
 
 // Gauss-Legendre nodes and weights on [-1, 1]: Newton's method on P_n,
@@ -101,7 +124,7 @@ bb_status nufft_geometry(bb_context ctx, const bb_nufft_options* o, int64_t n_pi
   if (o->n_ant_max < 2 || o->n_ant_max > bb::kMaxAnt)
     return fail(ctx, BB_ERR_INVALID_ARG, "n_ant_max must be in [2, %d]", bb::kMaxAnt);
   if (o->k_max < 1 || o->k_max > bb::kMaxEig) return fail(ctx, BB_ERR_INVALID_ARG, "k_max must be in [1, %d]", bb::kMaxEig);
-  if (o->reserved != 0) return fail(ctx, BB_ERR_INVALID_ARG, "reserved must be 0");
+  if (o->transform != 0 && o->transform != 1) return fail(ctx, BB_ERR_INVALID_ARG, "transform must be 0 or 1");
   if (!(o->epsilon >= 1e-7 && o->epsilon <= 1e-2)) return fail(ctx, BB_ERR_INVALID_ARG, "epsilon must be in [1e-7, 1e-2]");
   for (int i = 0; i < 3; ++i)
     if (!finite_pos(o->uvw_max[i])) return fail(ctx, BB_ERR_INVALID_ARG, "uvw_max must be finite and > 0");
@@ -197,17 +220,31 @@ size_t rocfft_work_bytes(const bb::NufftGeom& g, FftPlans* keep) {
   return bytes;
 }
 
-NufftLayout nufft_layout(const bb::NufftGeom& g, int n_levels, int64_t n_pix, size_t work_bytes) {
+NufftLayout nufft_layout(const bb::NufftGeom& g, int n_levels, int64_t n_pix, size_t work_bytes, bool line_fft) {
   NufftLayout l{};
   const size_t n_cell = (size_t)g.N[0] * g.N[1] * g.N[2];
-  const StageSizes st = stage_sizes(g);
   size_t p = 0;
   l.grid = p;
   p += align_up(8 * n_cell * (size_t)n_levels);
-  l.stage_ac = p;
-  p += align_up(8 * std::max(st.a, st.c));
-  l.stage_b = p;
-  p += align_up(8 * st.b);
+  if (line_fft) {
+    const StageSizes st = line_stage_sizes(g);
+    l.stage_ac = p;
+    p += align_up(8 * std::max(st.a, st.b));
+    l.stage_b = p;
+    p += align_up(8 * std::max(st.b, st.c));
+    for (int d = 0; d < 3; ++d) {
+      l.perm[d] = p;
+      p += align_up(4 * (size_t)g.M[d]);
+      l.tw[d] = p;
+      p += align_up(8 * (size_t)g.M[d]);
+    }
+  } else {
+    const StageSizes st = stage_sizes(g);
+    l.stage_ac = p;
+    p += align_up(8 * std::max(st.a, st.c));
+    l.stage_b = p;
+    p += align_up(8 * st.b);
+  }
   l.work = p;
   l.work_bytes = work_bytes;
   p += align_up(std::max<size_t>(work_bytes, 1));
@@ -245,6 +282,8 @@ struct bb_nufft_ {
   float* images = nullptr;
   char* ws = nullptr;
   NufftLayout lay{};
+  bool line_fft = false;
+  bb::LineFft lf[3]{};  // line-FFT stages: axis 2, axis 1, axis 0
   FftPlans plans;
   rocfft_execution_info info = nullptr;
   int64_t count = 0;  // instances spread since the last emit
@@ -269,11 +308,15 @@ bb_status bb_nufft_workspace_size(bb_context ctx, const bb_nufft_options* opt, i
   bb::NufftGeom g;
   bb_status st = nufft_geometry(ctx, opt, n_pix, pix_host, g);
   if (st != BB_OK) return st;
-  std::call_once(g_rocfft_once, [] { g_rocfft_setup = rocfft_setup(); });
-  if (g_rocfft_setup != rocfft_status_success) return fail(ctx, BB_ERR_DEVICE, "rocfft_setup failed");
-  const size_t work = rocfft_work_bytes(g, nullptr);
-  if (work == (size_t)-1) return fail(ctx, BB_ERR_DEVICE, "rocfft_plan_create failed");
-  *bytes = nufft_layout(g, opt->n_levels, n_pix, work).total;
+  const bool line_fft = use_line_fft(g, opt->transform, ctx->device);
+  size_t work = 0;
+  if (!line_fft) {
+    std::call_once(g_rocfft_once, [] { g_rocfft_setup = rocfft_setup(); });
+    if (g_rocfft_setup != rocfft_status_success) return fail(ctx, BB_ERR_DEVICE, "rocfft_setup failed");
+    work = rocfft_work_bytes(g, nullptr);
+    if (work == (size_t)-1) return fail(ctx, BB_ERR_DEVICE, "rocfft_plan_create failed");
+  }
+  *bytes = nufft_layout(g, opt->n_levels, n_pix, work, line_fft).total;
   return BB_OK;
 }
 
@@ -287,13 +330,17 @@ bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n
   if (!pix_xyz || !images || !workspace) return fail(ctx, BB_ERR_INVALID_ARG, "null device pointer");
   if (reinterpret_cast<uintptr_t>(workspace) % bb_host::kAlign)
     return fail(ctx, BB_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-  std::call_once(g_rocfft_once, [] { g_rocfft_setup = rocfft_setup(); });
-  if (g_rocfft_setup != rocfft_status_success) return fail(ctx, BB_ERR_DEVICE, "rocfft_setup failed");
+  const bool line_fft = use_line_fft(g, opt->transform, ctx->device);
   BB_HIP(ctx, hipSetDevice(ctx->device));
   FftPlans plans;
-  const size_t work = rocfft_work_bytes(g, &plans);
-  if (work == (size_t)-1) return fail(ctx, BB_ERR_DEVICE, "rocfft_plan_create failed");
-  const NufftLayout lay = nufft_layout(g, opt->n_levels, n_pix, work);
+  size_t work = 0;
+  if (!line_fft) {
+    std::call_once(g_rocfft_once, [] { g_rocfft_setup = rocfft_setup(); });
+    if (g_rocfft_setup != rocfft_status_success) return fail(ctx, BB_ERR_DEVICE, "rocfft_setup failed");
+    work = rocfft_work_bytes(g, &plans);
+    if (work == (size_t)-1) return fail(ctx, BB_ERR_DEVICE, "rocfft_plan_create failed");
+  }
+  const NufftLayout lay = nufft_layout(g, opt->n_levels, n_pix, work, line_fft);
   if (ws_bytes < lay.total) {
     plans.destroy();
     return fail(ctx, BB_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, lay.total);
@@ -312,6 +359,28 @@ bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n
   h->ws = static_cast<char*>(workspace);
   h->lay = lay;
   h->plans = plans;
+  h->line_fft = line_fft;
+  if (line_fft) {
+    const int64_t w0 = g.win_len[0], w1 = g.win_len[1], w2 = g.win_len[2];
+    for (int st = 0; st < 3; ++st) {
+      const int d = 2 - st;
+      bb::LineFft& p = h->lf[st];
+      bb::line_fft_plan(g.M[d], p);
+      p.n_in = g.N[d];
+      p.win_lo = g.win_lo[d];
+      p.win_len = g.win_len[d];
+    }
+    h->lf[0].n_lines = (int64_t)g.N[0] * g.N[1];  // grid lines along axis 2 -> A'[i0][w2][i1]
+    h->lf[0].in_stride = g.N[2];
+    h->lf[0].out_mode = 1;
+    h->lf[0].t_inner = g.N[1];
+    h->lf[1].n_lines = (int64_t)g.N[0] * w2;  // A' lines along axis 1 -> B[i0][w2][w1]
+    h->lf[1].in_stride = g.N[1];
+    h->lf[1].out_stride = w1;
+    h->lf[2].n_lines = w2 * w1;  // B' lines along axis 0 -> C[w2][w1][w0]
+    h->lf[2].in_stride = g.N[0];
+    h->lf[2].out_stride = w0;
+  }
   auto bail = [&](const char* what) {
     if (h->info) rocfft_execution_info_destroy(h->info);
     h->plans.destroy();
@@ -320,11 +389,14 @@ bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n
     delete h;
     return fail(ctx, BB_ERR_DEVICE, "%s", what);
   };
-  if (rocfft_execution_info_create(&h->info) != rocfft_status_success) return bail("rocfft_execution_info_create failed");
-  if (work > 0 && rocfft_execution_info_set_work_buffer(h->info, h->ws + lay.work, work) != rocfft_status_success)
-    return bail("rocfft_execution_info_set_work_buffer failed");
-  if (rocfft_execution_info_set_stream(h->info, ctx->stream) != rocfft_status_success)
-    return bail("rocfft_execution_info_set_stream failed");
+  if (!line_fft) {
+    if (rocfft_execution_info_create(&h->info) != rocfft_status_success)
+      return bail("rocfft_execution_info_create failed");
+    if (work > 0 && rocfft_execution_info_set_work_buffer(h->info, h->ws + lay.work, work) != rocfft_status_success)
+      return bail("rocfft_execution_info_set_work_buffer failed");
+    if (rocfft_execution_info_set_stream(h->info, ctx->stream) != rocfft_status_success)
+      return bail("rocfft_execution_info_set_stream failed");
+  }
   for (hipEvent_t& e : h->ev)
     if (hipEventCreate(&e) != hipSuccess) return bail("hipEventCreate failed");
 
@@ -345,7 +417,21 @@ bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n
       psi[d][i] = (float)(1.0 / (a * acc));  // psi_hat(g) M / (2 pi), inverted
     }
   }
+  std::vector<int> perm[3];
+  std::vector<float> tw[3];
+  if (line_fft)
+    for (int d = 0; d < 3; ++d) {
+      perm[d].resize(g.M[d]);
+      bb::line_fft_perm(h->lf[2 - d], perm[d].data());
+      tw[d].assign(2 * (size_t)g.M[d], 0.0f);
+      bb::line_fft_twiddles(h->lf[2 - d], tw[d].data());
+    }
   hipStream_t s = ctx->stream;
+  for (int d = 0; d < 3 && line_fft; ++d)
+    if (hipMemcpyAsync(nat<int>(h, lay.perm[d]), perm[d].data(), 4 * perm[d].size(), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(nat<float>(h, lay.tw[d]), tw[d].data(), 4 * tw[d].size(), hipMemcpyHostToDevice, s) != hipSuccess)
+      return bail("table upload failed");
   // pageable sources: each copy is staged before the call returns
   if (hipMemcpyAsync(nat<float>(h, lay.psi0), psi[0].data(), 4 * psi[0].size(), hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(nat<float>(h, lay.psi1), psi[1].data(), 4 * psi[1].size(), hipMemcpyHostToDevice, s) != hipSuccess ||
@@ -519,25 +605,43 @@ bb_status bb_nufft_emit(bb_nufft h) {
   const int64_t n_cell = (int64_t)g.N[0] * g.N[1] * g.N[2];
   void* ac = h->ws + h->lay.stage_ac;
   void* b = h->ws + h->lay.stage_b;
+  const float* psi[3] = {nat<float>(h, h->lay.psi0), nat<float>(h, h->lay.psi1), nat<float>(h, h->lay.psi2)};
   // the context's stream may have been rebound since the plan was made
-  if (rocfft_execution_info_set_stream(h->info, s) != rocfft_status_success)
+  if (!h->line_fft && rocfft_execution_info_set_stream(h->info, s) != rocfft_status_success)
     return fail(ctx, BB_ERR_DEVICE, "rocfft_execution_info_set_stream failed");
   BB_HIP(ctx, hipEventRecord(h->ev[2], s));
   for (int lv = 0; lv < h->opt.n_levels; ++lv) {
-    // pruned inverse transform: grid -> A (FFT along axis 2) -> B (axis 1) -> C (axis 0)
     const float* level_grid = nat<float>(h, h->lay.grid) + 2 * (int64_t)lv * n_cell;
-    void* const stage_in[3] = {const_cast<float*>(level_grid), ac, b};
-    void* const stage_out[3] = {ac, b, ac};
-    const size_t psi[3] = {h->lay.psi2, h->lay.psi1, h->lay.psi0};
-    for (int st = 0; st < 3; ++st) {
-      BB_HIP(ctx, bb::launch_nufft_gather(2 - st, g, stage_in[st], nat<float>(h, psi[st]), stage_out[st], s));
-      void* buf[1] = {stage_out[st]};
-      if (rocfft_execute(h->plans.p[st], buf, nullptr, h->info) != rocfft_status_success)
-        return fail(ctx, BB_ERR_DEVICE, "rocfft_execute failed");
+    bb::InterpLayout il;
+    const void* u;
+    if (h->line_fft) {
+      // axis 2: grid -> A'; axis 1: A' -> B; B -> B' (transpose); axis 0: B' -> C
+      const int64_t w1 = g.win_len[1], w2 = g.win_len[2];
+      BB_HIP(ctx, bb::launch_line_fft(h->lf[0], level_grid, psi[2], nat<int>(h, h->lay.perm[2]),
+                                      nat<float2>(h, h->lay.tw[2]), ac, s));
+      BB_HIP(ctx, bb::launch_line_fft(h->lf[1], ac, psi[1], nat<int>(h, h->lay.perm[1]), nat<float2>(h, h->lay.tw[1]),
+                                      b, s));
+      BB_HIP(ctx, bb::launch_transpose_c64(b, g.N[0], w2 * w1, ac, s));
+      BB_HIP(ctx, bb::launch_line_fft(h->lf[2], ac, psi[0], nat<int>(h, h->lay.perm[0]), nat<float2>(h, h->lay.tw[0]),
+                                      b, s));
+      il = {(int64_t)g.win_len[0], w1 * g.win_len[0], g.win_lo[0], g.win_len[0]};
+      u = b;
+    } else {
+      // grid -> A (FFT along axis 2) -> B (axis 1) -> C (axis 0)
+      void* const stage_in[3] = {const_cast<float*>(level_grid), ac, b};
+      void* const stage_out[3] = {ac, b, ac};
+      for (int st = 0; st < 3; ++st) {
+        BB_HIP(ctx, bb::launch_nufft_gather(2 - st, g, stage_in[st], psi[2 - st], stage_out[st], s));
+        void* buf[1] = {stage_out[st]};
+        if (rocfft_execute(h->plans.p[st], buf, nullptr, h->info) != rocfft_status_success)
+          return fail(ctx, BB_ERR_DEVICE, "rocfft_execute failed");
+      }
+      il = {(int64_t)g.win_len[2] * g.M[0], (int64_t)g.M[0], 0, g.M[0]};
+      u = ac;
     }
-    BB_HIP(ctx, bb::launch_nufft_interp(g, h->pix, h->n_pix, h->n_pix, static_cast<const float*>(ac),
-                                        nat<double>(h, h->lay.corr),
-                                        nat<double>(h, h->lay.diag), lv, h->images + (int64_t)lv * h->n_pix, s));
+    BB_HIP(ctx, bb::launch_nufft_interp(g, il, h->pix, h->n_pix, h->n_pix, static_cast<const float*>(u),
+                                        nat<double>(h, h->lay.corr), nat<double>(h, h->lay.diag), lv,
+                                        h->images + (int64_t)lv * h->n_pix, s));
   }
   BB_HIP(ctx, bb::launch_fill_zero(nat<float>(h, h->lay.grid), 2 * n_cell * h->opt.n_levels, s));
   BB_HIP(ctx, bb::launch_fill_zero_f64(nat<double>(h, h->lay.diag), bb::kMaxLevels, s));

@@ -64,9 +64,9 @@ def _uvw_bound(items, frame):
     return b * 1.01
 
 
-def _run(ctx, pix, items, n_levels, eps, frame, uvw, n_ant_max=64, k_max=64, emits=1):
+def _run(ctx, pix, items, n_levels, eps, frame, uvw, n_ant_max=64, k_max=64, emits=1, transform="auto"):
     from paper_2310_09200_amd import Batch, NufftSynthesis
-    plan = NufftSynthesis(ctx, pix, n_levels, n_ant_max, k_max, eps, frame, uvw)
+    plan = NufftSynthesis(ctx, pix, n_levels, n_ant_max, k_max, eps, frame, uvw, transform=transform)
     chunks = np.array_split(np.arange(len(items)), emits)
     for ch in chunks:
         b = Batch([(0, items[i][0], items[i][1], items[i][2], items[i][3], items[i][5]) for i in ch], ctx.device)
@@ -126,6 +126,22 @@ def test_nufft_batched_ragged_instances(ctx):
     _check(got, want_nufft, 1e-5)
 
 
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_nufft_transforms_agree(ctx, eps):
+    """The library's own line FFTs and rocFFT compute the same pruned transform:
+    both within 1e-5 of the FP64 NUFFT oracle and within FP32 rounding of each other."""
+    say(f"case nufft line FFTs vs rocFFT, eps={eps}")
+    pix, items, n_levels = _instances(3, [48, 37, 64], 32, 4, 3)
+    frame = np.array(sims.tangent_basis(90.0))
+    uvw = _uvw_bound(items, frame)
+    got_line, _ = _run(ctx, pix, items, n_levels, eps, frame, uvw, transform="auto")
+    got_roc, _ = _run(ctx, pix, items, n_levels, eps, frame, uvw, transform="rocfft")
+    want_nufft = nf.nufft_images([(x, wl, W, d, mem) for x, wl, W, d, mem, _ in items], pix, eps, X=uvw, frame=frame)
+    _check(got_line, want_nufft, 1e-5)
+    _check(got_roc, want_nufft, 1e-5)
+    _check(got_line, got_roc, 5e-6)
+
+
 def test_nufft_tilted_frame(ctx):
     """Pixels around a phase centre at declination +50 deg; the grid is thin along p0."""
     say("case nufft tilted frame")
@@ -167,15 +183,26 @@ def test_nufft_rejects_bad_options(ctx):
         NufftSynthesis(ctx, pix, 2, 16, 16, 1e-9, np.eye(3), [10.0, 10.0, 10.0])
     with pytest.raises(BluebildError):
         NufftSynthesis(ctx, pix, 2, 16, 16, 1e-4, np.diag([1.0, 1.0, 2.0]), [10.0, 10.0, 10.0])
+    from paper_2310_09200_amd import _lib
+    opt = _lib.bb_nufft_options(n_levels=2, n_ant_max=16, k_max=16, transform=2, epsilon=1e-4)
+    opt.frame[0] = opt.frame[4] = opt.frame[8] = 1.0
+    for i in range(3):
+        opt.uvw_max[i] = 10.0
+    pix_cm = np.ascontiguousarray(np.asarray(pix, np.float64).T)
+    import ctypes
+    sz = ctypes.c_size_t()
+    assert ctx.lib.bb_nufft_workspace_size(ctx.handle, ctypes.byref(opt), pix_cm.shape[1],
+                                           ctypes.c_void_p(pix_cm.ctypes.data), ctypes.byref(sz)) != 0
 
 
+@pytest.mark.parametrize("transform", ["auto", "rocfft"])
 @pytest.mark.parametrize("fov_deg,path", [(30.0, "tiles of 8 grid points"), (60.0, "global atomics")])
-def test_nufft_thick_grids(ctx, fov_deg, path):
+def test_nufft_thick_grids(ctx, fov_deg, path, transform):
     """A 3-D antenna cloud and a wide field make the grid thick along p0: the
     spread runs on smaller LDS tiles (32 < N2 <= 128) or, past 128 points,
     with global atomics; both against standard synthesis."""
     from paper_2310_09200_amd import Batch, NufftSynthesis
-    say(f"case nufft thick grid, field {fov_deg} deg ({path})")
+    say(f"case nufft thick grid, field {fov_deg} deg ({path}), transform {transform}")
     g = sims.rng(96, int(fov_deg))
     L, K = 40, 20
     x = g.uniform(-150.0, 150.0, (L, 3))
@@ -189,7 +216,7 @@ def test_nufft_thick_grids(ctx, fov_deg, path):
     items = [(x, wl, W, d, member, lev)]
     uvw = _uvw_bound(items, frame)
     eps = 1e-4
-    plan = NufftSynthesis(ctx, pix, 3, L, K, eps, frame, uvw)
+    plan = NufftSynthesis(ctx, pix, 3, L, K, eps, frame, uvw, transform=transform)
     N, M, wk = plan.shape
     assert (32 < N[2] <= 128) if fov_deg == 30.0 else (N[2] > 128), N
     plan.collect_eig_batched(Batch([(0, x, wl, W, d, lev)], ctx.device))
