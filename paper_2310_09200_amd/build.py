@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbluebild.so")
 
-SOURCES = ["api.cpp", "synth_kernels.hip", "prestep.hip", "synth_bwd.hip", "levels_weighting.hip", "nufft.hip", "nufft_fft.hip",
+SOURCES = ["api.cpp", "synth_kernels.hip", "prestep.hip", "synth_bwd.hip", "levels_weighting.hip", "nufft.hip", "nufft_fft.hip", "nufft_gather.hip",
            "nufft_api.cpp"]
 ARCH = "gfx950"
 

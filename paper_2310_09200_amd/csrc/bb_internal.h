@@ -178,9 +178,25 @@ hipError_t launch_fill_zero_f64(double* p, int n, hipStream_t s);
 hipError_t launch_nufft_vprime(const NufftInst* insts, int n_inst, int max_ant, const void* Wmat, const float* d,
                                const int* order, const int* lstart, int n_levels, void* vp, hipStream_t s);
 int nufft_tile_size(const NufftGeom& g);  // 16 or 8 grid points per tile side, 0 = no tiled path
+// Exclusive prefix sum of n ints into offset[0..n] (and cursor[0..n-1] unless
+// null); tmp: scan_tmp_ints(n) ints (may be null for n <= 65536).
+int scan_tmp_ints(int n);
+hipError_t launch_scan_i32(const int* count, int n, int* offset, int* cursor, int* tmp, hipStream_t s);
 hipError_t launch_nufft_bin(const NufftGeom& g, const NufftInst* insts, int n_inst, int max_ant, const double* ant,
                             int64_t ld, int bin, int* count, int* offset, int* cursor, uint64_t* list, int* err,
-                            hipStream_t s);
+                            int* scan_tmp, hipStream_t s);
+// Output-driven spread (nufft_gather.hip) for grids with N2 <= 32: points of
+// axis 2 per column (8, 16 or 32; 0 = not applicable) and column blocks.
+int nufft_gather_z(const NufftGeom& g);
+void nufft_gather_blocks(const NufftGeom& g, int& nbx, int& nby);
+constexpr int kGatherRecBytes = 128;  // per sorted baseline
+// After launch_nufft_bin with bin 1: records (max_src x 128 bytes), level values
+// (max_src x ((n_levels + 1) & ~1) complex64), nparts and part_off (blocks,
+// blocks + 1 ints), scan_tmp (scan_tmp_ints(blocks)).
+hipError_t launch_nufft_spread_gather(const NufftGeom& g, const NufftInst* insts, int64_t max_src, const double* ant,
+                                      int64_t ld, const void* vp, const int* offset, const uint64_t* list,
+                                      int n_levels, void* rec, void* cv, int* nparts, int* part_off, int* scan_tmp,
+                                      float* grid, int64_t n_cell, hipStream_t s);
 // nch, choff: n_tiles and n_tiles + 1 ints of scratch (chunks per tile and their offsets).
 hipError_t launch_nufft_spread_tiles(const NufftGeom& g, const NufftInst* insts, const double* ant, int64_t ld,
                                      const void* vp, const int* offset, const uint64_t* list, int bin, int n_levels,

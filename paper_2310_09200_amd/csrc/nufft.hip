@@ -27,36 +27,11 @@
 #include <type_traits>
 
 #include "bb_internal.h"
+#include "nufft_device.h"
 
 namespace bb {
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ float es_kernel(float z, float beta) {
-  const float t = fmaxf(1.0f - z * z, 0.0f);
-  return __expf(beta * (sqrtf(t) - 1.0f));
-}
-
-// Kernel values and wrapped grid indices of the W points nearest to xi
-// (grid units) on a periodic axis of n points.
-template <int W>
-__device__ __forceinline__ void kernel_row(double xi, int n, float beta, float (&k)[W], int (&idx)[W]) {
-  const double first = ceil(xi - 0.5 * W);
-  const float inv_half = 2.0f / (float)W;
-  int j = (int)first % n;
-  if (j < 0) j += n;
-#pragma unroll
-  for (int t = 0; t < W; ++t) {
-    k[t] = es_kernel((float)((first + t) - xi) * inv_half, beta);
-    idx[t] = j;
-    j = (j + 1 == n) ? 0 : j + 1;
-  }
-}
-
-__device__ __forceinline__ double frame_coord(const NufftGeom& g, int d, double a0, double a1, double a2) {
-#pragma clang fp contract(off)
-  return (a0 * g.R[d][0] + a1 * g.R[d][1]) + a2 * g.R[d][2];
-}
 
 // ---------------------------------------------------------------------------
 // Per instance: eigenpair order grouped by level (stable), level starts, and
@@ -241,30 +216,6 @@ __global__ __launch_bounds__(256) void nufft_vprime_kernel(const NufftInst* __re
   }
 }
 
-// Baseline (q, r) of an instance in spread-grid units; false (and the error
-// bit) when it lies beyond the planned extent.
-__device__ __forceinline__ bool source_coords(const NufftGeom& g, const NufftInst& I, const double* __restrict__ ant,
-                                              int64_t ld, int q, int r, double (&xi)[3], double& turns_d) {
-  const double* A = ant + I.ant_off;
-  double b[3];
-  {
-#pragma clang fp contract(off)
-    const double d0 = A[q] - A[r];
-    const double d1 = A[q + ld] - A[r + ld];
-    const double d2 = A[q + 2 * ld] - A[r + 2 * ld];
-    for (int d = 0; d < 3; ++d) b[d] = frame_coord(g, d, d0, d1, d2) / I.wavelength_m;
-  }
-  if (!(fabs(b[0]) <= g.X[0]) || !(fabs(b[1]) <= g.X[1]) || !(fabs(b[2]) <= g.X[2])) return false;
-  for (int d = 0; d < 3; ++d) xi[d] = b[d] * g.inv_h[d];
-  turns_d = b[0] * g.D[0] + b[1] * g.D[1] + b[2] * g.D[2];
-  return true;
-}
-
-__device__ __forceinline__ int first_cell(double xi, int w, int n) {
-  const int j = (int)ceil(xi - 0.5 * w) % n;
-  return j < 0 ? j + n : j;
-}
-
 // pass 0: count baselines per bin; pass 1: place them (cursor = bin starts).
 __global__ __launch_bounds__(256) void nufft_bin_kernel(NufftGeom g, const NufftInst* __restrict__ insts,
                                                         const double* __restrict__ ant, int64_t ld, int bin, int nb1,
@@ -306,13 +257,68 @@ __global__ __launch_bounds__(1024) void nufft_scan_kernel(const int* __restrict_
     }
     if (base + tid < n) {
       offset[base + tid] = carry + s[tid] - v;
-      cursor[base + tid] = carry + s[tid] - v;
+      if (cursor) cursor[base + tid] = carry + s[tid] - v;
     }
     __syncthreads();
     if (tid == 1023) carry += s[1023];
     __syncthreads();
   }
   if (tid == 0) offset[n] = carry;
+}
+
+// Exclusive prefix sums of long arrays in three steps: the sum of each chunk
+// of kScanChunk counts, a one-workgroup scan of those sums, and a scan inside
+// each chunk started at its chunk's offset.
+constexpr int kScanChunk = 4096;
+
+__global__ __launch_bounds__(1024) void scan_chunk_sums_kernel(const int* __restrict__ count, int n,
+                                                               int* __restrict__ sums) {
+  __shared__ int s[1024];
+  const int base = blockIdx.x * kScanChunk, t = threadIdx.x;
+  int v = 0;
+  for (int i = t; i < kScanChunk; i += 1024)
+    if (base + i < n) v += count[base + i];
+  s[t] = v;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off) s[t] += s[t + off];
+    __syncthreads();
+  }
+  if (t == 0) sums[blockIdx.x] = s[0];
+}
+
+// Each thread scans 4 consecutive counts; cursor may alias count (every count
+// is read before the barrier that precedes the writes).
+__global__ __launch_bounds__(1024) void scan_chunks_kernel(const int* count, int n, const int* __restrict__ chunk_off,
+                                                           int* __restrict__ offset, int* cursor) {
+  __shared__ int s[1024];
+  const int base = blockIdx.x * kScanChunk, t = threadIdx.x;
+  int v[4], sum = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int idx = base + 4 * t + i;
+    v[i] = idx < n ? count[idx] : 0;
+    sum += v[i];
+  }
+  s[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int x = t >= off ? s[t - off] : 0;
+    __syncthreads();
+    s[t] += x;
+    __syncthreads();
+  }
+  int run = chunk_off[blockIdx.x] + s[t] - sum;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int idx = base + 4 * t + i;
+    if (idx < n) {
+      offset[idx] = run;
+      if (cursor) cursor[idx] = run;
+    }
+    run += v[i];
+  }
+  if (blockIdx.x == gridDim.x - 1 && t == 0) offset[n] = chunk_off[gridDim.x];
 }
 
 // Bins holding the first cells x0 - (w - 1) .. x0 + t - 1 (mod n) of an axis:
@@ -619,19 +625,6 @@ __global__ __launch_bounds__(256) void fill_zero_f64_kernel(double* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-template <class F>
-static hipError_t with_width(int w, F f) {
-  switch (w) {
-    case 3: return f(std::integral_constant<int, 3>{});
-    case 4: return f(std::integral_constant<int, 4>{});
-    case 5: return f(std::integral_constant<int, 5>{});
-    case 6: return f(std::integral_constant<int, 6>{});
-    case 7: return f(std::integral_constant<int, 7>{});
-    case 8: return f(std::integral_constant<int, 8>{});
-    default: return hipErrorInvalidValue;
-  }
-}
-
 hipError_t launch_nufft_prep(const NufftInst* insts, int n_inst, const void* W, const float* d, const int* lev,
                              int n_levels, int* order, int* lstart, double* diag, int* err, hipStream_t s) {
   hipLaunchKernelGGL(nufft_prep_kernel, dim3(n_inst), dim3(256), 0, s, insts, (const float2*)W, d, lev, n_levels,
@@ -669,9 +662,25 @@ int nufft_tile_size(const NufftGeom& g) {
   return 0;  // too thick along axis 2 for an LDS tile: spread with global atomics
 }
 
+int scan_tmp_ints(int n) { return 2 * ((n + kScanChunk - 1) / kScanChunk) + 2; }
+
+hipError_t launch_scan_i32(const int* count, int n, int* offset, int* cursor, int* tmp, hipStream_t s) {
+  if (n <= 1 << 16 || !tmp) {
+    hipLaunchKernelGGL(nufft_scan_kernel, dim3(1), dim3(1024), 0, s, count, n, offset, cursor);
+    return hipGetLastError();
+  }
+  const int nc = (n + kScanChunk - 1) / kScanChunk;
+  int* sums = tmp;
+  int* chunk_off = tmp + nc;  // nc + 1 entries
+  hipLaunchKernelGGL(scan_chunk_sums_kernel, dim3((unsigned)nc), dim3(1024), 0, s, count, n, sums);
+  hipLaunchKernelGGL(nufft_scan_kernel, dim3(1), dim3(1024), 0, s, sums, nc, chunk_off, static_cast<int*>(nullptr));
+  hipLaunchKernelGGL(scan_chunks_kernel, dim3((unsigned)nc), dim3(1024), 0, s, count, n, chunk_off, offset, cursor);
+  return hipGetLastError();
+}
+
 hipError_t launch_nufft_bin(const NufftGeom& g, const NufftInst* insts, int n_inst, int max_ant, const double* ant,
                             int64_t ld, int bin, int* count, int* offset, int* cursor, uint64_t* list, int* err,
-                            hipStream_t s) {
+                            int* scan_tmp, hipStream_t s) {
   const int nb0 = (g.N[0] + bin - 1) / bin, nb1 = (g.N[1] + bin - 1) / bin;
   const int n_bins = nb0 * nb1;
   const int64_t pairs = (int64_t)max_ant * max_ant;
@@ -679,7 +688,8 @@ hipError_t launch_nufft_bin(const NufftGeom& g, const NufftInst* insts, int n_in
   hipError_t e = launch_fill_zero(reinterpret_cast<float*>(count), n_bins, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(nufft_bin_kernel, grd, dim3(256), 0, s, g, insts, ant, ld, bin, nb1, 0, count, list, err);
-  hipLaunchKernelGGL(nufft_scan_kernel, dim3(1), dim3(1024), 0, s, count, n_bins, offset, cursor);
+  e = launch_scan_i32(count, n_bins, offset, cursor, scan_tmp, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(nufft_bin_kernel, grd, dim3(256), 0, s, g, insts, ant, ld, bin, nb1, 1, cursor, list, err);
   return hipGetLastError();
 }

@@ -468,8 +468,10 @@ namespace {
 
 // Per-call workspace of a spread call (byte offsets).
 struct CallLayout {
-  size_t inst, order, lstart, vp, count, offset, cursor, list, nch, choff, total;
-  int bin = 0, n_bins = 0;
+  size_t inst, order, lstart, vp, count, offset, cursor, list, nch, choff, scan_tmp, rec, cv, nparts, part_off, total;
+  int mode = 0;  // 2: output-driven spread, 1: LDS tiles, 0: global atomics
+  int bin = 0, n_bins = 0, n_blocks = 0;
+  int64_t pairs = 0;
 };
 
 CallLayout call_layout(bb_nufft h, int32_t n_inst, const bb_instance* inst) {
@@ -481,7 +483,9 @@ CallLayout call_layout(bb_nufft h, int32_t n_inst, const bb_instance* inst) {
     vp += (size_t)h->opt.n_levels * L * L;
     pairs += L * (L > 0 ? L - 1 : 0) / 2;
   }
-  c.bin = bb::nufft_tile_size(h->g);
+  c.pairs = (int64_t)pairs;
+  c.mode = bb::nufft_gather_z(h->g) > 0 ? 2 : bb::nufft_tile_size(h->g) > 0 ? 1 : 0;
+  c.bin = c.mode == 2 ? 1 : c.mode == 1 ? bb::nufft_tile_size(h->g) : 0;
   size_t p = 0;
   c.inst = p;
   p += align_up(sizeof(bb::NufftInst) * n_inst);
@@ -489,8 +493,26 @@ CallLayout call_layout(bb_nufft h, int32_t n_inst, const bb_instance* inst) {
   p += align_up(4 * n_eig);
   c.lstart = p;
   p += align_up(4 * (size_t)n_inst * (h->opt.n_levels + 1));
-  if (c.bin > 0) {
+  if (c.mode > 0) {
     c.n_bins = ((h->g.N[0] + c.bin - 1) / c.bin) * ((h->g.N[1] + c.bin - 1) / c.bin);
+    int scan_n = c.n_bins;
+    if (c.mode == 2) {
+      int nbx, nby;
+      bb::nufft_gather_blocks(h->g, nbx, nby);
+      c.n_blocks = nbx * nby;
+      scan_n = std::max(scan_n, c.n_blocks);
+      const size_t lv_pad = (size_t)((h->opt.n_levels + 1) & ~1);
+      c.rec = p;
+      p += align_up((size_t)bb::kGatherRecBytes * std::max<size_t>(pairs, 1));
+      c.cv = p;
+      p += align_up(8 * lv_pad * std::max<size_t>(pairs, 1));
+      c.nparts = p;
+      p += align_up(4 * (size_t)c.n_blocks);
+      c.part_off = p;
+      p += align_up(4 * ((size_t)c.n_blocks + 1));
+    }
+    c.scan_tmp = p;
+    p += align_up(4 * (size_t)bb::scan_tmp_ints(scan_n));
     c.vp = p;
     p += align_up(8 * vp);
     c.count = p;
@@ -572,15 +594,28 @@ bb_status bb_nufft_collect_eig_batched(bb_nufft h, int32_t n_inst, const bb_inst
   BB_HIP(ctx, bb::launch_nufft_prep(d_inst, n_inst, W_packed, d_packed, level_packed, n_levels, d_order, d_lstart,
                                     nat<double>(h, h->lay.diag), nat<int>(h, h->lay.err), s));
   const int64_t n_cell = (int64_t)h->g.N[0] * h->g.N[1] * h->g.N[2];
-  if (cl.bin > 0) {
+  if (cl.mode > 0) {
     BB_HIP(ctx, bb::launch_nufft_vprime(d_inst, n_inst, max_ant, W_packed, d_packed, d_order, d_lstart, n_levels,
                                         ws + cl.vp, s));
     int* count = reinterpret_cast<int*>(ws + cl.count);
     int* offset = reinterpret_cast<int*>(ws + cl.offset);
     int* cursor = reinterpret_cast<int*>(ws + cl.cursor);
     uint64_t* list = reinterpret_cast<uint64_t*>(ws + cl.list);
+    int* scan_tmp = reinterpret_cast<int*>(ws + cl.scan_tmp);
     BB_HIP(ctx, bb::launch_nufft_bin(h->g, d_inst, n_inst, max_ant, ant_xyz_packed, n_ant_rows, cl.bin, count, offset,
-                                     cursor, list, nat<int>(h, h->lay.err), s));
+                                     cursor, list, nat<int>(h, h->lay.err), scan_tmp, s));
+  }
+  if (cl.mode == 2) {
+    BB_HIP(ctx, bb::launch_nufft_spread_gather(h->g, d_inst, cl.pairs, ant_xyz_packed, n_ant_rows, ws + cl.vp,
+                                               reinterpret_cast<int*>(ws + cl.offset),
+                                               reinterpret_cast<uint64_t*>(ws + cl.list), n_levels, ws + cl.rec,
+                                               ws + cl.cv, reinterpret_cast<int*>(ws + cl.nparts),
+                                               reinterpret_cast<int*>(ws + cl.part_off),
+                                               reinterpret_cast<int*>(ws + cl.scan_tmp), nat<float>(h, h->lay.grid),
+                                               n_cell, s));
+  } else if (cl.mode == 1) {
+    const int* offset = reinterpret_cast<int*>(ws + cl.offset);
+    const uint64_t* list = reinterpret_cast<uint64_t*>(ws + cl.list);
     BB_HIP(ctx, bb::launch_nufft_spread_tiles(h->g, d_inst, ant_xyz_packed, n_ant_rows, ws + cl.vp, offset, list,
                                               cl.bin, n_levels, reinterpret_cast<int*>(ws + cl.nch),
                                               reinterpret_cast<int*>(ws + cl.choff), nat<float>(h, h->lay.grid), n_cell,
