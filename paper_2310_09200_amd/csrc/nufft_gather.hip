@@ -161,7 +161,7 @@ __global__ __launch_bounds__(256) void nufft_block_parts_kernel(NufftGeom g, con
 
 // Persistent over the parts of every column block (part k of block b for
 // part_off[b] <= k < part_off[b + 1]); see the file comment.  LV: the level
-// count rounded up to a multiple of 4.
+// count rounded up to even.
 template <int Z, int LV>
 __global__ __launch_bounds__(256) void nufft_gather_spread_kernel(NufftGeom g, const int* __restrict__ offset,
                                                                   const SrcRec* __restrict__ rec,
@@ -300,10 +300,16 @@ hipError_t launch_nufft_spread_gather(const NufftGeom& g, const NufftInst* insts
     return hipGetLastError();
   };
   auto by_levels = [&](auto zc) -> hipError_t {
-    if (n_levels <= 4) return run(zc, std::integral_constant<int, 4>{});
-    if (n_levels <= 8) return run(zc, std::integral_constant<int, 8>{});
-    if (n_levels <= 12) return run(zc, std::integral_constant<int, 12>{});
-    return run(zc, std::integral_constant<int, 16>{});
+    switch ((n_levels + 1) / 2) {
+      case 1: return run(zc, std::integral_constant<int, 2>{});
+      case 2: return run(zc, std::integral_constant<int, 4>{});
+      case 3: return run(zc, std::integral_constant<int, 6>{});
+      case 4: return run(zc, std::integral_constant<int, 8>{});
+      case 5: return run(zc, std::integral_constant<int, 10>{});
+      case 6: return run(zc, std::integral_constant<int, 12>{});
+      case 7: return run(zc, std::integral_constant<int, 14>{});
+      default: return run(zc, std::integral_constant<int, 16>{});
+    }
   };
   return Zc == 16 ? by_levels(std::integral_constant<int, 16>{}) : by_levels(std::integral_constant<int, 32>{});
 }
