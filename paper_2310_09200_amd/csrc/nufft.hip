@@ -189,30 +189,71 @@ __global__ __launch_bounds__(256) void nufft_spread_kernel(NufftGeom g, const Nu
 // plain loads and stores; only LDS sees atomics.
 
 // V'_l[r, q] = sum_{k in l} d_k W_rk conj(W_qk) for q < r, at vp[vp_off + l L^2 + q + r L].
+// One workgroup per 32 x 32 block of (q, r) with q-block <= r-block: the two
+// blocks of W rows (the r side times d_k) go through LDS kVpK eigenpairs at a
+// time, level by level in the level-grouped order; each thread keeps 2 x 2
+// pairs.
+constexpr int kVpK = 64;
+
 __global__ __launch_bounds__(256) void nufft_vprime_kernel(const NufftInst* __restrict__ insts,
                                                            const float2* __restrict__ Wp, const float* __restrict__ dw,
                                                            const int* __restrict__ order, const int* __restrict__ lstart,
                                                            int n_levels, float2* __restrict__ vp) {
+  __shared__ float2 s_q[kVpK][32], s_r[kVpK][32];
   const NufftInst I = insts[blockIdx.y];
   const int L = I.n_ant;
-  const int64_t pair = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (pair >= (int64_t)L * L) return;
-  const int q = (int)(pair % L), r = (int)(pair / L);
-  if (q >= r) return;
+  const int nb = (L + 31) / 32;
+  // upper-triangular block (bq <= br) number blockIdx.x
+  int br = 0, rest = blockIdx.x;
+  while (br < nb && rest > br) rest -= br + 1, ++br;
+  if (br >= nb) return;
+  const int bq = rest;
+  const int tid = threadIdx.x, tq = tid & 15, tr = tid >> 4;
   const float2* Wi = Wp + I.w_off;
   const int* ord = order + I.ord_off;
   const int* ls = lstart + I.ls_off;
+  const int q0 = bq * 32, r0 = br * 32;
   for (int lv = 0; lv < n_levels; ++lv) {
-    float cr = 0.0f, ci = 0.0f;
-    for (int t2 = ls[lv]; t2 < ls[lv + 1]; ++t2) {
-      const int k = ord[t2];
-      const float2 wq = Wi[q + (int64_t)k * L];
-      const float2 wr = Wi[r + (int64_t)k * L];
-      const float dk = dw[I.eig_off + k];
-      cr += dk * (wr.x * wq.x + wr.y * wq.y);
-      ci += dk * (wr.y * wq.x - wr.x * wq.y);
+    float2 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = make_float2(0.0f, 0.0f);
+    const int k_lo = ls[lv], k_hi = ls[lv + 1];
+    for (int k0 = k_lo; k0 < k_hi; k0 += kVpK) {
+      const int nk = min(kVpK, k_hi - k0);
+      __syncthreads();  // the previous chunk is consumed
+      for (int i = tid; i < nk * 32; i += 256) {
+        const int row = i & 31, kk = i >> 5;
+        const int k = ord[k0 + kk];
+        const int64_t col = (int64_t)k * L;
+        const float dk = dw[I.eig_off + k];
+        const float2 wq = q0 + row < L ? Wi[q0 + row + col] : make_float2(0.0f, 0.0f);
+        const float2 wr = r0 + row < L ? Wi[r0 + row + col] : make_float2(0.0f, 0.0f);
+        s_q[kk][row] = wq;
+        s_r[kk][row] = make_float2(dk * wr.x, dk * wr.y);
+      }
+      __syncthreads();
+      for (int kk = 0; kk < nk; ++kk) {
+        const float2 wq[2] = {s_q[kk][tq], s_q[kk][tq + 16]};
+        const float2 wr[2] = {s_r[kk][tr], s_r[kk][tr + 16]};
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {  // wr conj(wq)
+            acc[a][b].x += wr[b].x * wq[a].x + wr[b].y * wq[a].y;
+            acc[a][b].y += wr[b].y * wq[a].x - wr[b].x * wq[a].y;
+          }
+      }
     }
-    vp[I.vp_off + (int64_t)lv * L * L + q + (int64_t)r * L] = make_float2(cr, ci);
+    float2* out = vp + I.vp_off + (int64_t)lv * L * L;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int q = q0 + tq + 16 * a, r = r0 + tr + 16 * b;
+        if (q < r && r < L) out[q + (int64_t)r * L] = acc[a][b];
+      }
   }
 }
 
@@ -648,8 +689,8 @@ hipError_t launch_nufft_spread(const NufftGeom& g, const NufftInst* insts, int n
 
 hipError_t launch_nufft_vprime(const NufftInst* insts, int n_inst, int max_ant, const void* Wmat, const float* d,
                                const int* order, const int* lstart, int n_levels, void* vp, hipStream_t s) {
-  const int64_t pairs = (int64_t)max_ant * max_ant;
-  hipLaunchKernelGGL(nufft_vprime_kernel, dim3((unsigned)((pairs + 255) / 256), (unsigned)n_inst), dim3(256), 0, s,
+  const int nb = (max_ant + 31) / 32;
+  hipLaunchKernelGGL(nufft_vprime_kernel, dim3((unsigned)(nb * (nb + 1) / 2), (unsigned)n_inst), dim3(256), 0, s,
                      insts, static_cast<const float2*>(Wmat), d, order, lstart, n_levels, static_cast<float2*>(vp));
   return hipGetLastError();
 }

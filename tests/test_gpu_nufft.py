@@ -229,3 +229,50 @@ def test_nufft_thick_grids(ctx, fov_deg, path, transform):
     if fov_deg == 30.0:  # small enough for the FP64 NUFFT oracle on the host
         want_nufft = nf.nufft_images([(x, wl, W, d, member)], pix, eps, X=uvw, frame=frame)
         _check(got, want_nufft, 1e-5)
+
+
+def test_nufft_dense_uv_split_parts(ctx):
+    """Many epochs of a compact array pile baselines into few grid columns, so
+    the output-driven spread splits busy column blocks into parts added with
+    atomics (a column sees more than 4096 baselines); against the FP64 NUFFT
+    oracle and standard synthesis."""
+    from paper_2310_09200_amd import Batch, NufftSynthesis
+    say("case nufft dense uv plane: split column blocks")
+    g = sims.rng(97, 0)
+    L, K, n_ep = 64, 24, 12
+    base = g.uniform(-40.0, 40.0, (L, 3))
+    base[:, 2] = 0.0
+    wl = 2.0
+    pix = sims.pixel_grid(20, 6.0, 90.0)
+    frame = np.array(sims.tangent_basis(90.0))
+    items = []
+    for e in range(n_ep):
+        x = sims.earth_rotate(base, 0.02 * e)
+        W = (g.normal(size=(L, K)) + 1j * g.normal(size=(L, K))) / np.sqrt(2 * L)
+        d = np.exp(g.normal(size=K))
+        lev = np.minimum(np.arange(K) // 8, 2).astype(np.int32)
+        items.append((x, wl, W, d, ref.membership_from_level_of(lev, 3), lev))
+    uvw = np.maximum(_uvw_bound(items, frame), 1.0)  # the array is flat: no extent along p0
+    eps = 1e-4
+    # the busiest grid column must see more than 4096 baselines
+    P = nf.plan_params(eps, uvw, nf.rotate(pix, frame))
+    N, h, wk = P["N"], P["h"], P["w"]
+    cnt = np.zeros((N[0], N[1]), np.int64)
+    for x, wl_, *_ in items:
+        li, mi = np.triu_indices(L, k=1)
+        xi = nf.rotate(x[li] - x[mi], frame) / wl_ / h
+        f0 = np.mod(np.ceil(xi[:, 0] - 0.5 * wk).astype(np.int64), N[0])
+        f1 = np.mod(np.ceil(xi[:, 1] - 0.5 * wk).astype(np.int64), N[1])
+        np.add.at(cnt, (f0, f1), 1)
+    col = sum(np.roll(np.roll(cnt, a, axis=0), c, axis=1) for a in range(wk) for c in range(wk))
+    assert col.max() > 4096, col.max()
+    plan = NufftSynthesis(ctx, pix, 3, L, K, eps, frame, uvw)
+    plan.collect_eig_batched(Batch([(0, x, wl_, W, d, lev) for x, wl_, W, d, _, lev in items], ctx.device))
+    plan.emit()
+    plan.sync()
+    got = plan.images.double().cpu().numpy()
+    plan.close()
+    want_nufft = nf.nufft_images([(x, wl_, W, d, mem) for x, wl_, W, d, mem, _ in items], pix, eps, X=uvw, frame=frame)
+    _check(got, want_nufft, 1e-5)
+    want = sum(ref.synthesize_blas(W, d, mem, x, pix, wl_) for x, wl_, W, d, mem, _ in items)
+    _check_contract(got, want, [(x, wl_, W, d, mem) for x, wl_, W, d, mem, _ in items], eps)
