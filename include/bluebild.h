@@ -287,9 +287,10 @@ bb_status bb_synth_eig_backward(bb_synth h, int32_t n_ant, int32_t n_eig, double
  *   spacing h_d = 1 / (4 S_d) turns, N_d = the least even 2^a 3^b 5^c
  *   >= max(2 w, ceil(8 X_d S_d) + w).
  * Instances collected before one bb_nufft_emit share the grid: the transform,
- * interpolation and correction run once per emit and level.  The grid is
- * accumulated with FP32 atomics, so the last bits of a result vary between
- * runs.  Memory: n_levels N0 N1 N2 complex64 grid cells plus two stage
+ * interpolation and correction run once per emit and level.  Where grid
+ * points are added with FP32 atomics (the busiest parts of the uv plane, and
+ * grids thicker than 32 points along p0) the last bits of a result vary
+ * between runs.  Memory: n_levels N0 N1 N2 complex64 grid cells plus two stage
  * buffers of about N0 M1 M2 / 2 cells each (bb_nufft_workspace_size). */
 typedef struct bb_nufft_* bb_nufft;
 typedef struct {

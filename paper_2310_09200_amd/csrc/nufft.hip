@@ -8,16 +8,19 @@
 //      V'_l[r, q] exp(2 pi i <b, D>) times the tensor-product
 //      exponential-of-semicircle kernel on the w^3 nearest points of the
 //      periodic N0 x N1 x N2 grid (spacing h_d turns), one channel per level.
-//      V'_l[r, q] is formed on the fly from the eigenpairs of the level;
+//      Grids thin along axis 2 are spread from the grid's side
+//      (nufft_gather.hip); thicker ones with LDS tiles or global atomics (here);
 //   2. deconvolve and zero-pad: each level's grid, divided by the type-2
-//      kernel's transform, goes into the centre of an M = 2N grid;
-//   3. FFT (rocFFT, unnormalised, e^{+i});
+//      kernel's transform, placed in an M = 2N grid;
+//   3. inverse FFT (unnormalised, e^{+i}), pruned to the lines that hold data
+//      and the outputs the pixels reach (nufft_fft.hip; rocFFT for long lines);
 //   4. interpolate at each pixel's rescaled position with the same kernel,
 //      divide by the spreading kernel's transform there, and add
 //      2 Re(.) + the diagonal term into the image.
 // The grid is the accumulator over instances: instances collected before one
-// emit share steps 2-4 (the sum is linear).  Grid accumulation uses FP32
-// hardware atomics (its order, and so the last bits, vary between runs).
+// emit share steps 2-4 (the sum is linear).  Where grid points are added with
+// FP32 atomics (split column blocks, tiles, the global-atomic path) their
+// order, and so the last bits, vary between runs.
 
 #include <hip/hip_runtime.h>
 #include <math.h>

@@ -1,6 +1,7 @@
 // Host side of NUFFT synthesis (Section 2.5; Section 3.4, Algorithm 3): plan
-// geometry from the options and the pixels, workspace carving, rocFFT plan,
-// and the spread / emit calls declared in include/bluebild.h.
+// geometry from the options and the pixels, workspace carving, the pruned
+// transform's line-FFT tables (or rocFFT plans), and the spread / emit calls
+// declared in include/bluebild.h.
 
 #include <hip/hip_runtime.h>
 #include <rocfft/rocfft.h>
