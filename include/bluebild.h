@@ -298,7 +298,7 @@ typedef struct {
   int32_t n_ant_max;  /* largest antenna count of an instance, 2..1024 */
   int32_t k_max;      /* largest eigenpair count of an instance, 1..1024 */
   int32_t transform;  /* type-2 transform: 0 = automatic (the library's own LDS line
-                         FFTs when every M_d <= 8192, else rocFFT), 1 = rocFFT */
+                         FFTs when every M_d <= 16384 and fits the device's LDS, else rocFFT), 1 = rocFFT */
   double epsilon;     /* requested accuracy, 1e-7 .. 1e-2 */
   double frame[9];    /* rows e_u, e_v, p0: orthonormal, in the frame of ant_xyz and pix_xyz */
   double uvw_max[3];  /* bound on |<x_q - x_r, frame row d>| / lambda_w over every baseline

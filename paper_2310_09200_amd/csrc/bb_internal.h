@@ -150,7 +150,7 @@ hipError_t launch_nufft_interp(const NufftGeom& g, const InterpLayout& lay, cons
                                int64_t n_pix, const float* u, const double* corr, const double* diag, int lv,
                                float* image, hipStream_t s);
 // Line FFTs of the pruned transform (nufft_fft.hip).
-constexpr int kLineFftMax = 8192;  // longest line held in LDS
+constexpr int kLineFftMax = 16384;  // longest line held in LDS (128 KB)
 struct LineFft {
   int L;                 // transform length (M of the axis)
   int n_in;              // stored inputs per line (N of the axis)
@@ -185,8 +185,8 @@ hipError_t launch_scan_i32(const int* count, int n, int* offset, int* cursor, in
 hipError_t launch_nufft_bin(const NufftGeom& g, const NufftInst* insts, int n_inst, int max_ant, const double* ant,
                             int64_t ld, int bin, int* count, int* offset, int* cursor, uint64_t* list, int* err,
                             int* scan_tmp, hipStream_t s);
-// Output-driven spread (nufft_gather.hip) for grids with N2 <= 32: points of
-// axis 2 per column (8, 16 or 32; 0 = not applicable) and column blocks.
+// Output-driven spread (nufft_gather.hip) for grids with N2 <= 64: points of
+// axis 2 per column (16, 32 or 64; 0 = not applicable) and column blocks.
 int nufft_gather_z(const NufftGeom& g);
 void nufft_gather_blocks(const NufftGeom& g, int& nbx, int& nby);
 constexpr int kGatherRecBytes = 128;  // per sorted baseline

@@ -1,7 +1,7 @@
 // Line FFTs of the NUFFT's pruned type-2 transform (gfx950).
 //
 // Each workgroup transforms one or more lines of L = M points held in LDS
-// (L 2,3,5-smooth, at most 8192).  A line's N stored inputs are placed at
+// (L 2,3,5-smooth, at most 16384).  A line's N stored inputs are placed at
 // their frequencies' positions (index i holds frequency i for i < N/2, else
 // i - N) and divided by the axis's kernel transform on load; the other M - N
 // positions are zero.  The inverse DFT X[m] = sum_n x[n] exp(+2 pi i n m / M)
@@ -17,7 +17,7 @@
 // its Ns (R_s - 1) values exp(2 pi i k r / P), k < Ns, 1 <= r < R_s, at
 // offset Ns - 1 (the earlier passes hold sum (P - Ns) = Ns - 1 of them), so
 // a butterfly reads its R - 1 twiddles as one contiguous run.  Index
-// quotients use an FP32 reciprocal: for j, d <= 8192, (j + 1/2) / d is at
+// quotients use an FP32 reciprocal: for j, d <= 16384, (j + 1/2) / d is at
 // least 1/(2d) from an integer and the rounding error stays below that.
 
 #include <hip/hip_runtime.h>
@@ -112,7 +112,7 @@ __device__ __forceinline__ void small_dft<5>(float2 (&v)[5]) {
   v[3] = csub(r2, j2);
 }
 
-// floor(j / d) for 0 <= j, 1 <= d <= 8192, given inv_d = 1 / d in FP32.
+// floor(j / d) for 0 <= j, 1 <= d <= 16384, given inv_d = 1 / d in FP32.
 __device__ __forceinline__ int quot(int j, float inv_d) { return (int)(((float)j + 0.5f) * inv_d); }
 
 // One in-place decimation-in-time pass of radix R over nl lines of L points

@@ -1,4 +1,5 @@
-// Output-driven spreading of the NUFFT (gfx950) for grids thin along axis 2.
+// Output-driven spreading of the NUFFT (gfx950) for grids of at most 64 points
+// along axis 2.
 //
 // The spread is the same sum as in nufft.hip (every baseline adds its value
 // times the tensor-product kernel on the w^3 grid points nearest to it), but
@@ -50,7 +51,7 @@ struct SrcRec {  // one sorted baseline (128 bytes); k2 and f2 share the first 4
 static_assert(sizeof(SrcRec) == kGatherRecBytes, "record size");
 
 // Columns of a workgroup: 256 threads = (256 / Z) columns x Z points of axis 2
-// (Z = 16 or 32: whole rows of 16 lanes per column).
+// (Z = 16, 32 or 64: whole rows of 16 lanes per column).
 template <int Z>
 struct ColBlock {
   static constexpr int COLS = 256 / Z;
@@ -253,7 +254,7 @@ __global__ __launch_bounds__(256) void nufft_gather_spread_kernel(NufftGeom g, c
 }  // namespace
 
 int nufft_gather_z(const NufftGeom& g) {
-  for (int z : {16, 32})
+  for (int z : {16, 32, 64})
     if (g.N[2] <= z) return z;
   return 0;
 }
@@ -285,8 +286,10 @@ hipError_t launch_nufft_spread_gather(const NufftGeom& g, const NufftInst* insts
     const unsigned pb = (unsigned)((n_blocks + 255) / 256);
     if (Zc == 16)
       hipLaunchKernelGGL((nufft_block_parts_kernel<KW, 16>), dim3(pb), dim3(256), 0, s, g, offset, nbx, nby, nparts);
-    else
+    else if (Zc == 32)
       hipLaunchKernelGGL((nufft_block_parts_kernel<KW, 32>), dim3(pb), dim3(256), 0, s, g, offset, nbx, nby, nparts);
+    else
+      hipLaunchKernelGGL((nufft_block_parts_kernel<KW, 64>), dim3(pb), dim3(256), 0, s, g, offset, nbx, nby, nparts);
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;
@@ -311,7 +314,9 @@ hipError_t launch_nufft_spread_gather(const NufftGeom& g, const NufftInst* insts
       default: return run(zc, std::integral_constant<int, 16>{});
     }
   };
-  return Zc == 16 ? by_levels(std::integral_constant<int, 16>{}) : by_levels(std::integral_constant<int, 32>{});
+  if (Zc == 16) return by_levels(std::integral_constant<int, 16>{});
+  if (Zc == 32) return by_levels(std::integral_constant<int, 32>{});
+  return by_levels(std::integral_constant<int, 64>{});
 }
 
 }  // namespace bb

@@ -197,12 +197,13 @@ def test_nufft_rejects_bad_options(ctx):
 
 @pytest.mark.parametrize("transform", ["auto", "rocfft"])
 @pytest.mark.parametrize("fov_deg,path", [(20.0, "output-driven, two rows per column"),
-                                          (30.0, "tiles of 8 grid points"), (60.0, "global atomics")])
+                                          (30.0, "output-driven, four rows per column"),
+                                          (45.0, "tiles of 8 grid points"), (60.0, "global atomics")])
 def test_nufft_thick_grids(ctx, fov_deg, path, transform):
     """A 3-D antenna cloud and a wide field make the grid thick along p0: the
-    output-driven spread with 32 lanes per column (16 < N2 <= 32), smaller LDS
-    tiles (32 < N2 <= 128) or, past 128 points, global atomics; against
-    standard synthesis."""
+    output-driven spread with 32 or 64 lanes per column (16 < N2 <= 64), LDS
+    tiles of 8 points (64 < N2 <= 128) or, past 128 points, global atomics;
+    against standard synthesis."""
     from paper_2310_09200_amd import Batch, NufftSynthesis
     say(f"case nufft thick grid, field {fov_deg} deg ({path}), transform {transform}")
     g = sims.rng(96, int(fov_deg))
@@ -220,7 +221,7 @@ def test_nufft_thick_grids(ctx, fov_deg, path, transform):
     eps = 1e-4
     plan = NufftSynthesis(ctx, pix, 3, L, K, eps, frame, uvw, transform=transform)
     N, M, wk = plan.shape
-    assert {20.0: 16 < N[2] <= 32, 30.0: 32 < N[2] <= 128, 60.0: N[2] > 128}[fov_deg], N
+    assert {20.0: 16 < N[2] <= 32, 30.0: 32 < N[2] <= 64, 45.0: 64 < N[2] <= 128, 60.0: N[2] > 128}[fov_deg], N
     plan.collect_eig_batched(Batch([(0, x, wl, W, d, lev)], ctx.device))
     plan.emit()
     plan.sync()
