@@ -216,7 +216,8 @@ def measure_nufft(args, torch, ctx):
     uvw = uvw * 1.001
 
     s = StandardSynthesis(ctx, w.pix, n_levels, 1, 512, 512, args.precision)
-    plan = NufftSynthesis(ctx, w.pix, n_levels, 512, 512, args.nufft_eps, frame, uvw, transform=args.nufft_transform)
+    plan = NufftSynthesis(ctx, w.pix, n_levels, 512, 512, args.nufft_eps, frame, uvw, transform=args.nufft_transform,
+                          partitions=args.nufft_partitions)
     N, M, kw = plan.shape
     s.collect_eig_batched(batch)
     plan.collect_eig_batched(batch)
@@ -252,7 +253,7 @@ def measure_nufft(args, torch, ctx):
     s.close()
     plan.close()
     prods = batch.products * w.n_pix
-    log(f"NUFFT {side}^2: standard {np.mean(std_ms):.1f} ms, NUFFT {np.mean(nu_ms):.1f} ms "
+    log(f"NUFFT {side}^2 ({args.nufft_partitions}x{args.nufft_partitions} partitions): standard {np.mean(std_ms):.1f} ms, NUFFT {np.mean(nu_ms):.1f} ms "
         f"(spread {np.mean(spread_ms):.1f}, emit {np.mean(emit_ms):.1f}), grid {N} fft {M} w={kw}, "
         f"max level diff {max(errs):.2e}")
     return {"workload": f"SKA-Low-like 512 stations (65 km), 50 epochs over 6 h, {side}x{side} pixels of 4 arcsec "
@@ -262,6 +263,7 @@ def measure_nufft(args, torch, ctx):
             "nufft_ms": float(np.mean(nu_ms)), "nufft_spread_ms": float(np.mean(spread_ms)),
             "nufft_emit_ms": float(np.mean(emit_ms)), "speedup_nufft_over_standard": float(np.mean(std_ms) / np.mean(nu_ms)),
             "products": prods, "standard_products_per_s": prods / (np.mean(std_ms) / 1e3),
+            "partitions": args.nufft_partitions,
             "transform": {"auto": "pruned, own LDS line FFTs where every axis fits, else rocFFT",
                           "rocfft": "pruned, rocFFT"}[args.nufft_transform],
             "max_level_diff_nufft_vs_standard": max(errs)}
@@ -329,6 +331,8 @@ def main():
     ap.add_argument("--nufft-eps", type=float, default=1e-5)
     ap.add_argument("--nufft-transform", choices=["auto", "rocfft"], default="auto",
                     help="type-2 transform of the NUFFT comparison")
+    ap.add_argument("--nufft-partitions", type=int, default=1,
+                    help="image-domain partitions per axis of the NUFFT comparison")
     ap.add_argument("--only-nufft", action="store_true",
                     help="print only the NUFFT-vs-standard measurement (for profiling it alone)")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,

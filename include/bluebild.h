@@ -304,6 +304,12 @@ typedef struct {
   double uvw_max[3];  /* bound on |<x_q - x_r, frame row d>| / lambda_w over every baseline
                          to be collected (wavelengths); a baseline beyond it is skipped and
                          reported by bb_nufft_sync */
+  int32_t partitions; /* image-domain partitions per axis, 0..8 (0 and 1: one grid).  With
+                         P > 1 the pixels are split into P x P tiles of the (e_u, e_v)
+                         extent, each imaged by its own NUFFT (grid sized to the tile;
+                         Section 3.4.1): every baseline is spread once per tile, and a wide
+                         field gets thinner, smaller grids */
+  int32_t reserved;   /* must be 0 */
 } bb_nufft_options;
 
 /* Workspace bytes of a plan.  pix_host: host, n_pix x 3 float64 column-major,
@@ -318,7 +324,8 @@ bb_status bb_nufft_workspace_size(bb_context ctx, const bb_nufft_options* opt, i
  * ws_bytes >= bb_nufft_workspace_size(...).  Waits for its set-up work. */
 bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix, const double* pix_host,
                           const double* pix_xyz, float* images, void* workspace, size_t ws_bytes, bb_nufft* out);
-/* Grid sizes (N, M, 3 values each) and kernel support of a plan; NULL outputs are skipped. */
+/* Grid sizes (N, M, 3 values each) and kernel support of a plan (of its largest
+ * partition when partitioned); NULL outputs are skipped. */
 bb_status bb_nufft_shape(bb_nufft h, int32_t* spread_grid, int32_t* fft_grid, int32_t* kernel_width);
 /* Spread instances onto the grid; packed arrays and descriptors as for
  * bb_synth_collect_eig_batched (slot must be 0, n_ant >= 2).  workspace:

@@ -175,6 +175,12 @@ hipError_t launch_transpose_c64(const void* in, int64_t rows, int64_t cols, void
 hipError_t launch_nufft_corr(const NufftGeom& g, const double* pix, int64_t pix_ld, int64_t n_pix, const double* quad_t,
                              const double* quad_wphi, int n_quad, double* corr, hipStream_t s);
 hipError_t launch_fill_zero_f64(double* p, int n, hipStream_t s);
+// Image-domain partitions of a NUFFT plan: out[p + d n] = pix[idx[p] + d ld];
+// images[l ld + idx[p]] += part_img[l n + p], then part_img = 0.
+hipError_t launch_nufft_gather_pix(const double* pix, int64_t ld, const int64_t* idx, int64_t n, double* out,
+                                   hipStream_t s);
+hipError_t launch_nufft_scatter_images(float* part_img, int64_t n, int n_levels, const int64_t* idx, float* images,
+                                       int64_t ld, hipStream_t s);
 hipError_t launch_nufft_vprime(const NufftInst* insts, int n_inst, int max_ant, const void* Wmat, const float* d,
                                const int* order, const int* lstart, int n_levels, void* vp, hipStream_t s);
 int nufft_tile_size(const NufftGeom& g);  // 16 or 8 grid points per tile side, 0 = no tiled path

@@ -761,6 +761,45 @@ hipError_t launch_nufft_spread_tiles(const NufftGeom& g, const NufftInst* insts,
 
 static unsigned grid_blocks(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 65536); }
 
+// Image-domain partitions: the pixels of one partition gathered into their own
+// column-major array, and its level images added into the plan's images (each
+// pixel belongs to one partition) and cleared.
+__global__ __launch_bounds__(256) void nufft_gather_pix_kernel(const double* __restrict__ pix, int64_t ld,
+                                                               const int64_t* __restrict__ idx, int64_t n,
+                                                               double* __restrict__ out) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx[p];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) out[p + d * n] = pix[i + d * ld];
+  }
+}
+
+__global__ __launch_bounds__(256) void nufft_scatter_images_kernel(float* __restrict__ part_img, int64_t n,
+                                                                   int n_levels, const int64_t* __restrict__ idx,
+                                                                   float* __restrict__ images, int64_t ld) {
+  const int64_t total = n * n_levels;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = e / n, p = e - l * n;
+    images[l * ld + idx[p]] += part_img[e];
+    part_img[e] = 0.0f;
+  }
+}
+
+hipError_t launch_nufft_gather_pix(const double* pix, int64_t ld, const int64_t* idx, int64_t n, double* out,
+                                   hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(nufft_gather_pix_kernel, dim3(grid_blocks(n)), dim3(256), 0, s, pix, ld, idx, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_nufft_scatter_images(float* part_img, int64_t n, int n_levels, const int64_t* idx, float* images,
+                                       int64_t ld, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(nufft_scatter_images_kernel, dim3(grid_blocks(n * n_levels)), dim3(256), 0, s, part_img, n,
+                     n_levels, idx, images, ld);
+  return hipGetLastError();
+}
+
 hipError_t launch_nufft_gather(int axis, const NufftGeom& g, const void* src, const float* inv_psi, void* dst,
                                hipStream_t s) {
   if (axis == 2) {

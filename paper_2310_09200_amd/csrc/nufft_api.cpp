@@ -126,6 +126,8 @@ bb_status nufft_geometry(bb_context ctx, const bb_nufft_options* o, int64_t n_pi
     return fail(ctx, BB_ERR_INVALID_ARG, "n_ant_max must be in [2, %d]", bb::kMaxAnt);
   if (o->k_max < 1 || o->k_max > bb::kMaxEig) return fail(ctx, BB_ERR_INVALID_ARG, "k_max must be in [1, %d]", bb::kMaxEig);
   if (o->transform != 0 && o->transform != 1) return fail(ctx, BB_ERR_INVALID_ARG, "transform must be 0 or 1");
+  if (o->partitions < 0 || o->partitions > 8) return fail(ctx, BB_ERR_INVALID_ARG, "partitions must be in [0, 8]");
+  if (o->reserved != 0) return fail(ctx, BB_ERR_INVALID_ARG, "reserved must be 0");
   if (!(o->epsilon >= 1e-7 && o->epsilon <= 1e-2)) return fail(ctx, BB_ERR_INVALID_ARG, "epsilon must be in [1e-7, 1e-2]");
   for (int i = 0; i < 3; ++i)
     if (!finite_pos(o->uvw_max[i])) return fail(ctx, BB_ERR_INVALID_ARG, "uvw_max must be finite and > 0");
@@ -274,8 +276,18 @@ rocfft_status g_rocfft_setup = rocfft_status_success;
 
 }  // namespace
 
+// One image-domain partition of a plan: an ordinary plan over its pixels,
+// whose images are added into the partitioned plan's images after each emit.
+struct NufftPart {
+  bb_nufft sub = nullptr;
+  int64_t n = 0;    // pixels
+  int64_t* idx;     // device: indices of its pixels in the plan's pixel list
+  float* img;       // device: its level images [n_levels][n]
+};
+
 struct bb_nufft_ {
   bb_context ctx = nullptr;
+  std::vector<NufftPart> parts;  // non-empty: a partitioned plan (the fields below describe its largest part)
   bb_nufft_options opt{};
   bb::NufftGeom g{};
   int64_t n_pix = 0;
@@ -299,6 +311,140 @@ T* nat(bb_nufft h, size_t off) {
   return reinterpret_cast<T*>(h->ws + off);
 }
 
+// ---- image-domain partitions (Section 3.4.1) --------------------------------
+// The pixels are split into P x P tiles of their extent along e_u and e_v;
+// each nonempty tile gets an ordinary plan (grid sized to the tile) with its
+// own pixel array, images and workspace, all carved from the caller's
+// workspace.
+struct PartLayout {
+  std::vector<std::vector<int64_t>> tiles;  // pixel indices per nonempty tile
+  std::vector<std::vector<double>> pix;     // host copy of each tile's pixels (column-major)
+  std::vector<size_t> idx, px, img, ws, ws_bytes;
+  size_t total = 0;
+};
+
+bb_status part_layout(bb_context ctx, const bb_nufft_options* o, int64_t n_pix, const double* pix_host,
+                      PartLayout& L) {
+#pragma clang fp contract(off)
+  bb_nufft_options one = *o;
+  one.partitions = 1;
+  bb::NufftGeom g;
+  bb_status st = nufft_geometry(ctx, &one, n_pix, pix_host, g);  // validates the options and every pixel
+  if (st != BB_OK) return st;
+  const int P = o->partitions;
+  std::vector<double> u(n_pix), v(n_pix);
+  double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
+  for (int64_t p = 0; p < n_pix; ++p) {
+    const double a0 = pix_host[p], a1 = pix_host[p + n_pix], a2 = pix_host[p + 2 * n_pix];
+    u[p] = (a0 * o->frame[0] + a1 * o->frame[1]) + a2 * o->frame[2];
+    v[p] = (a0 * o->frame[3] + a1 * o->frame[4]) + a2 * o->frame[5];
+    lo[0] = std::min(lo[0], u[p]);
+    hi[0] = std::max(hi[0], u[p]);
+    lo[1] = std::min(lo[1], v[p]);
+    hi[1] = std::max(hi[1], v[p]);
+  }
+  auto cell = [&](double x, int d) {
+    const double span = hi[d] - lo[d];
+    if (!(span > 0.0)) return 0;
+    return std::min(P - 1, std::max(0, (int)((x - lo[d]) / span * P)));
+  };
+  std::vector<std::vector<int64_t>> t(P * P);
+  for (int64_t p = 0; p < n_pix; ++p) t[cell(u[p], 0) * P + cell(v[p], 1)].push_back(p);
+  size_t off = 0;
+  for (auto& tile : t) {
+    if (tile.empty()) continue;
+    const int64_t n = (int64_t)tile.size();
+    std::vector<double> px(3 * n);
+    for (int64_t i = 0; i < n; ++i)
+      for (int d = 0; d < 3; ++d) px[i + d * n] = pix_host[tile[i] + d * n_pix];
+    size_t b = 0;
+    st = bb_nufft_workspace_size(ctx, &one, n, px.data(), &b);
+    if (st != BB_OK) return st;
+    L.idx.push_back(off);
+    off += align_up(8 * (size_t)n);
+    L.px.push_back(off);
+    off += align_up(24 * (size_t)n);
+    L.img.push_back(off);
+    off += align_up(4 * (size_t)o->n_levels * n);
+    L.ws.push_back(off);
+    L.ws_bytes.push_back(b);
+    off += align_up(b);
+    L.tiles.push_back(std::move(tile));
+    L.pix.push_back(std::move(px));
+  }
+  L.total = off;
+  return BB_OK;
+}
+
+bb_status part_destroy(bb_nufft h) {
+  bb_context ctx = h->ctx;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  for (NufftPart& q : h->parts)
+    if (q.sub) bb_nufft_destroy(q.sub);
+  for (hipEvent_t& e : h->ev)
+    if (e) hipEventDestroy(e);
+  delete h;
+  return BB_OK;
+}
+
+bb_status part_create(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix, const double* pix_host,
+                      const double* pix_xyz, float* images, void* workspace, size_t ws_bytes, bb_nufft* out) {
+  PartLayout L;
+  bb_status st = part_layout(ctx, opt, n_pix, pix_host, L);
+  if (st != BB_OK) return st;
+  if (!pix_xyz || !images || !workspace) return fail(ctx, BB_ERR_INVALID_ARG, "null device pointer");
+  if (reinterpret_cast<uintptr_t>(workspace) % bb_host::kAlign)
+    return fail(ctx, BB_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total) return fail(ctx, BB_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  bb_nufft h = new (std::nothrow) bb_nufft_;
+  if (!h) return fail(ctx, BB_ERR_DEVICE, "out of host memory");
+  h->ctx = ctx;
+  h->opt = *opt;
+  h->n_pix = n_pix;
+  h->pix = pix_xyz;
+  h->images = images;
+  h->ws = static_cast<char*>(workspace);
+  for (hipEvent_t& e : h->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      part_destroy(h);
+      return fail(ctx, BB_ERR_DEVICE, "hipEventCreate failed");
+    }
+  bb_nufft_options one = *opt;
+  one.partitions = 1;
+  hipStream_t s = ctx->stream;
+  int64_t biggest = -1;
+  for (size_t t = 0; t < L.tiles.size(); ++t) {
+    NufftPart q;
+    q.n = (int64_t)L.tiles[t].size();
+    q.idx = nat<int64_t>(h, L.idx[t]);
+    q.img = nat<float>(h, L.img[t]);
+    double* px = nat<double>(h, L.px[t]);
+    // pageable source: the copy is staged before the call returns
+    if (hipMemcpyAsync(q.idx, L.tiles[t].data(), 8 * (size_t)q.n, hipMemcpyHostToDevice, s) != hipSuccess ||
+        bb::launch_nufft_gather_pix(pix_xyz, n_pix, q.idx, q.n, px, s) != hipSuccess ||
+        bb::launch_fill_zero(q.img, (int64_t)opt->n_levels * q.n, s) != hipSuccess) {
+      part_destroy(h);
+      return fail(ctx, BB_ERR_DEVICE, "partition set-up failed");
+    }
+    st = bb_nufft_create(ctx, &one, q.n, L.pix[t].data(), px, q.img, h->ws + L.ws[t], L.ws_bytes[t], &q.sub);
+    if (st != BB_OK) {
+      part_destroy(h);
+      return st;
+    }
+    const int64_t cells = (int64_t)q.sub->g.N[0] * q.sub->g.N[1] * q.sub->g.N[2];
+    if (cells > biggest) {
+      biggest = cells;
+      h->g = q.sub->g;
+    }
+    h->parts.push_back(q);
+  }
+  ctx->live += 1;
+  *out = h;
+  return BB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -306,6 +452,12 @@ extern "C" {
 bb_status bb_nufft_workspace_size(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix, const double* pix_host,
                                   size_t* bytes) {
   if (!ctx || !bytes) return BB_ERR_INVALID_ARG;
+  if (opt && opt->partitions > 1) {
+    PartLayout L;
+    const bb_status st = part_layout(ctx, opt, n_pix, pix_host, L);
+    if (st == BB_OK) *bytes = L.total;
+    return st;
+  }
   bb::NufftGeom g;
   bb_status st = nufft_geometry(ctx, opt, n_pix, pix_host, g);
   if (st != BB_OK) return st;
@@ -325,6 +477,8 @@ bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n
                           const double* pix_xyz, float* images, void* workspace, size_t ws_bytes, bb_nufft* out) {
   if (!ctx || !out) return BB_ERR_INVALID_ARG;
   *out = nullptr;
+  if (opt && opt->partitions > 1)
+    return part_create(ctx, opt, n_pix, pix_host, pix_xyz, images, workspace, ws_bytes, out);
   bb::NufftGeom g;
   bb_status st = nufft_geometry(ctx, opt, n_pix, pix_host, g);
   if (st != BB_OK) return st;
@@ -539,6 +693,12 @@ extern "C" {
 
 bb_status bb_nufft_batched_workspace_size(bb_nufft h, int32_t n_inst, const bb_instance* inst, size_t* bytes) {
   if (!h || !bytes || n_inst < 1 || !inst) return BB_ERR_INVALID_ARG;
+  if (!h->parts.empty()) {  // the parts run one after another on the stream: the largest need
+    size_t most = 0;
+    for (NufftPart& q : h->parts) most = std::max(most, call_layout(q.sub, n_inst, inst).total);
+    *bytes = most;
+    return BB_OK;
+  }
   *bytes = call_layout(h, n_inst, inst).total;
   return BB_OK;
 }
@@ -548,6 +708,19 @@ bb_status bb_nufft_collect_eig_batched(bb_nufft h, int32_t n_inst, const bb_inst
                                        const int32_t* level_packed, void* workspace, size_t ws_bytes) {
   if (!h) return BB_ERR_INVALID_ARG;
   bb_context ctx = h->ctx;
+  if (!h->parts.empty()) {
+    BB_HIP(ctx, hipSetDevice(ctx->device));
+    BB_HIP(ctx, hipEventRecord(h->ev[0], ctx->stream));
+    for (NufftPart& q : h->parts) {
+      const bb_status st = bb_nufft_collect_eig_batched(q.sub, n_inst, inst, n_ant_rows, ant_xyz_packed, W_packed,
+                                                        d_packed, level_packed, workspace, ws_bytes);
+      if (st != BB_OK) return st;
+    }
+    BB_HIP(ctx, hipEventRecord(h->ev[1], ctx->stream));
+    h->spread_timed = true;
+    h->count += n_inst;
+    return BB_OK;
+  }
   if (n_inst < 1 || n_inst > 65535 || !inst) return fail(ctx, BB_ERR_INVALID_ARG, "n_inst must be in [1, 65535]");
   if (!ant_xyz_packed || !W_packed || !d_packed || !level_packed || !workspace)
     return fail(ctx, BB_ERR_INVALID_ARG, "null device pointer");
@@ -635,6 +808,20 @@ bb_status bb_nufft_collect_eig_batched(bb_nufft h, int32_t n_inst, const bb_inst
 bb_status bb_nufft_emit(bb_nufft h) {
   if (!h) return BB_ERR_INVALID_ARG;
   bb_context ctx = h->ctx;
+  if (!h->parts.empty()) {
+    BB_HIP(ctx, hipSetDevice(ctx->device));
+    BB_HIP(ctx, hipEventRecord(h->ev[2], ctx->stream));
+    for (NufftPart& q : h->parts) {
+      const bb_status st = bb_nufft_emit(q.sub);
+      if (st != BB_OK) return st;
+      BB_HIP(ctx, bb::launch_nufft_scatter_images(q.img, q.n, h->opt.n_levels, q.idx, h->images, h->n_pix,
+                                                  ctx->stream));
+    }
+    BB_HIP(ctx, hipEventRecord(h->ev[3], ctx->stream));
+    h->emit_timed = true;
+    h->count = 0;
+    return BB_OK;
+  }
   BB_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   const bb::NufftGeom& g = h->g;
@@ -690,6 +877,14 @@ bb_status bb_nufft_emit(bb_nufft h) {
 bb_status bb_nufft_sync(bb_nufft h) {
   if (!h) return BB_ERR_INVALID_ARG;
   bb_context ctx = h->ctx;
+  if (!h->parts.empty()) {  // every part's error word is read and cleared
+    bb_status first = BB_OK;
+    for (NufftPart& q : h->parts) {
+      const bb_status st = bb_nufft_sync(q.sub);
+      if (first == BB_OK) first = st;
+    }
+    return first;
+  }
   BB_HIP(ctx, hipSetDevice(ctx->device));
   BB_HIP(ctx, hipStreamSynchronize(ctx->stream));
   int err = 0;
@@ -722,6 +917,10 @@ bb_status bb_nufft_timings(bb_nufft h, double* ms_out, int32_t n) {
 bb_status bb_nufft_destroy(bb_nufft h) {
   if (!h) return BB_ERR_INVALID_ARG;
   bb_context ctx = h->ctx;
+  if (!h->parts.empty()) {
+    ctx->live -= 1;
+    return part_destroy(h);
+  }
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
   if (h->info) rocfft_execution_info_destroy(h->info);

@@ -279,3 +279,53 @@ def test_nufft_dense_uv_split_parts(ctx):
     _check(got, want_nufft, 1e-5)
     want = sum(ref.synthesize_blas(W, d, mem, x, pix, wl_) for x, wl_, W, d, mem, _ in items)
     _check_contract(got, want, [(x, wl_, W, d, mem) for x, wl_, W, d, mem, _ in items], eps)
+
+
+def _tiles(pix, frame, P):
+    """Pixel indices of the nonempty P x P tiles of the field along e_u, e_v (the library's split)."""
+    u = (pix[:, 0] * frame[0, 0] + pix[:, 1] * frame[0, 1]) + pix[:, 2] * frame[0, 2]
+    v = (pix[:, 0] * frame[1, 0] + pix[:, 1] * frame[1, 1]) + pix[:, 2] * frame[1, 2]
+
+    def cell(x):
+        span = x.max() - x.min()
+        if not span > 0:
+            return np.zeros(x.shape, np.int64)
+        return np.clip(((x - x.min()) / span * P).astype(np.int64), 0, P - 1)
+
+    key = cell(u) * P + cell(v)
+    return [np.nonzero(key == k)[0] for k in range(P * P) if np.any(key == k)]
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_nufft_image_partitions(ctx, P):
+    """Image-domain partitions: every tile of the field is its own NUFFT (grid
+    sized to the tile); a cross of pixels leaves the corner tiles empty.  Each
+    tile against the FP64 NUFFT oracle on its pixels, the whole against
+    standard synthesis."""
+    from paper_2310_09200_amd import Batch, NufftSynthesis
+    say(f"case nufft image partitions {P} x {P}")
+    pix_all, items, n_levels = _instances(2, [48, 40], 40, 3, 4, fov_deg=12.0)
+    frame = np.array(sims.tangent_basis(90.0))
+    uv = nf.rotate(pix_all, frame)[:, :2]
+    half = np.abs(uv).max()
+    pix = pix_all[(np.abs(uv[:, 0]) < 0.3 * half) | (np.abs(uv[:, 1]) < 0.3 * half)]
+    uvw = np.maximum(_uvw_bound(items, frame), 1.0)
+    eps = 1e-5
+    plan = NufftSynthesis(ctx, pix, n_levels, 64, 64, eps, frame, uvw, partitions=P)
+    plan_one = NufftSynthesis(ctx, pix, n_levels, 64, 64, eps, frame, uvw)
+    assert np.prod(plan.shape[0]) < np.prod(plan_one.shape[0])
+    plan_one.close()
+    b = Batch([(0, x, wl, W, d, lev) for x, wl, W, d, _, lev in items], ctx.device)
+    plan.collect_eig_batched(b)
+    plan.emit()
+    plan.sync()
+    got = plan.images.double().cpu().numpy()
+    plan.close()
+    tiles = _tiles(pix, frame, P)
+    assert sum(len(t) for t in tiles) == pix.shape[0] and len(tiles) == (P * P if P < 4 else P * P - 4)
+    insts = [(x, wl, W, d, mem) for x, wl, W, d, mem, _ in items]
+    for t in tiles:
+        want_t = nf.nufft_images(insts, pix[t], eps, X=uvw, frame=frame)
+        _check(got[:, t], want_t, 1e-5)
+    want = sum(ref.synthesize_blas(W, d, mem, x, pix, wl) for x, wl, W, d, mem, _ in items)
+    _check_contract(got, want, insts, eps)
