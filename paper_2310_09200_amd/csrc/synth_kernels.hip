@@ -30,6 +30,7 @@ namespace bb {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
@@ -39,6 +40,7 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 // for an LDS read would also wait for the prefetched W operand.  Casting them
 // to the global address space makes those loads vector-memory loads only.
 #define BB_GLOBAL __attribute__((address_space(1)))
+#define BB_LDS __attribute__((address_space(3)))
 template <class T>
 __device__ __forceinline__ const BB_GLOBAL T* as_global(const void* p) {
   return (const BB_GLOBAL T*)p;
@@ -48,7 +50,8 @@ __device__ __forceinline__ const BB_GLOBAL T* as_global(const void* p) {
 // phase in turns.  The reduction t - rint(t) is exact in FP64 and leaves
 // f in [-1/2, 1/2]; gfx950's transcendental unit takes its sine and cosine
 // argument in turns (sin(2 pi f)), with an absolute error near 1.3e-7 there.
-__device__ __forceinline__ void phase_pair(const BB_GLOBAL double* __restrict__ xs, double px, double py, double pz,
+// xs points into the workgroup's LDS copy of the instance's positions.
+__device__ __forceinline__ void phase_pair(const BB_LDS double* __restrict__ xs, double px, double py, double pz,
                                            float& c, float& s) {
   const double t = fma(xs[2], pz, fma(xs[1], py, xs[0] * px));
   const float f = (float)(t - rint(t));
@@ -324,7 +327,7 @@ struct TileCfg {
   static constexpr int TASKS = NT * G4;           // (pixel, 4-antenna) phase tasks per chunk
   static constexpr int JT = (TASKS + THREADS - 1) / THREADS;
   static_assert(THREADS % NT == 0, "a thread keeps one pixel");
-  static_assert(TASKS % THREADS == 0 || TASKS < THREADS, "task split");
+  static_assert(TASKS % THREADS == 0, "task split");
   static_assert(kAntChunk % LCH == 0, "antenna padding covers the chunk");
 };
 
@@ -338,25 +341,57 @@ struct ChunkVec {  // 16-byte vectors per LDS phase chunk
   static constexpr int N = PREC >= 2 ? 3 * C::LCH * C::NT / 4 : C::CHUNK_VEC;
 };
 
+// A thread's share of a phase chunk: JT tasks of 4 (antenna, pixel) pairs, one
+// pixel per task.  The pairs of a task are laid out so that each task fills
+// whole 16-byte vectors of the chunk's MFMA operand layout.
+template <class C>
+__device__ __forceinline__ int gen_group(int tid, int j) {  // antenna group of task j
+  const int t = tid + j * C::THREADS;
+  // wave-uniform when a wave's 64 lanes share one antenna group
+  return C::NT % 64 == 0 ? __builtin_amdgcn_readfirstlane(t / C::NT) : t / C::NT;
+}
+
+// Antenna (within the chunk) of pair s of a task in antenna group g4.
+template <int PREC>
+__device__ __forceinline__ int gen_antenna(int g4, int s) {
+  if (PREC == 3) {
+    // lane (h, jj) of a plane holds antennas 16 g16 + 8 h + e, e = 0..7; a task
+    // fills e = 4 half .. 4 half + 3 (8 bytes of each 16-byte operand)
+    const int g16 = g4 >> 2, h = (g4 >> 1) & 1, half = g4 & 1;
+    return 16 * g16 + 8 * h + 4 * half + s;
+  }
+  if (PREC == 2) return 8 * (g4 >> 1) + 2 * s + (g4 & 1);  // one lane of each of the three B planes
+  return 4 * g4 + s;
+}
+
+// Phase pairs first .. first + count - 1 (pair q = pair q % 4 of task q / 4) of
+// this thread's share of a chunk, into registers.
 template <class C, int PREC>
-__device__ __forceinline__ void gen_chunk(f32x4* __restrict__ buf, const BB_GLOBAL double* __restrict__ xs_chunk,
-                                          double px, double py, double pz, int tid) {
+__device__ __forceinline__ void gen_pairs(float (&cr)[4 * C::JT], float (&ci)[4 * C::JT],
+                                          const BB_LDS double* __restrict__ xs_chunk, double px, double py,
+                                          double pz, int tid, int first, int count) {
+#pragma unroll
+  for (int q = 0; q < 4 * C::JT; ++q)
+    if (q >= first && q < first + count)
+      phase_pair(xs_chunk + 4 * gen_antenna<PREC>(gen_group<C>(tid, q >> 2), q & 3), px, py, pz, cr[q], ci[q]);
+}
+
+// This thread's share of a chunk from its phase pairs into the LDS operand
+// layout of the precision: (Br, Bi) vectors (FP32), interleaved BF16 hi / lo
+// vectors (BF16 x3), or the three planes Br, Bi - Br, Br + Bi (three products).
+template <class C, int PREC>
+__device__ __forceinline__ void gen_store(f32x4* __restrict__ buf, const float (&pr)[4 * C::JT],
+                                          const float (&pi)[4 * C::JT], int tid) {
+  static_assert(C::TASKS % C::THREADS == 0, "whole tasks per thread");
 #pragma unroll
   for (int j = 0; j < C::JT; ++j) {
-    const int t = tid + j * C::THREADS;
-    if (C::TASKS < C::THREADS && t >= C::TASKS) break;
-    const int pl = t % C::NT;
-    // wave-uniform when a wave's 64 lanes share one antenna group
-    const int g4 = C::NT % 64 == 0 ? __builtin_amdgcn_readfirstlane(t / C::NT) : t / C::NT;
+    const int pl = (tid + j * C::THREADS) % C::NT;
+    const int g4 = gen_group<C>(tid, j);
     const int cb = pl >> 5, jj = pl & 31;
-    float cr[4], ci[4];
+    const float* cr = pr + 4 * j;
+    const float* ci = pi + 4 * j;
     if (PREC == 3) {
-      // lane (h, jj) of a plane holds antennas 16 g16 + 8 h + e, e = 0..7; this
-      // task fills e = 4 half .. 4 half + 3 (8 bytes of each 16-byte operand)
       const int g16 = g4 >> 2, h = (g4 >> 1) & 1, half = g4 & 1;
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-        phase_pair(xs_chunk + 4 * (16 * g16 + 8 * h + 4 * half + s), px, py, pz, cr[s], ci[s]);
       bf16x4* b4 = (bf16x4*)buf;
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
@@ -372,24 +407,15 @@ __device__ __forceinline__ void gen_chunk(f32x4* __restrict__ buf, const BB_GLOB
         b4[o] = hi;
         b4[o + 128] = lo;
       }
-      continue;
-    }
-    if (PREC == 2) {
-      // antennas 8 g8 + 2 s + h (s = 0..3): one lane of each of the three B planes
+    } else if (PREC == 2) {
       const int g8 = g4 >> 1, h = g4 & 1;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) phase_pair(xs_chunk + 4 * (8 * g8 + 2 * s + h), px, py, pz, cr[s], ci[s]);
       f32x4 vr = {cr[0], cr[1], cr[2], cr[3]};
       f32x4 vd = {ci[0] - cr[0], ci[1] - cr[1], ci[2] - cr[2], ci[3] - cr[3]};
       f32x4 vs = {cr[0] + ci[0], cr[1] + ci[1], cr[2] + ci[2], cr[3] + ci[3]};
       buf[((g8 * 3 + 0) * C::NCB + cb) * 64 + h * 32 + jj] = vr;
       buf[((g8 * 3 + 1) * C::NCB + cb) * 64 + h * 32 + jj] = vd;
       buf[((g8 * 3 + 2) * C::NCB + cb) * 64 + h * 32 + jj] = vs;
-      continue;
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s) phase_pair(xs_chunk + 4 * (4 * g4 + s), px, py, pz, cr[s], ci[s]);
-    if (PREC == 0) {
+    } else if (PREC == 0) {
       f32x4 vr = {cr[0], cr[1], cr[2], cr[3]};
       f32x4 vi = {ci[0], ci[1], ci[2], ci[3]};
       buf[(g4 * C::NCB + cb) * 64 + jj] = vr;
@@ -410,6 +436,14 @@ __device__ __forceinline__ void gen_chunk(f32x4* __restrict__ buf, const BB_GLOB
       b16[((g8 * C::NCB + cb) * 2 + 1) * 64 + h * 32 + jj] = lo;
     }
   }
+}
+
+template <class C, int PREC>
+__device__ __forceinline__ void gen_chunk(f32x4* __restrict__ buf, const BB_LDS double* __restrict__ xs_chunk,
+                                          double px, double py, double pz, int tid) {
+  float cr[4 * C::JT], ci[4 * C::JT];
+  gen_pairs<C, PREC>(cr, ci, xs_chunk, px, py, pz, tid, 0, 4 * C::JT);
+  gen_store<C, PREC>(buf, cr, ci, tid);
 }
 
 // A operand (the W^H side) of one MFMA group: 4 contraction steps of the
@@ -564,6 +598,11 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
   constexpr int NA = Acc<PREC>::N;
   constexpr int NG = NGroups<C, PREC>::N;
   __shared__ float s_part[WK][kMaxLevels][C::NT];
+  // scaled positions of the current instance, (x, y, z, 0) per antenna: every
+  // phase chunk reads them from here (a broadcast LDS read per antenna) rather
+  // than through L2, whose latency would otherwise open each chunk
+  __shared__ __align__(16) double s_xs[4 * kMaxAnt];
+  const BB_LDS double* const xs = (const BB_LDS double*)s_xs;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -572,11 +611,12 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
   const int wn = wave / WK;
   const int cb0 = wn * NB;
   const int n_levels = P.n_levels;
-  // Ping-pong: the first half of the waves generates the next phase chunk and
-  // then multiplies, the second half multiplies first.  Waves are laid out
-  // round-robin over the four SIMDs, so each SIMD holds one wave of each half
-  // and its VALU (phases) and matrix core (MFMA) work at the same time.
-  const bool gen_first = wave < C::WAVES / 2;
+  // Phases of the next chunk are spread over the MFMA groups of the current
+  // one: a vector instruction issues in the shadow of a 64-cycle MFMA, whereas
+  // phases generated in one burst per chunk stall at the chunk's barrier (a
+  // SIMD issues few vector instructions while another wave streams MFMAs).
+  constexpr int PPG = 4 * C::JT / NG;  // phase pairs per MFMA group
+  static_assert(PPG * NG == 4 * C::JT, "pairs split evenly over the groups");
 
   // Persistent grid: workgroup b owns pixel tiles b, b + gridDim.x, ...; every
   // workgroup walks the groups (slots) and their instances in the same order,
@@ -591,7 +631,7 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
       const int inst = __builtin_amdgcn_readfirstlane(P.inst_list[ii]);
       const InstDesc& Dg = P.descs[inst];
       const void* const apack = Dg.apack;
-      const BB_GLOBAL double* const xs = as_global<double>(Dg.xs);
+      const BB_GLOBAL double* const xs_g = as_global<double>(Dg.xs);
       const BB_GLOBAL float* const wts = as_global<float>(Dg.wts);
       const BB_GLOBAL int* const levs = as_global<int>(Dg.levs);
       const BB_GLOBAL int* const kbr = as_global<int>(Dg.kbr);  // (lo, hi) pairs
@@ -601,6 +641,12 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
       const int n_pass = (K_pad + C::KC - 1) / C::KC;
       // 16-byte vectors per A row tile (PREC 0/1) or per plane (PREC 2/3)
       const int64_t a_stride = PREC >= 2 ? (int64_t)(L_pad / 8) * 64 : (int64_t)(L_pad / 4) * 64;
+      if (blockIdx.x < P.n_tiles) {  // workgroup-uniform: this workgroup owns a tile
+        __syncthreads();  // the previous instance's phase chunks are done with s_xs
+        for (int i = tid; i < 2 * L_pad; i += C::THREADS)
+          ((f64x2*)s_xs)[i] = ((const BB_GLOBAL f64x2*)xs_g)[i];
+        __syncthreads();
+      }
       for (int64_t tile = blockIdx.x; tile < P.n_tiles; tile += gridDim.x) {
         const int64_t p0 = tile * C::NT;
         for (int i = tid; i < WK * kMaxLevels * C::NT; i += C::THREADS) (&s_part[0][0][0])[i] = 0.0f;
@@ -626,31 +672,28 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
           gen_chunk<C, PREC>(s_buf[0], xs, px, py, pz, tid);
           __syncthreads();
           for (int c = 0; c < n_chunks; ++c) {
-            auto gen = [&]() {
-              if (c + 1 < n_chunks)
-                gen_chunk<C, PREC>(s_buf[(c + 1) & 1], xs + 4 * (c + 1) * C::LCH, px, py, pz, tid);
-            };
-            auto mma = [&]() {
-              if (!active) return;
+            // the last chunk regenerates itself into the idle buffer (read by
+            // nobody), so that no branch splits the MFMA stream
+            const int c_next = min(c + 1, n_chunks - 1);
+            const BB_LDS double* const xs_next = xs + 4 * c_next * C::LCH;
+            float cr[4 * C::JT], ci[4 * C::JT];
+            if (active) {
 #pragma unroll
               for (int g = 0; g < NG; ++g) {
-                AFrag<PREC> a_nxt;
-                const bool more = g + 1 < NG || c + 1 < n_chunks;
-                if (g + 1 < NG)
-                  load_a<C, PREC>(a_nxt, apack, a_base, a_stride, c, g + 1, lane);
-                else if (c + 1 < n_chunks)
-                  load_a<C, PREC>(a_nxt, apack, a_base, a_stride, c + 1, 0, lane);
+                AFrag<PREC> a_nxt;  // next group's operand (past the end: reloads the last chunk's)
+                load_a<C, PREC>(a_nxt, apack, a_base, a_stride, g + 1 < NG ? c : c_next, g + 1 < NG ? g + 1 : 0,
+                                lane);
+                gen_pairs<C, PREC>(cr, ci, xs_next, px, py, pz, tid, g * PPG, PPG);
                 mma_group<C, PREC, NB>(acc, a_cur, s_buf[c & 1], g, cb0, lane);
-                if (more) a_cur = a_nxt;
+                a_cur = a_nxt;
+                // keep each group's phase pairs among its own MFMAs (left to
+                // itself the scheduler sinks them all behind the last group)
+                __builtin_amdgcn_sched_barrier(0);
               }
-            };
-            if (gen_first) {
-              gen();
-              mma();
             } else {
-              mma();
-              gen();
+              gen_pairs<C, PREC>(cr, ci, xs_next, px, py, pz, tid, 0, 4 * C::JT);
             }
+            gen_store<C, PREC>(s_buf[(c + 1) & 1], cr, ci, tid);
             __syncthreads();
           }
           if (!active) continue;
