@@ -678,6 +678,9 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
             const BB_LDS double* const xs_next = xs + 4 * c_next * C::LCH;
             float cr[4 * C::JT], ci[4 * C::JT];
             if (active) {
+              // FP32 three products: the second wave of each SIMD multiplies at a
+              // higher priority, which staggers the two waves' phase slices
+              if (PREC == 2 && wave >= C::WAVES / 2) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
               for (int g = 0; g < NG; ++g) {
                 AFrag<PREC> a_nxt;  // next group's operand (past the end: reloads the last chunk's)
@@ -690,6 +693,7 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
                 // itself the scheduler sinks them all behind the last group)
                 __builtin_amdgcn_sched_barrier(0);
               }
+              if (PREC == 2 && wave >= C::WAVES / 2) __builtin_amdgcn_s_setprio(0);
             } else {
               gen_pairs<C, PREC>(cr, ci, xs_next, px, py, pz, tid, 0, 4 * C::JT);
             }
