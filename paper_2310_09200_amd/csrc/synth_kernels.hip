@@ -8,13 +8,14 @@
 // with antennas interleaved (re, im) along the contraction axis.
 //
 // Kernel structure (one workgroup = one pixel tile of one image slot):
-//   for each instance of the slot, for each K pass, for each 32-antenna chunk:
-//     phase generation: FP64 <x_l, p> in turns, exact FP64 reduction to
-//       [-1/2, 1/2], hardware FP32 sin/cos in turns -> B chunk in LDS
-//       (double-buffered: the next chunk is generated while this one is used)
+//   for each instance of the slot (its scaled positions copied to LDS once),
+//   for each K pass, for each 32-antenna chunk:
 //     MFMA: real-embedded W^H operand streamed from HBM/L2 in operand order
 //       and prefetched one MFMA group ahead, B operand from LDS, accumulators
 //       for [Er; Ei] in registers
+//     phase generation of the next chunk, a slice per MFMA group: FP64
+//       <x_l, p> in turns, exact FP64 reduction to [-1/2, 1/2], hardware FP32
+//       sin/cos in turns -> the other B buffer in LDS (double-buffered)
 //   epilogue of a pass: d_k (Er^2 + Ei^2) reduced over k in-lane, across the
 //     two half-waves, and into per-level partial sums in LDS
 //   end of the tile: sum over waves in a fixed order, one read-modify-write of
