@@ -33,7 +33,7 @@ BF16_PEAK_TFLOPS = 2516.6     # MI355X dense BF16 matrix
 # (sha256 of csrc/synth_kernels.hip), reported as null otherwise.
 MEASURED_TRAFFIC = {
     "fp32_3m": {"bytes": 8.7692e+10,
-                "kernel_source_sha256": "dc9b01347a473064f0c2126a7a0c13db1f1ac8f3cef2c35fc6c43c2ea4149f61"},
+                "kernel_source_sha256": "88f3ea9148b531932594c5934144c345642a59b032a711544537c27e8a7a9ec1"},
 }
 
 
@@ -78,6 +78,26 @@ def build_inputs(args, torch, dev):
     log(f"GPU FP64 pre-step (Gram + zhegvd) for {len(items)} epochs in {time.time() - t0:.1f}s")
     pre.close()
     return ctx, w, intervals, items, insts
+
+
+def measure_phase_peak(torch, ctx, w, items, reps=4, steps=3):
+    """Peak phase-generation rate of this device: the probe kernel evaluates every (antenna, pixel) phase of
+    the workload's first epoch with the synthesis kernel's arithmetic and no contraction beside it.
+    Returns (pairs per second, ms per probe call, pairs per call)."""
+    from paper_2310_09200_amd import phase_probe
+    _, x, wl = items[0][:3]
+    pix = torch.as_tensor(w.pix).to(ctx.device)  # the per-call column-major copy stays on the device
+    out = phase_probe(ctx, x, wl, pix, reps)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        phase_probe(ctx, x, wl, pix, reps, out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    pairs = float(x.shape[0]) * w.n_pix * reps
+    return pairs / (ms / 1000.0), ms, pairs
 
 
 def time_modes(args, torch, ctx, w, items, modes, n_levels):
@@ -417,6 +437,23 @@ def main():
                         "mfma_fraction_of_own_peak": exec_flop[m] * total_products / (kern_m / 1000.0)
                         / (peak[m] * 1e12)}
     out["modes"] = modes_out
+    # phase generation (FP64 argument and reduction, hardware sin/cos) against its own peak on this device:
+    # the synthesis kernel evaluates every phase once per K pass of 256 eigenpairs (two passes at K = 512)
+    peak_pairs, probe_ms, probe_pairs = measure_phase_peak(torch, ctx, w, items)
+    n_pass = -(-512 // 256)
+    gen_pairs = float(n_pass) * 512 * w.n_pix * args.epochs
+    alg_pairs = 512.0 * w.n_pix * args.epochs
+    out["phase_generation"] = {
+        "peak_pairs_per_s": peak_pairs, "probe": f"bb_phase_probe: {probe_pairs:.3e} pairs in {probe_ms:.3f} ms",
+        "pairs_per_launch": alg_pairs, "passes": n_pass,
+        "achieved_pairs_per_s": alg_pairs / (kern / 1000.0),
+        "frac": alg_pairs / (kern / 1000.0) / peak_pairs,
+        "generated_frac": gen_pairs / (kern / 1000.0) / peak_pairs,
+        "note": "pairs_per_launch = N_pix * L * epochs; generated_frac counts every pass's evaluation: the share "
+                "of the launch that phase generation would take at its own peak"}
+    log(f"phase generation: probe peak {peak_pairs:.3e} pairs/s; synthesis {alg_pairs / (kern / 1000.0):.3e} "
+        f"pairs/s ({100 * alg_pairs / (kern / 1000.0) / peak_pairs:.1f} % of peak; with {n_pass} passes "
+        f"{100 * gen_pairs / (kern / 1000.0) / peak_pairs:.1f} %)")
     # compensated (BF16 x3) forms against the plain FP32 forms, whole-step times
     comp = {}
     for cm in ("bf16x3", "bf16x3_3m"):

@@ -361,6 +361,27 @@ bb_status bb_synth_set_count(bb_synth h, int64_t count);
 bb_status bb_synth_timings(bb_synth h, double* ms_out, int32_t n);
 bb_status bb_synth_destroy(bb_synth h);
 
+/* Phase-generation throughput probe, for measurement only.  Standard synthesis
+ * evaluates the phase exp(+j 2 pi <x_l, p> / lambda) of every (antenna, pixel)
+ * pair (Section 2.4, Eq. standard_synthesis; Algorithm 2); this call does that
+ * work alone, with the synthesis kernel's arithmetic (FP64 argument and exact
+ * reduction in turns, hardware FP32 sine and cosine), and no contraction, so
+ * that timing it gives the device's peak rate of phase generation.  For each
+ * pixel p it writes out[p] = reps * sum_l (cos + sin)(2 pi <x_l, p> / lambda),
+ * summed in FP32 (every antenna's phase evaluated reps times).
+ *  n_ant         antennas, 1 .. 1024
+ *  wavelength_m  > 0
+ *  ant_xyz       device, n_ant x 3 column-major, metres
+ *  n_pix         pixels, >= 1
+ *  pix           device, n_pix x 3 column-major unit vectors
+ *  reps          repetitions over the antennas, >= 1
+ *  out           device, n_pix floats (written)
+ * Enqueued on the context's stream (time it with events there); the caller
+ * owns every buffer.  BB_ERR_INVALID_ARG for null pointers or sizes out of
+ * range, BB_ERR_DEVICE if the launch fails. */
+bb_status bb_phase_probe(bb_context ctx, int32_t n_ant, double wavelength_m, const double* ant_xyz, int64_t n_pix,
+                         const double* pix, int32_t reps, float* out);
+
 #ifdef __cplusplus
 }
 #endif

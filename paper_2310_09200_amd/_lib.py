@@ -86,6 +86,7 @@ PROTOS = {
     "bb_synth_get_count": (c_int32, [c_void_p, POINTER(c_int64)]),
     "bb_synth_set_count": (c_int32, [c_void_p, c_int64]),
     "bb_synth_timings": (c_int32, [c_void_p, POINTER(c_double), c_int32]),
+    "bb_phase_probe": (c_int32, [c_void_p, c_int32, c_double, c_void_p, c_int64, c_void_p, c_int32, c_void_p]),
     "bb_synth_destroy": (c_int32, [c_void_p]),
 }
 

@@ -955,6 +955,19 @@ bb_status bb_synth_set_count(bb_synth h, int64_t count) {
   return BB_OK;
 }
 
+bb_status bb_phase_probe(bb_context ctx, int32_t n_ant, double wavelength_m, const double* ant_xyz, int64_t n_pix,
+                         const double* pix, int32_t reps, float* out) {
+  if (!ctx) return BB_ERR_INVALID_ARG;
+  if (!ant_xyz || !pix || !out) return fail(ctx, BB_ERR_INVALID_ARG, "null pointer");
+  if (n_ant < 1 || n_ant > bb::kMaxAnt) return fail(ctx, BB_ERR_INVALID_ARG, "n_ant must be in [1, %d]", bb::kMaxAnt);
+  if (n_pix < 1 || reps < 1) return fail(ctx, BB_ERR_INVALID_ARG, "n_pix and reps must be >= 1");
+  if (!(wavelength_m > 0.0) || !std::isfinite(wavelength_m))
+    return fail(ctx, BB_ERR_INVALID_ARG, "wavelength must be positive and finite");
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  BB_HIP(ctx, bb::launch_phase_probe(ant_xyz, n_ant, 1.0 / wavelength_m, pix, n_pix, reps, out, ctx->stream));
+  return BB_OK;
+}
+
 bb_status bb_synth_timings(bb_synth h, double* ms_out, int32_t n) {
   if (!h || !ms_out || n < 0) return BB_ERR_INVALID_ARG;
   bb_context ctx = h->ctx;

@@ -81,6 +81,8 @@ int synth_tile_kc(int max_K_alloc, int precision);
 
 // Zero-fill of a float buffer (graph-capture safe, no memset nodes).
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
+hipError_t launch_phase_probe(const double* ant, int n_ant, double inv_wl, const double* pix, int64_t n_pix, int reps,
+                              float* out, hipStream_t s);
 
 // Pre-step kernels (prestep.hip).
 hipError_t launch_gram(const double* ant, int64_t ant_ld, int L, double wl, double* G_c128, int ldg, bool identity,

@@ -875,6 +875,46 @@ hipError_t launch_fields(const FwdParams& p, int K_alloc, hipStream_t s) {
   return launch_cfg<1, 4, 4, 2, 0, 1>(p, s);
 }
 
+// Phase-generation throughput probe (measurement only): every thread takes one
+// pixel and evaluates the phases of all antennas `reps` times with the
+// synthesis kernel's own arithmetic (positions from LDS, FP64 argument and
+// reduction, hardware sine and cosine), summing cos + sin so that nothing is
+// dropped.  No MFMA work runs beside it: its rate is the device's peak for
+// phase generation alone.
+__global__ __launch_bounds__(256) void phase_probe_kernel(const double* __restrict__ ant, int n_ant, double inv_wl,
+                                                          const double* __restrict__ pix, int64_t n_pix, int reps,
+                                                          float* __restrict__ out) {
+  __shared__ __align__(16) double s_xs[4 * kMaxAnt];
+  for (int l = threadIdx.x; l < n_ant; l += blockDim.x) {
+    s_xs[4 * l + 0] = ant[l] * inv_wl;
+    s_xs[4 * l + 1] = ant[l + n_ant] * inv_wl;
+    s_xs[4 * l + 2] = ant[l + 2 * n_ant] * inv_wl;
+    s_xs[4 * l + 3] = 0.0;
+  }
+  __syncthreads();
+  const BB_LDS double* const xs = (const BB_LDS double*)s_xs;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n_pix; p += (int64_t)gridDim.x * blockDim.x) {
+    const double px = pix[p], py = pix[p + n_pix], pz = pix[p + 2 * n_pix];
+    float acc = 0.0f;
+    for (int r = 0; r < reps; ++r)
+      for (int l = 0; l < n_ant; ++l) {
+        float c, sn;
+        phase_pair(xs + 4 * l, px, py, pz, c, sn);
+        acc += c + sn;
+      }
+    out[p] = acc;
+  }
+}
+
+hipError_t launch_phase_probe(const double* ant, int n_ant, double inv_wl, const double* pix, int64_t n_pix, int reps,
+                              float* out, hipStream_t s) {
+  int64_t blocks = (n_pix + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(phase_probe_kernel, dim3((unsigned)blocks), dim3(256), 0, s, ant, n_ant, inv_wl, pix, n_pix, reps,
+                     out);
+  return hipGetLastError();
+}
+
 __global__ void fill_zero_kernel(float* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0.0f;

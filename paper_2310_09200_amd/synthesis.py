@@ -57,6 +57,26 @@ class Context:
             pass
 
 
+def phase_probe(ctx, ant_xyz, wavelength_m, pix, reps=1, out=None):
+    """Phase-generation throughput probe (measurement only; ``bb_phase_probe``).
+
+    ``ant_xyz`` (n_ant, 3) metres and ``pix`` (n_pix, 3) unit vectors; returns
+    ``out`` (n_pix,) float32 with reps * sum over antennas of (cos + sin) of the
+    phase 2 pi <x, p> / wavelength.  Enqueued on torch's current stream (time
+    it with events there).
+    """
+    dev = ctx.device
+    x = _colmajor(torch.as_tensor(ant_xyz), torch.float64, dev)
+    p = _colmajor(torch.as_tensor(pix), torch.float64, dev)
+    n_ant, n_pix = x.shape[1], p.shape[1]
+    if out is None:
+        out = torch.empty(n_pix, dtype=torch.float32, device=dev)
+    ctx.bind_current_stream()
+    check(ctx.lib.bb_phase_probe(ctx.handle, n_ant, float(wavelength_m), _ptr(x), n_pix, _ptr(p), int(reps),
+                                 _ptr(out)), ctx.handle)
+    return out
+
+
 class StandardSynthesis:
     """Imaging handle: accumulates per-level images over collected instances.
 
