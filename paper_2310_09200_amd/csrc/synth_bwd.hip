@@ -8,8 +8,11 @@
 //   dW_lk = 2 sum_p B_lp M_kp            (d/dRe W + j d/dIm W)
 //   H_lp  = sum_k conj(W_lk) M_kp
 //   dx_l  = -(4 pi / lambda_w) sum_p Im(H_lp B_lp) p
-// E is recomputed by the forward MFMA kernel (FP32) into HBM; the kernels
-// below work in level-sorted eigenpair order (the staging permutation) and
+// E is recomputed by the forward MFMA kernel (FP32) into HBM; the
+// contractions dW and H run on FP32 MFMA (32x32x2), in one kernel sharing its
+// staged phases and M when every eigenpair fits one 64-wide slice, in two
+// otherwise.  The kernels work in level-sorted eigenpair order (the staging
+// permutation) and
 // the reduction writes results back in the caller's order.  Contractions over
 // pixels are split into fixed pixel ranges whose FP64 partials are summed in a
 // fixed order: the result is deterministic.
@@ -78,23 +81,30 @@ __global__ __launch_bounds__(256) void bwd_m_kernel(const BwdParams P) {
 }
 
 // dW partial: sum over the split's pixels of B_lp M_kp for a 32 x 32 (l, k)
-// tile.  grid (L_pad/32, K_alloc/32, n_split), 256 threads; each thread owns
-// one antenna and four eigenpairs.  LDS: phases [64 px][32 l] and M [64 px][32 k].
+// tile, on MFMA.  grid (L_pad/32, K_alloc/32, n_split), 256 threads.  Each
+// 64-pixel chunk stages phases [64 px][32 l] and M [64 px][32 k] in LDS; wave
+// w contracts pixels 16 w .. 16 w + 15 of it as 8 steps of 32x32x2 MFMAs
+// (A = B phases, rows l; B = M, columns k):
+//   Re += Br Mr - Bi Mi,  Im += Br Mi + Bi Mr.
+// The four waves' partial tiles are summed in a fixed order at the end.
+typedef float bwd_f32x16 __attribute__((ext_vector_type(16)));
+
 __global__ __launch_bounds__(256) void bwd_dw_kernel(const BwdParams P) {
   __shared__ float2 sB[64][32];
   __shared__ float2 sM[64][32];
   const InstDesc& D = *P.desc;
   const int l0 = blockIdx.x * 32, k0 = blockIdx.y * 32, s = blockIdx.z;
-  const int t = threadIdx.x;
-  const int tl = t >> 3, tk = (t & 7) * 4;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int64_t p0 = (int64_t)s * P.split_len;
   int64_t p1 = p0 + P.split_len;
   if (p1 > P.n_pix) p1 = P.n_pix;
-  float ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+  bwd_f32x16 are, aim;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) are[r] = aim[r] = 0.0f;
   const float* Er = P.E;
   const float* Ei = P.E + (int64_t)P.K_alloc * P.n_pix;
   for (int64_t pc = p0; pc < p1; pc += 64) {
-    // phases: 32 antennas x 64 pixels, 8 per thread
+    // phases: 32 antennas x 64 pixels, 8 per thread (zero past the split)
     for (int i = t; i < 64 * 32; i += 256) {
       const int pp = i >> 5, ll = i & 31;
       const int64_t p = pc + pp;
@@ -112,38 +122,60 @@ __global__ __launch_bounds__(256) void bwd_dw_kernel(const BwdParams P) {
       sM[pp][kk] = m;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int pp = 0; pp < 64; ++pp) {
-      const float2 b = sB[pp][tl];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float2 m = sM[pp][tk + j];
-        ar[j] = fmaf(b.x, m.x, fmaf(-b.y, m.y, ar[j]));
-        ai[j] = fmaf(b.x, m.y, fmaf(b.y, m.x, ai[j]));
-      }
+    for (int st = 0; st < 8; ++st) {
+      const int pp = 16 * wave + 2 * st + (lane >> 5);  // this lane's contraction row (pixel)
+      const float2 b = sB[pp][lane & 31];               // A operand: row l = lane % 32
+      const float2 m = sM[pp][lane & 31];               // B operand: column k = lane % 32
+      are = __builtin_amdgcn_mfma_f32_32x32x2f32(b.x, m.x, are, 0, 0, 0);
+      are = __builtin_amdgcn_mfma_f32_32x32x2f32(-b.y, m.y, are, 0, 0, 0);
+      aim = __builtin_amdgcn_mfma_f32_32x32x2f32(b.x, m.y, aim, 0, 0, 0);
+      aim = __builtin_amdgcn_mfma_f32_32x32x2f32(b.y, m.x, aim, 0, 0, 0);
     }
     __syncthreads();
   }
-  double* out = P.dW_part + (((int64_t)s * P.L_pad + (l0 + tl)) * P.K_alloc + k0 + tk) * 2;
+  // fixed-order sum of the four waves' tiles: wave w's register r of lane q
+  // holds (l, k) = (8 (r / 4) + 4 (q / 32) + r % 4, q % 32)
+  float* const red = reinterpret_cast<float*>(&sB[0][0]);  // [4 waves][16 regs][64 lanes] re, then im in sM
+  float* const redi = reinterpret_cast<float*>(&sM[0][0]);
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    out[2 * j] = ar[j];
-    out[2 * j + 1] = ai[j];
+  for (int r = 0; r < 16; ++r) {
+    red[(wave * 16 + r) * 64 + lane] = are[r];
+    redi[(wave * 16 + r) * 64 + lane] = aim[r];
+  }
+  __syncthreads();
+  for (int i = t; i < 16 * 64; i += 256) {
+    const int r = i >> 6, q = i & 63;
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      re += red[(w * 16 + r) * 64 + q];
+      im += redi[(w * 16 + r) * 64 + q];
+    }
+    const int l = 8 * (r >> 2) + 4 * (q >> 5) + (r & 3), k = q & 31;
+    double* out = P.dW_part + (((int64_t)s * P.L_pad + (l0 + l)) * P.K_alloc + k0 + k) * 2;
+    out[0] = re;
+    out[1] = im;
   }
 }
 
-// dx partial: H_lp = sum_k conj(W_lk) M_kp, then Im(H_lp B_lp) p summed over
-// the split's pixels.  grid (L_pad/32, n_split), 256 threads; each thread owns
-// one antenna and 8 pixels of every 64-pixel chunk.
+// dx partial: H_lp = sum_k conj(W_lk) M_kp on MFMA, then Im(H_lp B_lp) p
+// summed over the split's pixels.  grid (L_pad/32, n_split), 256 threads.  Per
+// 64-pixel chunk and 64-eigenpair slice, conj(W) [32 l][64 k] and M [64 k][64 p]
+// are staged in LDS; wave w computes one real 32 x 32 block of H: pixel half
+// w / 2, real part (w even: Wr Mr - Wi' Mi with W' = conj W) or imaginary part
+// (w odd: Wr' Mi + Wi' Mr).  The blocks go through LDS to the threads that
+// own (antenna t / 8, pixels t % 8 + 8 j), which evaluate the phases.
 __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
-  __shared__ float2 sW[32][65];   // conj(W) for 32 antennas x 64 eigenpairs (+1 pad)
-  __shared__ float2 sM[64][65];   // M for 64 eigenpairs x 64 pixels (+1 pad)
+  __shared__ float2 sW[32][65];   // conj(W) for 32 antennas x 64 eigenpairs (+1 pad: column reads)
+  __shared__ float2 sM[64][65];   // M for 64 eigenpairs x 64 pixels; then H re / im [2][32][64] floats
   __shared__ double sh[3][256];
   const InstDesc& D = *P.desc;
   const int l0 = blockIdx.x * 32, s = blockIdx.y;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int tl = t >> 3, tp = (t & 7);
   const int l = l0 + tl;
+  const int blk = wave >> 1, part = wave & 1;  // this wave's H block: pixel half, re / im
   const int64_t p0 = (int64_t)s * P.split_len;
   int64_t p1 = p0 + P.split_len;
   if (p1 > P.n_pix) p1 = P.n_pix;
@@ -151,13 +183,16 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
   const float* Er = P.E;
   const float* Ei = P.E + (int64_t)P.K_alloc * P.n_pix;
   const float* Wf = (const float*)P.W;
+  float* const sH = reinterpret_cast<float*>(&sM[0][0]);  // [2 parts][32 l][64 p]
   double gx = 0.0, gy = 0.0, gz = 0.0;
   for (int64_t pc = p0; pc < p1; pc += 64) {
-    float hr[8], hi[8];
+    bwd_f32x16 acc;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) hr[j] = hi[j] = 0.0f;
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
     for (int kc = 0; kc < K_pad; kc += 64) {
-      for (int i = t; i < 32 * 64; i += 256) {
+      // conj(W) does not depend on the pixels: with a single eigenpair slice it
+      // is staged by the first chunk only (no later pass writes sW)
+      for (int i = t; i < 32 * 64 && (K_pad > 64 || pc == p0); i += 256) {
         const int ll = i >> 6, kk = i & 63;
         const int k = kc + kk;
         float2 wv = make_float2(0.0f, 0.0f);
@@ -179,31 +214,192 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
         sM[kk][pp] = m;
       }
       __syncthreads();
-      for (int kk = 0; kk < 64; ++kk) {
-        const float2 w = sW[tl][kk];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const float2 m = sM[kk][tp + 8 * j];
-          hr[j] = fmaf(w.x, m.x, fmaf(-w.y, m.y, hr[j]));
-          hi[j] = fmaf(w.x, m.y, fmaf(w.y, m.x, hi[j]));
+#pragma unroll 8
+      for (int st = 0; st < 32; ++st) {
+        const int kk = 2 * st + (lane >> 5);             // this lane's contraction row (eigenpair)
+        const float2 w = sW[lane & 31][kk];              // A operand: row l = lane % 32
+        const float2 m = sM[kk][32 * blk + (lane & 31)];  // B operand: column p = lane % 32 of the half
+        if (part == 0) {
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(w.x, m.x, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(-w.y, m.y, acc, 0, 0, 0);
+        } else {
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(w.x, m.y, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(w.y, m.x, acc, 0, 0, 0);
         }
       }
       __syncthreads();
     }
+    // register r of lane q holds H at (l, p) = (8 (r / 4) + 4 (q / 32) + r % 4, 32 blk + q % 32)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int ll = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      sH[(part * 32 + ll) * 64 + 32 * blk + (lane & 31)] = acc[r];
+    }
+    __syncthreads();
     if (l < P.L) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const int64_t p = pc + tp + 8 * j;
+        const int pp = tp + 8 * j;
+        const int64_t p = pc + pp;
         if (p < p1) {
           const double px = P.pix[p], py = P.pix[p + P.pix_ld], pz = P.pix[p + 2 * P.pix_ld];
           float c, sn;
           phase_b(D.xs + 4 * l, px, py, pz, c, sn);
-          const double v = (double)fmaf(hr[j], sn, hi[j] * c);  // Im(H B)
+          const float hr = sH[tl * 64 + pp], hi = sH[(32 + tl) * 64 + pp];
+          const double v = (double)fmaf(hr, sn, hi * c);  // Im(H B)
           gx += v * px;
           gy += v * py;
           gz += v * pz;
         }
       }
+    }
+    __syncthreads();  // sH (in sM) is restaged by the next chunk
+  }
+  sh[0][t] = gx;
+  sh[1][t] = gy;
+  sh[2][t] = gz;
+  __syncthreads();
+  if (tp == 0 && l < P.L_pad) {
+    double a = 0, b = 0, c = 0;
+    for (int j = 0; j < 8; ++j) {
+      a += sh[0][t + j];
+      b += sh[1][t + j];
+      c += sh[2][t + j];
+    }
+    double* o = P.dx_part + ((int64_t)s * P.L_pad + l) * 3;
+    o[0] = a;
+    o[1] = b;
+    o[2] = c;
+  }
+}
+
+// dW and dx partials together when every eigenpair fits one 64-wide slice
+// (K_alloc <= 64): each 64-pixel chunk's phases [64 p][32 l] and M [64 k][64 p]
+// are staged once and serve both contractions.  grid (L_pad/32, n_split), 256
+// threads; wave w owns
+//   the dW block of eigenpairs 32 (w / 2) .. + 31, part w % 2 (re / im),
+//     accumulated over the split (A = phases, rows l; B = M, columns k);
+//   the H block of pixels 32 (w / 2) .. + 31 of the chunk, part w % 2
+//     (A = conj(W), rows l; B = M, columns p).
+// H goes through LDS to the threads that own (antenna t / 8, pixels t % 8 + 8 j),
+// which form Im(H B) p with the staged phases.
+__global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
+  __shared__ float2 sW[32][65];   // conj(W) [32 l][64 k], staged once (+1 pad: column reads)
+  __shared__ float2 sM[64][65];   // M [64 k][64 p] (+1 pad: column reads); then H re / im [2][32][64] floats
+  __shared__ float2 sB[64][32];   // phases [64 p][32 l]
+  __shared__ double sh[3][256];
+  const InstDesc& D = *P.desc;
+  const int l0 = blockIdx.x * 32, s = blockIdx.y;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int tl = t >> 3, tp = (t & 7);
+  const int l = l0 + tl;
+  const int blk = wave >> 1, part = wave & 1;
+  const bool dw_active = 32 * blk < P.K_alloc;  // wave-uniform: this wave's dW block exists
+  const int64_t p0 = (int64_t)s * P.split_len;
+  int64_t p1 = p0 + P.split_len;
+  if (p1 > P.n_pix) p1 = P.n_pix;
+  const int K_pad = P.dyn->K_pad;
+  const float* Er = P.E;
+  const float* Ei = P.E + (int64_t)P.K_alloc * P.n_pix;
+  const float* Wf = (const float*)P.W;
+  float* const sH = reinterpret_cast<float*>(&sM[0][0]);  // [2 parts][32 l][64 p]
+  for (int i = t; i < 32 * 64; i += 256) {
+    const int ll = i >> 6, kk = i & 63;
+    float2 wv = make_float2(0.0f, 0.0f);
+    if (l0 + ll < P.L && kk < K_pad) {
+      const int src = D.perm[kk];
+      if (src >= 0) {
+        const float* w = Wf + 2 * ((int64_t)src * P.L + l0 + ll);
+        wv = make_float2(w[0], -w[1]);
+      }
+    }
+    sW[ll][kk] = wv;
+  }
+  bwd_f32x16 dw;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) dw[r] = 0.0f;
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+  for (int64_t pc = p0; pc < p1; pc += 64) {
+    for (int i = t; i < 64 * 32; i += 256) {
+      const int pp = i >> 5, ll = i & 31;
+      const int64_t p = pc + pp;
+      float c = 0.0f, sn = 0.0f;
+      if (p < p1) {
+        phase_b(D.xs + 4 * (l0 + ll), P.pix[p], P.pix[p + P.pix_ld], P.pix[p + 2 * P.pix_ld], c, sn);
+      }
+      sB[pp][ll] = make_float2(c, sn);
+    }
+    for (int i = t; i < 64 * 64; i += 256) {
+      const int kk = i >> 6, pp = i & 63;
+      const int64_t p = pc + pp;
+      float2 m = make_float2(0.0f, 0.0f);
+      if (p < p1 && kk < K_pad) m = make_float2(Er[(int64_t)kk * P.n_pix + p], Ei[(int64_t)kk * P.n_pix + p]);
+      sM[kk][pp] = m;
+    }
+    __syncthreads();
+    if (dw_active) {
+      // dW += B M^T over the chunk's pixels: Re = Br Mr - Bi Mi, Im = Br Mi + Bi Mr
+#pragma unroll 8
+      for (int st = 0; st < 32; ++st) {
+        const int pp = 2 * st + (lane >> 5);
+        const float2 b = sB[pp][lane & 31];
+        const float2 m = sM[32 * blk + (lane & 31)][pp];
+        if (part == 0) {
+          dw = __builtin_amdgcn_mfma_f32_32x32x2f32(b.x, m.x, dw, 0, 0, 0);
+          dw = __builtin_amdgcn_mfma_f32_32x32x2f32(-b.y, m.y, dw, 0, 0, 0);
+        } else {
+          dw = __builtin_amdgcn_mfma_f32_32x32x2f32(b.x, m.y, dw, 0, 0, 0);
+          dw = __builtin_amdgcn_mfma_f32_32x32x2f32(b.y, m.x, dw, 0, 0, 0);
+        }
+      }
+    }
+    // H = conj(W) M for this wave's pixel half
+    bwd_f32x16 h;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) h[r] = 0.0f;
+#pragma unroll 8
+    for (int st = 0; st < 32; ++st) {
+      const int kk = 2 * st + (lane >> 5);
+      const float2 w = sW[lane & 31][kk];
+      const float2 m = sM[kk][32 * blk + (lane & 31)];
+      if (part == 0) {
+        h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.x, m.x, h, 0, 0, 0);
+        h = __builtin_amdgcn_mfma_f32_32x32x2f32(-w.y, m.y, h, 0, 0, 0);
+      } else {
+        h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.x, m.y, h, 0, 0, 0);
+        h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.y, m.x, h, 0, 0, 0);
+      }
+    }
+    __syncthreads();  // every wave is done with sM
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int ll = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      sH[(part * 32 + ll) * 64 + 32 * blk + (lane & 31)] = h[r];
+    }
+    __syncthreads();
+    if (l < P.L) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int pp = tp + 8 * j;
+        const int64_t p = pc + pp;
+        if (p < p1) {
+          const double px = P.pix[p], py = P.pix[p + P.pix_ld], pz = P.pix[p + 2 * P.pix_ld];
+          const float2 b = sB[pp][tl];
+          const float hr = sH[tl * 64 + pp], hi = sH[(32 + tl) * 64 + pp];
+          const double v = (double)fmaf(hr, b.y, hi * b.x);  // Im(H B)
+          gx += v * px;
+          gy += v * py;
+          gz += v * pz;
+        }
+      }
+    }
+    __syncthreads();  // sB and sM (holding H) are restaged by the next chunk
+  }
+  if (dw_active) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int ll = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), k = 32 * blk + (lane & 31);
+      P.dW_part[(((int64_t)s * P.L_pad + (l0 + ll)) * P.K_alloc + k) * 2 + part] = dw[r];
     }
   }
   sh[0][t] = gx;
@@ -272,6 +468,10 @@ hipError_t launch_backward(const BwdParams& p, hipStream_t s) {
   hipLaunchKernelGGL(bwd_m_kernel, dim3(p.K_alloc, p.n_split), dim3(256), 0, s, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (p.K_alloc <= 64) {  // one eigenpair slice: both contractions share their staged tiles
+    hipLaunchKernelGGL(bwd_fused_kernel, dim3(p.L_pad / 32, p.n_split), dim3(256), 0, s, p);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(bwd_dw_kernel, dim3(p.L_pad / 32, p.K_alloc / 32, p.n_split), dim3(256), 0, s, p);
   e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -864,15 +864,12 @@ hipError_t launch_synth(const FwdParams& p, int max_K_alloc, int precision, int 
   return launch_prec<0>(p, max_K_alloc, s);
 }
 
-int fields_tile_pixels(int K_alloc) {
-  if (K_alloc > 128) return TileCfg<1, 4, 8, 1>::NT;
-  return TileCfg<1, 4, 4, 2>::NT;
-}
+int fields_tile_pixels(int K_alloc) { return synth_tile_pixels(K_alloc, 0); }
 
 hipError_t launch_fields(const FwdParams& p, int K_alloc, hipStream_t s) {
-  // FP32 recompute of E for the backward pass (the handle's precision does not apply)
-  if (K_alloc > 128) return launch_cfg<1, 4, 8, 1, 0, 1>(p, s);
-  return launch_cfg<1, 4, 4, 2, 0, 1>(p, s);
+  // FP32 recompute of E for the backward pass (the handle's precision does not
+  // apply), in the forward's tile shape for this K: no idle k-block waves
+  return Shapes<0>::pick(K_alloc, [&](auto cfg) { return launch_tc<0, 1>(p, cfg, s); });
 }
 
 // Phase-generation throughput probe (measurement only): every thread takes one
