@@ -33,7 +33,7 @@ BF16_PEAK_TFLOPS = 2516.6     # MI355X dense BF16 matrix
 # (sha256 of csrc/synth_kernels.hip), reported as null otherwise.
 MEASURED_TRAFFIC = {
     "fp32_3m": {"bytes": 8.7692e+10,
-                "kernel_source_sha256": "d03ca651d81c8053d419aed84df46b1cfe11c357419c84547ca6b6d5a253e18f"},
+                "kernel_source_sha256": "bdb809b89feeedbac11d238b9d36ce5b643c24192d8ad505ad2ca66964454b7c"},
 }
 
 

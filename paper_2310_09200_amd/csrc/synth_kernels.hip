@@ -613,9 +613,10 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
   const int cb0 = wn * NB;
   const int n_levels = P.n_levels;
   // Phases of the next chunk are spread over the MFMA groups of the current
-  // one: a vector instruction issues in the shadow of a 64-cycle MFMA, whereas
-  // phases generated in one burst per chunk stall at the chunk's barrier (a
-  // SIMD issues few vector instructions while another wave streams MFMAs).
+  // one.  A SIMD issues few vector instructions while another of its waves
+  // streams MFMAs, so phases generated in one burst per chunk left the matrix
+  // pipe idle at the chunk's barrier; in slices, each wave's phase work sits
+  // between its own MFMA groups while the other wave keeps multiplying.
   constexpr int PPG = 4 * C::JT / NG;  // phase pairs per MFMA group
   static_assert(PPG * NG == 4 * C::JT, "pairs split evenly over the groups");
 
