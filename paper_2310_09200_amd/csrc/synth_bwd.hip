@@ -282,11 +282,13 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
 //   the H block of pixels 32 (w / 2) .. + 31 of the chunk, part w % 2
 //     (A = conj(W), rows l; B = M, columns p).
 // H goes through LDS to the threads that own (antenna t / 8, pixels t % 8 + 8 j),
-// which form Im(H B) p with the staged phases.
+// which form Im(H B) p with the staged phases.  The next chunk's M and pixel
+// coordinates are loaded into registers while the current chunk is processed.
 __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
   __shared__ float2 sW[32][65];   // conj(W) [32 l][64 k], staged once (+1 pad: column reads)
   __shared__ float2 sM[64][65];   // M [64 k][64 p] (+1 pad: column reads); then H re / im [2][32][64] floats
   __shared__ float2 sB[64][32];   // phases [64 p][32 l]
+  __shared__ double sP[3][64];    // the chunk's pixel coordinates
   __shared__ double sh[3][256];
   const InstDesc& D = *P.desc;
   const int l0 = blockIdx.x * 32, s = blockIdx.y;
@@ -315,26 +317,38 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
     }
     sW[ll][kk] = wv;
   }
+  // the next chunk's M (16 values per thread: eigenpair 4 j + t / 64, pixel
+  // t % 64) and pixel coordinates (threads < 192: axis t / 64, pixel t % 64)
+  // are loaded into registers while the current chunk is processed
+  float2 mnext[16];
+  double pnext = 0.0;
+  auto load_chunk = [&](int64_t pc) {
+    const int pp = t & 63;
+    const int64_t p = pc + pp;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int kk = 4 * j + (t >> 6);
+      mnext[j] = (p < p1 && kk < K_pad) ? make_float2(Er[(int64_t)kk * P.n_pix + p], Ei[(int64_t)kk * P.n_pix + p])
+                                        : make_float2(0.0f, 0.0f);
+    }
+    if (t < 192) pnext = p < p1 ? P.pix[p + (t >> 6) * P.pix_ld] : 0.0;
+  };
+  load_chunk(p0);
   bwd_f32x16 dw;
 #pragma unroll
   for (int r = 0; r < 16; ++r) dw[r] = 0.0f;
   double gx = 0.0, gy = 0.0, gz = 0.0;
   for (int64_t pc = p0; pc < p1; pc += 64) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sM[4 * j + (t >> 6)][t & 63] = mnext[j];
+    if (t < 192) sP[t >> 6][t & 63] = pnext;
+    __syncthreads();
+    if (pc + 64 < p1) load_chunk(pc + 64);  // workgroup-uniform
     for (int i = t; i < 64 * 32; i += 256) {
       const int pp = i >> 5, ll = i & 31;
-      const int64_t p = pc + pp;
       float c = 0.0f, sn = 0.0f;
-      if (p < p1) {
-        phase_b(D.xs + 4 * (l0 + ll), P.pix[p], P.pix[p + P.pix_ld], P.pix[p + 2 * P.pix_ld], c, sn);
-      }
+      if (pc + pp < p1) phase_b(D.xs + 4 * (l0 + ll), sP[0][pp], sP[1][pp], sP[2][pp], c, sn);
       sB[pp][ll] = make_float2(c, sn);
-    }
-    for (int i = t; i < 64 * 64; i += 256) {
-      const int kk = i >> 6, pp = i & 63;
-      const int64_t p = pc + pp;
-      float2 m = make_float2(0.0f, 0.0f);
-      if (p < p1 && kk < K_pad) m = make_float2(Er[(int64_t)kk * P.n_pix + p], Ei[(int64_t)kk * P.n_pix + p]);
-      sM[kk][pp] = m;
     }
     __syncthreads();
     if (dw_active) {
@@ -381,19 +395,17 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int pp = tp + 8 * j;
-        const int64_t p = pc + pp;
-        if (p < p1) {
-          const double px = P.pix[p], py = P.pix[p + P.pix_ld], pz = P.pix[p + 2 * P.pix_ld];
+        if (pc + pp < p1) {
           const float2 b = sB[pp][tl];
           const float hr = sH[tl * 64 + pp], hi = sH[(32 + tl) * 64 + pp];
           const double v = (double)fmaf(hr, b.y, hi * b.x);  // Im(H B)
-          gx += v * px;
-          gy += v * py;
-          gz += v * pz;
+          gx += v * sP[0][pp];
+          gy += v * sP[1][pp];
+          gz += v * sP[2][pp];
         }
       }
     }
-    __syncthreads();  // sB and sM (holding H) are restaged by the next chunk
+    __syncthreads();  // sB, sP and sM (holding H) are restaged by the next chunk
   }
   if (dw_active) {
 #pragma unroll
