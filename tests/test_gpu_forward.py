@@ -403,3 +403,73 @@ def test_phase_probe_against_fp64(ctx):
     # per term: ~1.3e-7 (hardware sin/cos) + 3e-8 (FP32 argument); the FP32 running sum of 111 terms adds
     # at most ~1e-4 at the magnitudes reached here
     assert np.max(np.abs(got - want)) < 2e-4
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp32", "fp32_3m", "bf16x3_3m"])
+def test_maximum_sizes_against_oracle(ctx, precision):
+    """The largest instance the library accepts: 1024 antennas (the workgroup's LDS position table full) and
+    1024 eigenpairs (four K passes of the K > 128 tile), ragged pixel count."""
+    L, K, n_side = 1024, 1024, 13
+    say(f"case maximum sizes L={L} K={K} n_side={n_side} precision={precision}")
+    g = np.random.default_rng(77)
+    x = sims.disk_layout(L, 20000.0, g, z_sigma_m=5.0)
+    wl = sims.wavelength_m(150e6)
+    pix = sims.pixel_grid(n_side, 4.0, 50.0)
+    W = sims.random_eigvecs(L, K, g)
+    d = g.normal(0, 1, K)
+    n_levels = 4
+    lev = g.integers(-1, n_levels, K).astype(np.int32)
+    d32 = d.astype(np.float32).astype(np.float64)
+    want = oracle_images(W.astype(np.complex64).astype(np.complex128), d32, lev, x, wl, pix, n_levels)
+    got = run_eig(ctx, pix, n_levels, x, wl, W, d, lev, precision)
+    err = level_errors(got, want)
+    say("max err per level", err[:, 0])
+    assert np.all(err[:, 0] <= TOL[precision]), err
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("L,K,n_pix", [(1, 1, 1), (1, 1, 97), (33, 1, 1), (2, 2, 2), (40, 40, 1)])
+def test_degenerate_sizes(ctx, L, K, n_pix):
+    """One antenna, one eigenpair, one pixel: tiles that are almost entirely padding."""
+    say(f"case degenerate L={L} K={K} n_pix={n_pix}")
+    g = np.random.default_rng(300 + L + K + n_pix)
+    x = g.uniform(-500.0, 500.0, (L, 3))
+    wl = 2.0
+    pix = g.normal(size=(n_pix, 3)) + np.array([0.0, 0.0, 4.0])
+    pix /= np.linalg.norm(pix, axis=1, keepdims=True)
+    W = (g.normal(size=(L, K)) + 1j * g.normal(size=(L, K))) / np.sqrt(2 * L)
+    d = np.abs(g.normal(0, 1, K)) + 0.5
+    lev = np.zeros(K, np.int32)
+    d32 = d.astype(np.float32).astype(np.float64)
+    want = oracle_images(W.astype(np.complex64).astype(np.complex128), d32, lev, x, wl, pix, 1)
+    for precision in ("fp32", "fp32_3m", "bf16x3", "bf16x3_3m"):
+        got = run_eig(ctx, pix, 1, x, wl, W, d, lev, precision)
+        err = level_errors(got, want)
+        assert np.all(err[:, 0] <= TOL[precision]), (precision, err)
+
+
+@pytest.mark.gpu
+def test_empty_batch_is_rejected(ctx):
+    """A batch of zero instances is an argument error and leaves the images untouched."""
+    from paper_2310_09200_amd import StandardSynthesis, _lib
+    say("case empty batch")
+    s = StandardSynthesis(ctx, sims.pixel_grid(8, 5.0, 90.0), 2, 1, 16, 16)
+    sz = ctypes.c_size_t()
+    assert s.lib.bb_batched_workspace_size(s.handle, 0, None, ctypes.byref(sz)) == _lib.BB_ERR_INVALID_ARG
+    # valid (dummy) device buffers, so that the empty instance table is what gets rejected
+    dev = ctx.device
+    ant = torch.zeros(3, dtype=torch.float64, device=dev)
+    W = torch.zeros(2, dtype=torch.float32, device=dev)
+    d = torch.zeros(1, dtype=torch.float32, device=dev)
+    lev = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = torch.zeros(4096, dtype=torch.uint8, device=dev)
+    ws_ptr = (ws.data_ptr() + 255) // 256 * 256
+    st = s.lib.bb_synth_collect_eig_batched(s.handle, 0, None, 1, ctypes.c_void_p(ant.data_ptr()),
+                                            ctypes.c_void_p(W.data_ptr()), ctypes.c_void_p(d.data_ptr()),
+                                            ctypes.c_void_p(lev.data_ptr()), ctypes.c_void_p(ws_ptr), 2048)
+    assert st == _lib.BB_ERR_INVALID_ARG
+    assert b"empty" in s.lib.bb_last_error(ctx.handle)
+    s.sync()
+    assert torch.count_nonzero(s.images).item() == 0
+    s.close()
