@@ -33,7 +33,7 @@ BF16_PEAK_TFLOPS = 2516.6     # MI355X dense BF16 matrix
 # (sha256 of csrc/synth_kernels.hip), reported as null otherwise.
 MEASURED_TRAFFIC = {
     "fp32_3m": {"bytes": 8.7692e+10,
-                "kernel_source_sha256": "bdb809b89feeedbac11d238b9d36ce5b643c24192d8ad505ad2ca66964454b7c"},
+                "kernel_source_sha256": "3b7f0cfcdb9f5d8caba89c37355e8c77931c35022bc63fe776feaf4d0d315973"},
 }
 
 

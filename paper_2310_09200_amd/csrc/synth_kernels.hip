@@ -813,7 +813,7 @@ struct Shapes<2> {  // 3 products: k1/k2/k3 accumulators, 48 regs per output blo
     if (K > 128) return f(TileCfg<1, 2, 8, 1>{});
     if (K > 64) return f(TileCfg<1, 2, 4, 2>{});
     if (K > 32) return f(TileCfg<1, 2, 2, 4>{});
-    return f(TileCfg<1, 2, 1, 4>{});
+    return f(TileCfg<1, 1, 1, 8>{});  // one pixel block per wave: two waves per SIMD
   }
 };
 
