@@ -33,7 +33,7 @@ BF16_PEAK_TFLOPS = 2516.6     # MI355X dense BF16 matrix
 # (sha256 of csrc/synth_kernels.hip), reported as null otherwise.
 MEASURED_TRAFFIC = {
     "fp32_3m": {"bytes": 8.7692e+10,
-                "kernel_source_sha256": "3b7f0cfcdb9f5d8caba89c37355e8c77931c35022bc63fe776feaf4d0d315973"},
+                "kernel_source_sha256": "32ff6b0bc86e4020d0512878d3b20f9d513c6fd20f4c841d2f061c3925f6f748"},
 }
 
 

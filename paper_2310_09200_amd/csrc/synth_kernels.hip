@@ -608,8 +608,11 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wk = wave % WK;
-  const int wn = wave / WK;
+  // k-block of a wave = wave / WN: the waves of one SIMD (wave mod 4) cover the
+  // k-blocks evenly, so an instance whose K fills only part of the tile leaves
+  // no SIMD idle
+  const int wk = wave / WN;
+  const int wn = wave % WN;
   const int cb0 = wn * NB;
   const int n_levels = P.n_levels;
   // Phases of the next chunk are spread over the MFMA groups of the current
@@ -811,7 +814,9 @@ template <>
 struct Shapes<2> {  // 3 products: k1/k2/k3 accumulators, 48 regs per output block
   template <class F> static hipError_t pick(int K, F f) {
     if (K > 128) return f(TileCfg<1, 2, 8, 1>{});
-    if (K > 64) return f(TileCfg<1, 2, 4, 2>{});
+    // 16 waves of one pixel block each: 3 active k-blocks (K <= 96) still
+    // spread evenly over the four SIMDs
+    if (K > 64) return f(TileCfg<1, 1, 4, 4>{});
     if (K > 32) return f(TileCfg<1, 2, 2, 4>{});
     return f(TileCfg<1, 1, 1, 8>{});  // one pixel block per wave: two waves per SIMD
   }
@@ -823,7 +828,14 @@ static hipError_t launch_tc(const FwdParams& p, TileCfg<MB, NB, WK, WN>, hipStre
 }
 
 template <>
-struct Shapes<3> : Shapes<2> {};
+struct Shapes<3> {  // BF16 three products: in 16 waves its operand fragments would spill
+  template <class F> static hipError_t pick(int K, F f) {
+    if (K > 128) return f(TileCfg<1, 2, 8, 1>{});
+    if (K > 64) return f(TileCfg<1, 2, 4, 2>{});
+    if (K > 32) return f(TileCfg<1, 2, 2, 4>{});
+    return f(TileCfg<1, 1, 1, 8>{});
+  }
+};
 
 int synth_tile_pixels(int max_K_alloc, int precision) {
   int nt = 0;
@@ -831,7 +843,9 @@ int synth_tile_pixels(int max_K_alloc, int precision) {
     nt = decltype(cfg)::NT;
     return hipSuccess;
   };
-  if (precision >= 2)
+  if (precision == 3)
+    Shapes<3>::pick(max_K_alloc, f);
+  else if (precision == 2)
     Shapes<2>::pick(max_K_alloc, f);
   else
     Shapes<0>::pick(max_K_alloc, f);
@@ -844,7 +858,9 @@ int synth_tile_kc(int max_K_alloc, int precision) {
     kc = decltype(cfg)::KC;
     return hipSuccess;
   };
-  if (precision >= 2)
+  if (precision == 3)
+    Shapes<3>::pick(max_K_alloc, f);
+  else if (precision == 2)
     Shapes<2>::pick(max_K_alloc, f);
   else
     Shapes<0>::pick(max_K_alloc, f);
