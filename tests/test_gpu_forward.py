@@ -473,3 +473,24 @@ def test_empty_batch_is_rejected(ctx):
     s.sync()
     assert torch.count_nonzero(s.images).item() == 0
     s.close()
+
+
+@pytest.mark.gpu
+def test_phase_probe_rejects_bad_arguments(ctx):
+    """Sizes out of range and null pointers are argument errors, found before anything is enqueued."""
+    from paper_2310_09200_amd import _lib
+    say("case phase probe errors")
+    dev = ctx.device
+    x = torch.zeros(3 * 1025, dtype=torch.float64, device=dev)
+    p = torch.zeros(3 * 4, dtype=torch.float64, device=dev)
+    out = torch.full((4,), 7.0, dtype=torch.float32, device=dev)
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    lib, h = ctx.lib, ctx.handle
+    assert lib.bb_phase_probe(h, 0, 2.0, vp(x), 4, vp(p), 1, vp(out)) == _lib.BB_ERR_INVALID_ARG
+    assert lib.bb_phase_probe(h, 1025, 2.0, vp(x), 4, vp(p), 1, vp(out)) == _lib.BB_ERR_INVALID_ARG
+    assert lib.bb_phase_probe(h, 3, 2.0, vp(x), 0, vp(p), 1, vp(out)) == _lib.BB_ERR_INVALID_ARG
+    assert lib.bb_phase_probe(h, 3, 2.0, vp(x), 4, vp(p), 0, vp(out)) == _lib.BB_ERR_INVALID_ARG
+    assert lib.bb_phase_probe(h, 3, -1.0, vp(x), 4, vp(p), 1, vp(out)) == _lib.BB_ERR_INVALID_ARG
+    assert lib.bb_phase_probe(h, 3, 2.0, None, 4, vp(p), 1, vp(out)) == _lib.BB_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert torch.all(out == 7.0)  # nothing was written
