@@ -438,11 +438,12 @@ def main():
                         / (peak[m] * 1e12)}
     out["modes"] = modes_out
     # phase generation (FP64 argument and reduction, hardware sin/cos) against its own peak on this device:
-    # the synthesis kernel evaluates every phase once per K pass of 256 eigenpairs (two passes at K = 512)
+    # the synthesis kernel evaluates every phase once per K pass of its tile (256 eigenpairs for K > 128)
     peak_pairs, probe_ms, probe_pairs = measure_phase_peak(torch, ctx, w, items)
-    n_pass = -(-512 // 256)
-    gen_pairs = float(n_pass) * 512 * w.n_pix * args.epochs
-    alg_pairs = 512.0 * w.n_pix * args.epochs
+    n_ant, n_eig, eig_per_pass = 512, 512, 256
+    n_pass = -(-n_eig // eig_per_pass)
+    alg_pairs = float(n_ant) * w.n_pix * args.epochs
+    gen_pairs = n_pass * alg_pairs
     out["phase_generation"] = {
         "peak_pairs_per_s": peak_pairs, "probe": f"bb_phase_probe: {probe_pairs:.3e} pairs in {probe_ms:.3f} ms",
         "pairs_per_launch": alg_pairs, "passes": n_pass,
