@@ -245,16 +245,18 @@ bb_status bb_synth_collect_eig(bb_synth h, int32_t slot, int32_t n_ant, int32_t 
  * instance per call).  inst is a host array of n_inst descriptors; the packed
  * device arrays hold every instance's data at the descriptor offsets:
  *  ant_xyz_packed  device, float64 n_ant_rows x 3 column-major (leading dim n_ant_rows)
- *  W_packed        device, complex64
- *  d_packed        device, float32
- *  level_packed    device, int32
- *  workspace       device, ws_bytes >= bb_batched_workspace_size(...)
+ *  W_packed        device, complex64, n_w_elems elements
+ *  d_packed        device, float32, n_eig_elems elements
+ *  level_packed    device, int32, n_eig_elems elements
+ *  workspace       device, 256-byte aligned, ws_bytes >= bb_batched_workspace_size(...)
+ * Every instance's rows, W block and eigenpairs must lie inside these lengths
+ * (BB_ERR_INVALID_ARG otherwise, found on the host before anything is enqueued).
  * Results equal calling bb_synth_collect_eig once per instance, up to the
  * order of floating-point summation across instances of one slot. */
 bb_status bb_batched_workspace_size(bb_synth h, int32_t n_inst, const bb_instance* inst, size_t* bytes);
 bb_status bb_synth_collect_eig_batched(bb_synth h, int32_t n_inst, const bb_instance* inst,
-                                       int64_t n_ant_rows, const double* ant_xyz_packed,
-                                       const void* W_packed, const float* d_packed,
+                                       int64_t n_ant_rows, int64_t n_w_elems, int64_t n_eig_elems,
+                                       const double* ant_xyz_packed, const void* W_packed, const float* d_packed,
                                        const int32_t* level_packed, void* workspace, size_t ws_bytes);
 
 /* Backward of collect_eig for the loss sum_l sum_p grad_images[l][p] * I_l(p)
@@ -333,8 +335,9 @@ bb_status bb_nufft_shape(bb_nufft h, int32_t* spread_grid, int32_t* fft_grid, in
  * in use until the stream reaches the work. */
 bb_status bb_nufft_batched_workspace_size(bb_nufft h, int32_t n_inst, const bb_instance* inst, size_t* bytes);
 bb_status bb_nufft_collect_eig_batched(bb_nufft h, int32_t n_inst, const bb_instance* inst, int64_t n_ant_rows,
-                                       const double* ant_xyz_packed, const void* W_packed, const float* d_packed,
-                                       const int32_t* level_packed, void* workspace, size_t ws_bytes);
+                                       int64_t n_w_elems, int64_t n_eig_elems, const double* ant_xyz_packed,
+                                       const void* W_packed, const float* d_packed, const int32_t* level_packed,
+                                       void* workspace, size_t ws_bytes);
 /* Transform what has been spread since the last emit, add it to the images,
  * and clear the grid. */
 bb_status bb_nufft_emit(bb_nufft h);

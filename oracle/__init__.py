@@ -10,7 +10,7 @@ Modules
 -------
 bluebild_ref
     Gram matrix, generalized eigensolve, selection, levels, phases, synthesis
-    (two evaluators), accumulation, and the closed-form images used as pins.
+    (two evaluators), and the closed-form images used as pins.
 grad_ref
     Analytic FP64 gradient of a weighted image loss w.r.t. (W, lambda, x),
     and central finite differences of the same loss.

@@ -17,8 +17,8 @@ C_LIGHT = 299_792_458.0
 __all__ = [
     "C_LIGHT", "wavelength", "gram", "check_hermitian", "geneig", "select_top", "n_eig_for_energy",
     "level_membership", "membership_from_level_of", "lsq_filter", "std_filter", "phases",
-    "synthesize_blas", "synthesize_loops", "collect", "collect_beamformed", "accumulate", "lsq_image",
-    "backprojection_image", "point_source_image", "rel_errors",
+    "synthesize_blas", "synthesize_loops", "collect", "collect_beamformed", "lsq_image",
+    "backprojection_image", "point_source_image",
 ]
 
 
@@ -111,7 +111,13 @@ def level_membership(lam, intervals):
 
 
 def membership_from_level_of(level_of, n_levels):
-    """(N_L, K) boolean from one level id per eigenpair (-1 = in no level)."""
+    """(N_L, K) boolean from one level id per eigenpair (-1 = in no level).
+
+    The same membership as :func:`level_membership` when the ids come from
+    intervals that share at most their endpoints (Algorithm 1's interval loop
+    with each eigenpair in at most one level): eigenpair k is in level l iff
+    level_of[k] == l.  An id outside [0, n_levels) puts the eigenpair in no level.
+    """
     level_of = np.asarray(level_of)
     return level_of[None, :] == np.arange(n_levels)[:, None]
 
@@ -216,12 +222,6 @@ def collect_beamformed(Vw, Wbf, x, wl, p, n_eig, intervals, filt="lsq"):
     return synthesize_blas(U, d, member, x, p, wl), lam, U, member
 
 
-def accumulate(images, slot, step_images):
-    """images[slot] += step_images: plain sum over time steps (Section 2.3; Algorithm 1 update)."""
-    images[slot] += step_images
-    return images
-
-
 def lsq_image(V, G, x, p, wl):
     """Least-squares image diag(Psi G^{-1} V G^{-1} Psi*) (Section 2.2, Eq. skyreco) by two solves.
 
@@ -246,15 +246,3 @@ def point_source_image(x, r0, p, wl, flux=1.0):
     t = (x @ (np.asarray(r0)[None, :] - p).T) / wl
     s = np.exp(2j * np.pi * t).sum(axis=0)
     return flux * (s.real ** 2 + s.imag ** 2)
-
-
-def rel_errors(img, ref):
-    """Per-level (max |I - I_ref| / max |I_ref|, rms(I - I_ref) / rms(I_ref)) for (N_L, N) arrays."""
-    img = np.asarray(img, np.float64).reshape(ref.shape[0], -1)
-    ref = np.asarray(ref, np.float64).reshape(ref.shape[0], -1)
-    out = []
-    for a, b in zip(img, ref):
-        mb = max(np.max(np.abs(b)), 1e-300)
-        rb = max(np.sqrt(np.mean(b * b)), 1e-300)
-        out.append((np.max(np.abs(a - b)) / mb, np.sqrt(np.mean((a - b) ** 2)) / rb))
-    return np.array(out)

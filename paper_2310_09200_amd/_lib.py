@@ -62,8 +62,8 @@ PROTOS = {
     "bb_synth_collect_eig": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_double, c_void_p, c_void_p,
                                        c_void_p, c_void_p]),
     "bb_batched_workspace_size": (c_int32, [c_void_p, c_int32, POINTER(bb_instance), POINTER(c_size_t)]),
-    "bb_synth_collect_eig_batched": (c_int32, [c_void_p, c_int32, POINTER(bb_instance), c_int64, c_void_p,
-                                               c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
+    "bb_synth_collect_eig_batched": (c_int32, [c_void_p, c_int32, POINTER(bb_instance), c_int64, c_int64, c_int64,
+                                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
     "bb_backward_workspace_size": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_size_t)]),
     "bb_synth_eig_backward": (c_int32, [c_void_p, c_int32, c_int32, c_double, c_void_p, c_void_p, c_void_p,
                                         c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
@@ -75,8 +75,8 @@ PROTOS = {
                                   c_size_t, POINTER(c_void_p)]),
     "bb_nufft_shape": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]),
     "bb_nufft_batched_workspace_size": (c_int32, [c_void_p, c_int32, c_void_p, POINTER(c_size_t)]),
-    "bb_nufft_collect_eig_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p,
-                                               c_void_p, c_void_p, c_size_t]),
+    "bb_nufft_collect_eig_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_int64, c_int64, c_int64, c_void_p,
+                                               c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
     "bb_nufft_emit": (c_int32, [c_void_p]),
     "bb_nufft_sync": (c_int32, [c_void_p]),
     "bb_nufft_timings": (c_int32, [c_void_p, POINTER(c_double), c_int32]),

@@ -7,12 +7,21 @@ weights d and the antenna positions x.  Level ids and pixels are not
 differentiated.
 """
 
+from collections import OrderedDict
+
 import torch
 
 from .synthesis import Context, StandardSynthesis
 
 _CTX = {}
-_SYNTH = {}
+# Handles keep their own column-major copy of the pixels, so a cache entry
+# holds the pixel tensor it was made from (its storage cannot be reused while
+# the entry lives) and is keyed on that tensor's identity and version counter
+# (an in-place edit bumps the version and misses the entry).  At most
+# _MAX_HANDLES handles are kept; the least recently used one is dropped (and
+# freed once no saved autograd context refers to it any more).
+_SYNTH = OrderedDict()
+_MAX_HANDLES = 4
 
 
 def _handle(pix, n_levels, n_ant, n_eig, precision):
@@ -20,11 +29,17 @@ def _handle(pix, n_levels, n_ant, n_eig, precision):
     ctx = _CTX.get(dev.index)
     if ctx is None:
         ctx = _CTX[dev.index] = Context(dev.index or 0)
-    key = (dev.index, pix.data_ptr(), int(pix.shape[0]), n_levels, precision)
-    s = _SYNTH.get(key)
-    if s is None or s.opt.n_ant_max < n_ant or s.opt.k_max < n_eig:
-        s = StandardSynthesis(ctx, pix, n_levels, 1, max(n_ant, 32), max(n_eig, 32), precision)
-        _SYNTH[key] = s
+    key = (dev.index, id(pix), pix._version, int(pix.shape[0]), n_levels, precision)
+    ent = _SYNTH.get(key)
+    if ent is not None and ent[0] is pix and ent[1].opt.n_ant_max >= n_ant and ent[1].opt.k_max >= n_eig:
+        _SYNTH.move_to_end(key)
+        return ent[1]
+    if ent is not None:
+        del _SYNTH[key]
+    s = StandardSynthesis(ctx, pix, n_levels, 1, max(n_ant, 32), max(n_eig, 32), precision)
+    _SYNTH[key] = (pix, s)
+    while len(_SYNTH) > _MAX_HANDLES:
+        _SYNTH.popitem(last=False)
     return s
 
 

@@ -642,7 +642,11 @@ struct BatchPlan {
   int max_K_alloc = 0, max_L_pad = 0;
 };
 
-bb_status plan_batch(bb_synth h, int32_t n_inst, const bb_instance* inst, int64_t n_ant_rows, BatchPlan& bp) {
+// n_w_elems / n_eig_elems: lengths of the packed W (complex elements) and of
+// the packed weights and level ids; negative skips those two checks (the
+// workspace-size query, which sees no arrays).
+bb_status plan_batch(bb_synth h, int32_t n_inst, const bb_instance* inst, int64_t n_ant_rows, int64_t n_w_elems,
+                     int64_t n_eig_elems, BatchPlan& bp) {
   bb_context ctx = h->ctx;
   if (n_inst < 1 || !inst) return fail(ctx, BB_ERR_INVALID_ARG, "empty instance table");
   std::vector<int> kcs;
@@ -652,6 +656,12 @@ bb_status plan_batch(bb_synth h, int32_t n_inst, const bb_instance* inst, int64_
     if (st != BB_OK) return st;
     if (b.ant_off < 0 || b.w_off < 0 || b.eig_off < 0 || b.ant_off + b.n_ant > n_ant_rows)
       return fail(ctx, BB_ERR_INVALID_ARG, "instance %d: offsets out of range", i);
+    if (n_w_elems >= 0 && b.w_off + (int64_t)b.n_ant * b.n_eig > n_w_elems)
+      return fail(ctx, BB_ERR_INVALID_ARG, "instance %d: W block [%lld, %lld) beyond the %lld packed elements", i,
+                  (long long)b.w_off, (long long)(b.w_off + (int64_t)b.n_ant * b.n_eig), (long long)n_w_elems);
+    if (n_eig_elems >= 0 && b.eig_off + b.n_eig > n_eig_elems)
+      return fail(ctx, BB_ERR_INVALID_ARG, "instance %d: eigenpairs [%lld, %lld) beyond the %lld packed elements", i,
+                  (long long)b.eig_off, (long long)(b.eig_off + b.n_eig), (long long)n_eig_elems);
     const int L_pad = bb::round_up(b.n_ant, bb::kAntChunk), K_alloc = bb::round_up(b.n_eig, 32);
     bp.max_K_alloc = std::max(bp.max_K_alloc, K_alloc);
     bp.max_L_pad = std::max(bp.max_L_pad, L_pad);
@@ -712,15 +722,16 @@ bb_status bb_batched_workspace_size(bb_synth h, int32_t n_inst, const bb_instanc
   BatchPlan bp;
   int64_t rows = 0;
   for (int i = 0; inst && i < n_inst; ++i) rows = std::max<int64_t>(rows, inst[i].ant_off + inst[i].n_ant);
-  bb_status st = plan_batch(h, n_inst, inst, rows, bp);
+  bb_status st = plan_batch(h, n_inst, inst, rows, -1, -1, bp);
   if (st != BB_OK) return st;
   *bytes = bp.total;
   return BB_OK;
 }
 
 bb_status bb_synth_collect_eig_batched(bb_synth h, int32_t n_inst, const bb_instance* inst, int64_t n_ant_rows,
-                                       const double* ant_xyz_packed, const void* W_packed, const float* d_packed,
-                                       const int32_t* level_packed, void* workspace, size_t ws_bytes) {
+                                       int64_t n_w_elems, int64_t n_eig_elems, const double* ant_xyz_packed,
+                                       const void* W_packed, const float* d_packed, const int32_t* level_packed,
+                                       void* workspace, size_t ws_bytes) {
   if (!h) return BB_ERR_INVALID_ARG;
   bb_context ctx = h->ctx;
   if (!ant_xyz_packed || !W_packed || !d_packed || !level_packed || !workspace)
@@ -728,7 +739,8 @@ bb_status bb_synth_collect_eig_batched(bb_synth h, int32_t n_inst, const bb_inst
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
     return fail(ctx, BB_ERR_INVALID_ARG, "workspace must be %zu-byte aligned", kAlign);
   BatchPlan bp;
-  bb_status st = plan_batch(h, n_inst, inst, n_ant_rows, bp);
+  if (n_w_elems < 0 || n_eig_elems < 0) return fail(ctx, BB_ERR_INVALID_ARG, "packed array lengths must be >= 0");
+  bb_status st = plan_batch(h, n_inst, inst, n_ant_rows, n_w_elems, n_eig_elems, bp);
   if (st != BB_OK) return st;
   if (ws_bytes < bp.total) return fail(ctx, BB_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, bp.total);
   BB_HIP(ctx, hipSetDevice(ctx->device));

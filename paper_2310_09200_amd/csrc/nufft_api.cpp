@@ -704,16 +704,18 @@ bb_status bb_nufft_batched_workspace_size(bb_nufft h, int32_t n_inst, const bb_i
 }
 
 bb_status bb_nufft_collect_eig_batched(bb_nufft h, int32_t n_inst, const bb_instance* inst, int64_t n_ant_rows,
-                                       const double* ant_xyz_packed, const void* W_packed, const float* d_packed,
-                                       const int32_t* level_packed, void* workspace, size_t ws_bytes) {
+                                       int64_t n_w_elems, int64_t n_eig_elems, const double* ant_xyz_packed,
+                                       const void* W_packed, const float* d_packed, const int32_t* level_packed,
+                                       void* workspace, size_t ws_bytes) {
   if (!h) return BB_ERR_INVALID_ARG;
   bb_context ctx = h->ctx;
   if (!h->parts.empty()) {
     BB_HIP(ctx, hipSetDevice(ctx->device));
     BB_HIP(ctx, hipEventRecord(h->ev[0], ctx->stream));
     for (NufftPart& q : h->parts) {
-      const bb_status st = bb_nufft_collect_eig_batched(q.sub, n_inst, inst, n_ant_rows, ant_xyz_packed, W_packed,
-                                                        d_packed, level_packed, workspace, ws_bytes);
+      const bb_status st = bb_nufft_collect_eig_batched(q.sub, n_inst, inst, n_ant_rows, n_w_elems, n_eig_elems,
+                                                        ant_xyz_packed, W_packed, d_packed, level_packed, workspace,
+                                                        ws_bytes);
       if (st != BB_OK) return st;
     }
     BB_HIP(ctx, hipEventRecord(h->ev[1], ctx->stream));
@@ -740,6 +742,8 @@ bb_status bb_nufft_collect_eig_batched(bb_nufft h, int32_t n_inst, const bb_inst
     if (!finite_pos(b.wavelength_m)) return fail(ctx, BB_ERR_INVALID_ARG, "instance %d: bad wavelength", i);
     if (b.ant_off < 0 || b.ant_off + b.n_ant > n_ant_rows || b.w_off < 0 || b.eig_off < 0)
       return fail(ctx, BB_ERR_INVALID_ARG, "instance %d: offsets out of range", i);
+    if (b.w_off + (int64_t)b.n_ant * b.n_eig > n_w_elems || b.eig_off + b.n_eig > n_eig_elems)
+      return fail(ctx, BB_ERR_INVALID_ARG, "instance %d: W block or eigenpairs beyond the packed arrays", i);
     bb::NufftInst& d = ni[i];
     d.n_ant = b.n_ant;
     d.n_eig = b.n_eig;

@@ -232,8 +232,8 @@ class StandardSynthesis:
         ws_ptr = (ws.data_ptr() + 255) // 256 * 256
         self.ctx.bind_current_stream()
         check(self.lib.bb_synth_collect_eig_batched(
-            self.handle, len(batch.inst), arr, batch.n_ant_rows, _ptr(batch.ant), _ptr(batch.W), _ptr(batch.d),
-            _ptr(batch.lev), ctypes.c_void_p(ws_ptr), sz.value), self.ctx.handle)
+            self.handle, len(batch.inst), arr, batch.n_ant_rows, batch.n_w, batch.n_eig_rows, _ptr(batch.ant),
+            _ptr(batch.W), _ptr(batch.d), _ptr(batch.lev), ctypes.c_void_p(ws_ptr), sz.value), self.ctx.handle)
         self._keep = [ws]
 
     def eig_backward(self, x, wavelength, W, d, level_of, grad_images):
@@ -361,8 +361,8 @@ class NufftSynthesis:
         ws_ptr = (ws.data_ptr() + 255) // 256 * 256
         self.ctx.bind_current_stream()
         check(self.lib.bb_nufft_collect_eig_batched(
-            self.handle, len(batch.inst), arr, batch.n_ant_rows, _ptr(batch.ant), _ptr(batch.W), _ptr(batch.d),
-            _ptr(batch.lev), ctypes.c_void_p(ws_ptr), sz.value), self.ctx.handle)
+            self.handle, len(batch.inst), arr, batch.n_ant_rows, batch.n_w, batch.n_eig_rows, _ptr(batch.ant),
+            _ptr(batch.W), _ptr(batch.d), _ptr(batch.lev), ctypes.c_void_p(ws_ptr), sz.value), self.ctx.handle)
         self._keep = [batch, ws]
 
     def emit(self):
@@ -394,7 +394,8 @@ class Batch:
     """Packed device arrays + instance table for :meth:`StandardSynthesis.collect_eig_batched`.
 
     ``items`` is a list of (slot, x (L,3), wavelength, W (L,K), d (K,), level_of (K,)); arrays may be
-    numpy arrays or tensors on any device.
+    numpy arrays or tensors on any device.  ``products`` counts antennas x kept eigenpairs (level id
+    >= 0) over the instances: the complex products per pixel that the synthesis performs.
     """
 
     def __init__(self, items, device):
@@ -420,4 +421,9 @@ class Batch:
         self.d = torch.cat(ds)
         self.lev = torch.cat(ls)
         self.inst = inst
-        self.products = sum(int(i.n_ant) * int(i.n_eig) for i in inst)
+        self.n_w = int(self.W.numel())
+        self.n_eig_rows = int(self.d.numel())
+        # pixel-independent work: antennas x kept eigenpairs (level id >= 0) summed over instances
+        kept = (self.lev.cpu().numpy() >= 0).astype(np.int64)
+        csum = np.concatenate([[0], np.cumsum(kept)])
+        self.products = sum(int(i.n_ant) * int(csum[i.eig_off + i.n_eig] - csum[i.eig_off]) for i in inst)

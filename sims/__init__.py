@@ -33,4 +33,5 @@ from .visibilities import (  # noqa: F401
 )
 from .levels import kmeans1d_intervals, levels_from_intervals  # noqa: F401
 from .random_fields import random_eigvecs, random_eigvals  # noqa: F401
+from .sampling import sample_pixels  # noqa: F401
 from . import configs  # noqa: F401

@@ -4,6 +4,8 @@ import os
 import subprocess
 import sys
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
@@ -16,11 +18,29 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert r.stdout.strip() == ""
 
 
-def test_traffic_figure_is_keyed_to_the_kernel_source():
+def test_counter_figures_are_keyed_to_the_kernel_source(tmp_path, monkeypatch):
+    """Counter figures are read only while the summary names the current kernel source's hash."""
     import bench
-    assert bench.measured_traffic("no such mode") is None
-    rec = bench.MEASURED_TRAFFIC["fp32_3m"]
-    got = bench.measured_traffic("fp32_3m")
-    # either the recorded counter figure (source unchanged since the counters) or null
-    assert got is None or got == rec["bytes"]
-    assert rec["bytes"] > 0 and len(rec["kernel_source_sha256"]) == 64
+    sha = bench.kernel_source_sha256()
+    f = tmp_path / "c.md"
+    f.write_text(f"# x\n\n`kernel_source_sha256: {sha}`\n`fp32_3m.fetch_bytes: 1.5e10`\n"
+                 "`fp32_3m.write_bytes: 2e9`\n`fp32_3m.mfma_busy: 0.85`\nfp32.mfma_busy: 0.9\n")
+    monkeypatch.setattr(bench, "COUNTER_SUMMARY", str(f))
+    got = bench.counter_figures("fp32_3m")
+    assert got == {"fetch_bytes": 1.5e10, "write_bytes": 2e9, "mfma_busy": 0.85}
+    assert bench.counter_figures("fp32") == {"mfma_busy": 0.9}
+    assert bench.counter_figures("bf16x3") is None
+    f.write_text(f.read_text().replace(sha, "0" * 64))
+    assert bench.counter_figures("fp32_3m") is None          # stale: another kernel source
+    monkeypatch.setattr(bench, "COUNTER_SUMMARY", str(tmp_path / "missing.md"))
+    assert bench.counter_figures("fp32_3m") is None
+
+
+def test_level_errors_definition():
+    """Per level: max error over the reference's peak, rms error over the reference's rms; empty levels skipped."""
+    import bench
+    want = np.array([[1.0, -2.0, 4.0], [0.0, 0.0, 0.0], [3.0, 3.0, 3.0]])
+    got = want + np.array([[0.4, 0.0, 0.0], [5.0, 0.0, 0.0], [0.0, 0.0, -0.3]])
+    mx, rms = bench.level_errors(got, want)
+    assert np.allclose(mx, [0.1, 0.1])
+    assert np.allclose(rms, [np.sqrt(0.16 / 3 / (21 / 3)), np.sqrt(0.09 / 3 / 9.0)])

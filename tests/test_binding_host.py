@@ -29,7 +29,10 @@ def test_batch_packing_offsets_and_layout():
     assert [i.ant_off for i in b.inst] == [0, 5, 12]
     assert [i.w_off for i in b.inst] == [0, 15, 29]
     assert [i.eig_off for i in b.inst] == [0, 3, 5]
-    assert b.products == 5 * 3 + 7 * 2 + 4 * 4
+    # products count antennas x kept eigenpairs (level id >= 0), the work the synthesis does per pixel
+    assert b.products == sum(x.shape[0] * int((np.asarray(lev) >= 0).sum()) for _, x, _, _, _, lev in items)
+    assert b.products < 5 * 3 + 7 * 2 + 4 * 4       # this draw drops some eigenpairs
+    assert b.n_w == 5 * 3 + 7 * 2 + 4 * 4 and b.n_eig_rows == 3 + 2 + 4
     ant = b.ant.numpy()                       # column-major n_rows x 3
     Wp = b.W.numpy()
     for (slot, x, wl, W, d, lev), inst in zip(items, b.inst):

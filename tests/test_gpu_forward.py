@@ -243,32 +243,21 @@ def test_batched_uneven_instances(ctx, precision):
         assert np.all(err[:, 0] <= TOL[precision]), (sl, err)
 
 
-def _sample_pixels(n_side, src, stride=8):
-    iy, ix = np.meshgrid(np.arange(0, n_side, stride), np.arange(0, n_side, stride), indexing="ij")
-    sel = set((iy * n_side + ix).ravel().tolist())
-    for p in src:
-        cy, cx = divmod(int(p), n_side)
-        for dy in range(-4, 5):
-            for dx in range(-4, 5):
-                y, x_ = cy + dy, cx + dx
-                if 0 <= y < n_side and 0 <= x_ < n_side:
-                    sel.add(y * n_side + x_)
-    return np.array(sorted(sel))
+@pytest.fixture(scope="module")
+def c2_case():
+    """Twelve C2 epochs spread over the 6 h track, FP64 oracle eigenpairs, sampled pixels.
 
-
-@pytest.mark.parametrize("precision", ["fp32", "fp32_3m", "bf16x3", "bf16x3_3m"])
-def test_c2_full_size_sampled(ctx, precision):
-    """C2 at full size (L=512, K=512, 1024^2, 8+1 levels) in the benchmarked launch (batched), sampled pixels."""
-    from paper_2310_09200_amd import Batch, StandardSynthesis
-    say(f"case C2 full size precision={precision}")
+    Pixels: every 8th row and column of the 1024^2 grid, the 9 x 9
+    neighbourhood of every point source, and the last pixel.
+    """
     w = configs.c2(n_steps=100)
-    steps = [0, 63, 99]
-    sel = _sample_pixels(w.n_side, w.source_pixels(), stride=16)
+    steps = np.linspace(0, 99, 12).round().astype(int)
+    sel = sims.sample_pixels(w.n_side, w.source_pixels(), stride=8)
     want = np.zeros((9, sel.size))
     iv = None
     items = []
     for st in steps:
-        inst = w.instance(st)
+        inst = w.instance(int(st))
         lam, A = ref.geneig(inst.V, ref.gram(inst.x, inst.wl))
         lam, W = ref.select_top(lam, A, 512)
         if iv is None:
@@ -277,6 +266,15 @@ def test_c2_full_size_sampled(ctx, precision):
         W64 = W.astype(np.complex64)
         want += oracle_images(W64.astype(np.complex128), lam.astype(np.float32), lev, inst.x, inst.wl, w.pix[sel], 9)
         items.append((0, inst.x, inst.wl, W64, lam.astype(np.float32), lev))
+    return w, steps, sel, items, want
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_3m", "bf16x3", "bf16x3_3m"])
+def test_c2_full_size_sampled(ctx, c2_case, precision):
+    """C2 at full size (L=512, K=512, 1024^2, 8+1 levels) in the benchmarked launch (batched), sampled pixels."""
+    from paper_2310_09200_amd import Batch, StandardSynthesis
+    w, steps, sel, items, want = c2_case
+    say(f"case C2 full size precision={precision} epochs={len(steps)} sampled pixels={sel.size}")
     s = StandardSynthesis(ctx, w.pix, 9, 1, 512, 512, precision)
     s.collect_eig_batched(Batch(items, ctx.device))
     s.sync()
@@ -284,6 +282,7 @@ def test_c2_full_size_sampled(ctx, precision):
     s.close()
     err = level_errors(got, want)
     say("C2 max err per level", err[:, 0])
+    say("C2 rms err per level", err[:, 1])
     assert np.all(err[:, 0] <= TOL[precision]), err
 
 
@@ -465,13 +464,50 @@ def test_empty_batch_is_rejected(ctx):
     lev = torch.zeros(1, dtype=torch.int32, device=dev)
     ws = torch.zeros(4096, dtype=torch.uint8, device=dev)
     ws_ptr = (ws.data_ptr() + 255) // 256 * 256
-    st = s.lib.bb_synth_collect_eig_batched(s.handle, 0, None, 1, ctypes.c_void_p(ant.data_ptr()),
+    st = s.lib.bb_synth_collect_eig_batched(s.handle, 0, None, 1, 1, 1, ctypes.c_void_p(ant.data_ptr()),
                                             ctypes.c_void_p(W.data_ptr()), ctypes.c_void_p(d.data_ptr()),
                                             ctypes.c_void_p(lev.data_ptr()), ctypes.c_void_p(ws_ptr), 2048)
     assert st == _lib.BB_ERR_INVALID_ARG
     assert b"empty" in s.lib.bb_last_error(ctx.handle)
     s.sync()
     assert torch.count_nonzero(s.images).item() == 0
+    s.close()
+
+
+@pytest.mark.gpu
+def test_batched_instance_table_out_of_range_is_rejected(ctx):
+    """An instance whose W block or eigenpairs run past the packed arrays is an argument error.
+
+    The lengths of the packed arrays go into the call, so a wrong table is
+    caught on the host: nothing is enqueued and the images stay as they were.
+    """
+    from paper_2310_09200_amd import Batch, StandardSynthesis, _lib
+    say("case batched table out of range")
+    g = np.random.default_rng(4)
+    L, K = 40, 24
+    x = sims.disk_layout(L, 100.0, g)
+    W = (g.normal(size=(L, K)) + 1j * g.normal(size=(L, K))) / np.sqrt(2 * L)
+    d = np.ones(K)
+    lev = np.zeros(K, np.int32)
+    s = StandardSynthesis(ctx, sims.pixel_grid(16, 5.0, 90.0), 1, 1, 64, 32)
+    b = Batch([(0, x, 2.0, W, d, lev), (0, x, 2.0, W, d, lev)], ctx.device)
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    ws = torch.zeros(1 << 22, dtype=torch.uint8, device=ctx.device)
+    ws_ptr = ctypes.c_void_p((ws.data_ptr() + 255) // 256 * 256)
+    for field, delta in (("w_off", 1), ("eig_off", 1), ("w_off", L * K), ("eig_off", K)):
+        inst = [_lib.bb_instance(n_ant=i.n_ant, n_eig=i.n_eig, slot=i.slot, wavelength_m=i.wavelength_m,
+                                 ant_off=i.ant_off, w_off=i.w_off, eig_off=i.eig_off) for i in b.inst]
+        setattr(inst[1], field, getattr(inst[1], field) + delta)
+        arr = (_lib.bb_instance * 2)(*inst)
+        st = s.lib.bb_synth_collect_eig_batched(s.handle, 2, arr, b.n_ant_rows, b.n_w, b.n_eig_rows, vp(b.ant),
+                                                vp(b.W), vp(b.d), vp(b.lev), ws_ptr, (1 << 22) - 256)
+        assert st == _lib.BB_ERR_INVALID_ARG, (field, delta, st)
+        assert b"beyond the" in s.lib.bb_last_error(ctx.handle)
+    s.sync()
+    assert torch.count_nonzero(s.images).item() == 0
+    s.collect_eig_batched(b)  # the table itself is valid
+    s.sync()
+    assert torch.count_nonzero(s.images).item() > 0
     s.close()
 
 

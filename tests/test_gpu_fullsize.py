@@ -4,6 +4,10 @@ C3: SKA-Low-like precision study (L=512, K=512, 2048^2 pixels, 65 km baselines),
     FP32 and BF16x3 contraction, several epochs in one batched launch.
 C4: 2048 uneven instances (L 200..512, K 16..128, 64 channel slots, 512^2 pixels)
     in one batched launch.
+C2 pre-step: one LOFAR-like epoch (L=512) through the full step on the GPU
+    (FP64 Gram, rocSOLVER generalized eigensolve, selection, synthesis).
+Translation: a geocentric offset of every antenna leaves the images unchanged
+    (the FP64 phase argument and its exact reduction).
 """
 
 import sys
@@ -33,24 +37,11 @@ def ctx(gpu):
     return Context(0)
 
 
-def sample_pixels(n_side, src, stride):
-    iy, ix = np.meshgrid(np.arange(0, n_side, stride), np.arange(0, n_side, stride), indexing="ij")
-    sel = set((iy * n_side + ix).ravel().tolist())
-    for p in src:
-        cy, cx = divmod(int(p), n_side)
-        for dy in range(-4, 5):
-            for dx in range(-4, 5):
-                if 0 <= cy + dy < n_side and 0 <= cx + dx < n_side:
-                    sel.add((cy + dy) * n_side + cx + dx)
-    sel.add(n_side * n_side - 1)   # last pixel (ragged tail of the last tile)
-    return np.array(sorted(sel))
-
-
 @pytest.fixture(scope="module")
 def c3_case():
     w = configs.c3()
     epochs = [0, 17, 33, 49]
-    sel = sample_pixels(w.n_side, w.source_pixels(), 64)
+    sel = sims.sample_pixels(w.n_side, w.source_pixels(), 64)
     items, want, iv = [], np.zeros((9, sel.size)), None
     for e in epochs:
         inst = w.instance(e)
@@ -115,3 +106,78 @@ def test_c4_batched_full_size(ctx):
         worst = max(worst, float(np.max(err[:, 0])))
     say(f"C4 worst per-level max err over 64 slots: {worst:.2e}")
     assert worst <= 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp32_3m", "bf16x3_3m"])
+def test_c2_full_step_prestep_on_gpu(ctx, precision):
+    """Full Algorithm 1 step at the C2 size: GPU Gram + FP64 eigensolve (L = 512) + selection + synthesis.
+
+    Compared with the oracle's own full step (Gram, Cholesky reduction and
+    eigh in FP64, selection, closed-interval levels) on sampled pixels of the
+    1024^2 grid.  The eigenvectors of the two eigensolvers differ by a phase
+    per eigenpair (the images do not); the level bounds sit at eigenvalue-gap
+    midpoints, so membership does not depend on the last bits of either solver.
+    """
+    from paper_2310_09200_amd import StandardSynthesis
+    w = configs.c2(n_steps=100)
+    inst = w.instance(37)
+    say(f"case C2 full step (GPU pre-step) precision={precision}, epoch 37")
+    sel = sims.sample_pixels(w.n_side, w.source_pixels(), 16)
+    lam, A = ref.geneig(inst.V, ref.gram(inst.x, inst.wl))
+    lam, W = ref.select_top(lam, A, 512)
+    iv = sims.kmeans1d_intervals(lam, 8, negative_level=True)
+    want, lam_o, _, _ = ref.collect(inst.V, inst.x, inst.wl, w.pix[sel], 512, iv)
+    s = StandardSynthesis(ctx, w.pix, 9, 1, 512, 512, precision)
+    s.collect(0, inst.x, inst.wl, inst.V, 512, iv)
+    s.sync()
+    got = s.images[0][:, torch.as_tensor(sel, device=ctx.device)].double().cpu().numpy()
+    Wg, lam_g, _, lev_g = s.prestep(inst.x, inst.wl, inst.V, 512, iv)
+    s.sync()
+    s.close()
+    lam_g = lam_g.cpu().numpy()
+    say(f"eigenvalues: max |GPU - oracle| / max |lam| = {np.max(np.abs(lam_g - lam_o)) / np.max(np.abs(lam_o)):.2e}")
+    assert np.max(np.abs(lam_g - lam_o)) <= 1e-10 * np.max(np.abs(lam_o))
+    assert np.array_equal(lev_g.cpu().numpy(), sims.levels_from_intervals(lam_o, iv))
+    err = level_errors(got, want)
+    say(f"C2 full step {precision} per-level max err {err[:, 0]}")
+    assert np.all(err[:, 0] <= TOL[precision]), err
+
+
+@pytest.mark.parametrize("precision", ["fp32_3m", "bf16x3_3m"])
+def test_geocentric_translation_leaves_images_unchanged(ctx, precision):
+    """Translation invariance on the GPU: every antenna moved by (6.4e6, -1.1e6, 3.3e5) m.
+
+    The phase of every antenna at a pixel shifts by the same <c, p> / lambda
+    (about 3.3e6 turns here), which |E|^2 does not see.  With an FP32 phase
+    argument the shift alone would leave errors of order one; with the FP64
+    argument and its exact reduction the images stay within the contraction's
+    own rounding.  SKA-Low-like epoch (512 stations, 65 km baselines), full
+    2048^2 grid; both images also checked against the oracle on sampled pixels.
+    """
+    from paper_2310_09200_amd import StandardSynthesis
+    w = configs.c3()
+    inst = w.instance(11)
+    say(f"case geocentric translation precision={precision}")
+    lam, A = ref.geneig(inst.V, ref.gram(inst.x, inst.wl))
+    lam, W = ref.select_top(lam, A, 512)
+    iv = sims.kmeans1d_intervals(lam, 8, negative_level=True)
+    lev = sims.levels_from_intervals(lam, iv)
+    W64 = W.astype(np.complex64)
+    shift = np.array([6.4e6, -1.1e6, 3.3e5])
+    imgs = []
+    for x in (inst.x, inst.x + shift[None, :]):
+        s = StandardSynthesis(ctx, w.pix, 9, 1, 512, 512, precision)
+        s.collect_eig(0, x, inst.wl, W64, lam.astype(np.float32), lev)
+        s.sync()
+        imgs.append(s.images[0].double().cpu().numpy())
+        s.close()
+    err = level_errors(imgs[1], imgs[0])
+    say(f"translated vs original, per-level max {err[:, 0]}")
+    assert np.all(err[:, 0] <= 1e-5), err
+    sel = sims.sample_pixels(w.n_side, w.source_pixels(), 128)
+    member = ref.membership_from_level_of(lev, 9)
+    want = ref.synthesize_blas(W64.astype(np.complex128), lam.astype(np.float32).astype(np.float64), member,
+                               inst.x, w.pix[sel], inst.wl)
+    for img in imgs:
+        e = level_errors(img[:, sel], want)
+        assert np.all(e[:, 0] <= TOL[precision]), e

@@ -145,6 +145,44 @@ def test_level_membership_closed_intervals():
     assert np.array_equal(m, expect)
 
 
+def test_membership_from_level_ids():
+    """Membership from one level id per eigenpair (the form the GPU tests pass level ids in).
+
+    A hand-written case (ids -1 and out of range add nothing, repeated ids),
+    then agreement with the interval test for disjoint k-means intervals,
+    with the ids found by a plain search for the interval holding each value,
+    and the images it gives: the levels of a partition add up to the
+    single-level image of every kept eigenpair (a swapped axis or an
+    off-by-one level index fails one of these).
+    """
+    m = ref.membership_from_level_of(np.array([0, 2, -1, 1, 2, 5, 0]), 3)
+    expect = np.array([[1, 0, 0, 0, 0, 0, 1], [0, 0, 0, 1, 0, 0, 0], [0, 1, 0, 0, 1, 0, 0]], bool)
+    assert m.shape == (3, 7) and np.array_equal(m, expect)
+    assert not ref.membership_from_level_of(np.array([-1, -1]), 2).any()
+
+    x, wl, pix, V, _ = tiny_case(L=16, seed=5)
+    lam, A = ref.geneig(V, ref.gram(x, wl))
+    lam, W = ref.select_top(lam, A, 12)
+    iv = sims.kmeans1d_intervals(lam, 3, negative_level=True)
+    ids = np.full(lam.size, -1)
+    for k, v in enumerate(lam):
+        for lv in range(iv.shape[0]):
+            if iv[lv, 0] <= v <= iv[lv, 1]:
+                ids[k] = lv
+                break
+    assert (ids >= 0).all()
+    m = ref.membership_from_level_of(ids, iv.shape[0])
+    assert np.array_equal(m, ref.level_membership(lam, iv))
+    d = ref.lsq_filter(lam)
+    levels = ref.synthesize_blas(W, d, m, x, pix, wl)
+    whole = ref.synthesize_blas(W, d, np.ones((1, lam.size), bool), x, pix, wl)[0]
+    assert rel(levels.sum(0), whole) < 1e-12
+    for lv in range(iv.shape[0]):
+        only = ref.synthesize_blas(W[:, ids == lv], d[ids == lv], np.ones((1, int((ids == lv).sum())), bool),
+                                   x, pix, wl)[0]
+        assert rel(levels[lv], only) < 1e-12
+
+
 # ---------------------------------------------------------------- P3: non-negativity
 def test_nonnegative_levels_for_psd_visibilities():
     """P3: V PSD and G PD => all lam >= 0 (Sylvester inertia) and every level image >= 0."""
