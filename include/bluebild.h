@@ -189,6 +189,34 @@ bb_status bb_synth_prestep(bb_synth h, int32_t n_ant, double wavelength_m, const
                            const double* vis, int32_t n_eig, const double* intervals, void* W_out,
                            double* lam_out, float* d_out, int32_t* level_out);
 
+/* The FP64 pre-step of bb_synth_prestep for n_inst instances of one antenna
+ * count at once (Algorithm 1's per-step Gram, eigensolve and selection, over
+ * many time steps or channels): the Gram matrices, one strided-batched
+ * generalized eigensolve and the selections are enqueued together, and the
+ * call waits once for all solver statuses instead of once per instance.
+ *  n_inst          >= 1
+ *  n_ant, n_eig    as bb_synth_prestep (1 <= n_eig <= n_ant, n_eig <= k_max)
+ *  wavelengths_m   host, float64 n_inst
+ *  ant_xyz_packed  device, float64 (n_inst n_ant) x 3 column-major (leading
+ *                  dimension n_inst n_ant); instance i at rows i n_ant ..
+ *  vis_packed      device, complex128, n_inst column-major n_ant x n_ant
+ *                  matrices one after the other, each Hermitian
+ *  intervals       host, as bb_synth_collect (one partition for all instances)
+ *  W_out, lam_out, d_out, level_out  device, as bb_synth_prestep per instance,
+ *                  instance i at element i n_ant n_eig of W_out and i n_eig of
+ *                  the others: the packed layout bb_synth_collect_eig_batched
+ *                  takes (ant_off = i n_ant, w_off = i n_ant n_eig, eig_off = i n_eig)
+ *  workspace       device, 256-byte aligned,
+ *                  ws_bytes >= bb_prestep_batched_workspace_size(...)
+ *                  (two n_ant^2 complex128 matrices per instance plus the solver's area)
+ * Errors as bb_synth_prestep, naming the first failing instance; the outputs
+ * are then not written.  Images untouched. */
+bb_status bb_prestep_batched_workspace_size(bb_synth h, int32_t n_inst, int32_t n_ant, int32_t n_eig, size_t* bytes);
+bb_status bb_synth_prestep_batched(bb_synth h, int32_t n_inst, int32_t n_ant, int32_t n_eig,
+                                   const double* wavelengths_m, const double* ant_xyz_packed, const double* vis_packed,
+                                   const double* intervals, void* W_out, double* lam_out, float* d_out,
+                                   int32_t* level_out, void* workspace, size_t ws_bytes);
+
 /* Energy levels by k-means on the eigenvalues (Section 2.6; the split of the
  * positive eigenvalues into levels plus one level for every negative
  * eigenvalue follows Section 4.2).  The positive eigenvalues are cut into

@@ -36,12 +36,16 @@ Readings (the paper gives the steps, not the constants):
   * w is evaluated as ceil(log10(1 / eps) - 1e-9) + 1, so that a tolerance
     that is a power of ten does not gain a point from rounding;
   * grid coordinates are formed as x * (1 / h) for sources and
-    (s - D) * (h * M) for targets, and the w points used are
-    ceil(xi - w/2) .. ceil(xi - w/2) + w - 1.  The kernel is e^{-beta}, not 0,
-    at the ends of its support, so when a coordinate lands exactly on a grid
-    point (the extreme pixels do: they sit at +-S, i.e. at +-M/4) the choice
-    of the dropped end changes the result by about e^{-beta} of a grid value;
-    the arithmetic above fixes that choice;
+    (s - D) * (h * M) for targets, and the w points used are the half-open
+    window [xi - w/2, xi + w/2): ceil(xi - w/2) .. ceil(xi - w/2) + w - 1.
+    The kernel is e^{-beta}, not 0, at the ends of its support, so when a
+    coordinate lands exactly on a grid point (the extreme pixels do: they sit
+    at +-S, i.e. at +-M/4) the window could keep either end, and the two
+    choices differ by about e^{-beta} of a grid value.  Section 3.4 fixes
+    neither the window nor the arithmetic of the coordinates; both are a
+    convention here (``tie="low"`` keeps the lower end, ``tie="high"`` the
+    upper one), and either meets the same accuracy bound against the exact
+    sum (pinned on the CPU), which is what the method promises;
   * "smooth" is the least even integer >= n with no prime factor above 5;
   * kernel Fourier transforms are evaluated by 100-node Gauss-Legendre
     quadrature of the (even) kernel.
@@ -136,18 +140,29 @@ def kernel_ft(k, half_width, beta):
     return half_width * np.cos(np.multiply.outer(k * half_width, t)) @ (wq * vals)
 
 
-def _neighbours(xi, w):
-    """Integer grid points within w/2 of xi (w of them), and the kernel arguments (g - xi) / (w/2)."""
-    first = np.ceil(xi - 0.5 * w).astype(np.int64)
+def _neighbours(xi, w, tie="low"):
+    """The w integer grid points of the window around xi, and the kernel arguments (g - xi) / (w/2).
+
+    tie="low": the half-open window [xi - w/2, xi + w/2); tie="high": (xi - w/2, xi + w/2].
+    They differ only when xi - w/2 is an integer.
+    """
+    if tie == "low":
+        first = np.ceil(xi - 0.5 * w).astype(np.int64)
+    elif tie == "high":
+        first = np.floor(xi - 0.5 * w).astype(np.int64) + 1
+    else:
+        raise ValueError("tie must be 'low' or 'high'")
     g = first[..., None] + np.arange(w)
     return g, (g - xi[..., None]) / (0.5 * w)
 
 
-def nufft3(c, x, s, eps, X=None):
+def nufft3(c, x, s, eps, X=None, tie="low"):
     """Type-3 NUFFT approximation of nudft3(c, x, s) in the steps of Section 3.4.
 
     c: (n_src, n_ch) strengths (several channels share the coordinates);
-    x: (n_src, 3) sources, centred at 0, |x_d| <= X_d; s: (n_tgt, 3) targets.
+    x: (n_src, 3) sources, centred at 0, |x_d| <= X_d; s: (n_tgt, 3) targets;
+    tie: which end of the kernel window is kept when a grid coordinate sits
+    exactly half a support from a grid point (see the module notes).
     Returns (n_tgt, n_ch) complex128.
     """
     c = np.asarray(c, np.complex128)
@@ -171,7 +186,7 @@ def nufft3(c, x, s, eps, X=None):
     grid = np.zeros((c.shape[1],) + tuple(N), np.complex128)
     gi, ki = [], []
     for d in range(3):
-        g, z = _neighbours(xi[:, d], w)
+        g, z = _neighbours(xi[:, d], w, tie)
         gi.append(np.mod(g, N[d]))
         ki.append(es_kernel(z, beta))
     n_src = x.shape[0]
@@ -202,7 +217,7 @@ def nufft3(c, x, s, eps, X=None):
     eta = st * (h * M)[None, :]                   # targets in type-2 grid units (2 pi s h M / (2 pi))
     gi, ki = [], []
     for d in range(3):
-        g, z = _neighbours(eta[:, d], w)
+        g, z = _neighbours(eta[:, d], w, tie)
         gi.append(np.mod(g, M[d]))
         ki.append(es_kernel(z, beta))
     n_tgt = s.shape[0]
@@ -217,12 +232,12 @@ def nufft3(c, x, s, eps, X=None):
     return F / phi_hat[:, None]
 
 
-def nufft_images(instances, pix, eps, X=None, frame=None):
+def nufft_images(instances, pix, eps, X=None, frame=None, tie="low"):
     """Level images summed over instances by NUFFT synthesis.
 
     instances: iterable of (x (L, 3) metres, wavelength, W (L, K), d (K,), member (N_L, K) bool).
     frame: rows e_u, e_v, p0 (default: the identity); X: per-axis bound on |b| in
-    wavelengths in that frame (default: the largest over the instances).
+    wavelengths in that frame (default: the largest over the instances); tie: as in nufft3.
     Returns (N_L, N_pix) float64.
     """
     R = np.eye(3) if frame is None else np.asarray(frame, np.float64)
@@ -235,7 +250,7 @@ def nufft_images(instances, pix, eps, X=None, frame=None):
         diag = diag + np.real(np.einsum("nll->n", Vp))
     pos = np.concatenate(pos)
     val = np.concatenate(val)
-    f = nufft3(val, pos, rotate(pix, R), eps, X=X)             # (N_pix, N_L)
+    f = nufft3(val, pos, rotate(pix, R), eps, X=X, tie=tie)    # (N_pix, N_L)
     return (2.0 * np.real(f)).T + np.asarray(diag)[:, None]
 
 

@@ -67,6 +67,10 @@ PROTOS = {
     "bb_backward_workspace_size": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_size_t)]),
     "bb_synth_eig_backward": (c_int32, [c_void_p, c_int32, c_int32, c_double, c_void_p, c_void_p, c_void_p,
                                         c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
+    "bb_prestep_batched_workspace_size": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_size_t)]),
+    "bb_synth_prestep_batched": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_double), c_void_p,
+                                           c_void_p, POINTER(c_double), c_void_p, c_void_p, c_void_p, c_void_p,
+                                           c_void_p, c_size_t]),
     "bb_synth_levels_kmeans": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p]),
     "bb_synth_uniform_weighting": (c_int32, [c_void_p, c_int32, c_double, c_void_p, POINTER(c_double),
                                              POINTER(c_double), c_double, c_void_p]),

@@ -194,33 +194,43 @@ InstDesc staging_desc(bb_synth h, char* base, int L, int K, double wl, int slot)
   return d;
 }
 
-// Stage + synthesize one instance whose descriptor is `d` (single-instance calls).
-bb_status run_single(bb_synth h, const InstDesc& d) {
-  bb_context ctx = h->ctx;
+// Stage + synthesize one instance whose descriptor is `d` (its staging
+// regions already point into `stage`'s owner), with the metadata block at
+// `meta` and the device error word at `err`; ev_staged / ev_done (may be
+// null) are recorded after staging and after the synthesis.
+bb_status launch_single(bb_context ctx, SingleMeta* meta, int* err, const InstDesc& d, const double* pix,
+                        int64_t n_pix, float* images, int n_levels, int precision, hipEvent_t ev_staged,
+                        hipEvent_t ev_done) {
   hipStream_t s = ctx->stream;
-  SingleMeta* meta = at<SingleMeta>(h, h->lay.meta);
   hipLaunchKernelGGL(write_meta_kernel, dim3(1), dim3(1), 0, s, meta, d, d.slot);
   BB_HIP(ctx, hipGetLastError());
-  BB_HIP(ctx, bb::launch_stage(&meta->desc, &meta->dyn, 1, d.K_alloc, d.L_pad, h->opt.n_levels, h->opt.precision,
-                               at<int>(h, h->lay.err), s));
-  BB_HIP(ctx, hipEventRecord(h->ev[2], s));
+  BB_HIP(ctx, bb::launch_stage(&meta->desc, &meta->dyn, 1, d.K_alloc, d.L_pad, n_levels, precision, err, s));
+  if (ev_staged) BB_HIP(ctx, hipEventRecord(ev_staged, s));
   bb::FwdParams p{};
-  p.pix = h->pix;
-  p.pix_ld = h->n_pix;
-  p.n_pix = h->n_pix;
+  p.pix = pix;
+  p.pix_ld = n_pix;
+  p.n_pix = n_pix;
   p.descs = &meta->desc;
   p.dyn = &meta->dyn;
   p.group_slot = &meta->group_slot;
   p.group_begin = meta->group_begin;
   p.inst_list = &meta->inst_list;
-  p.img = h->images;
-  p.img_ld = h->n_pix;
-  p.n_levels = h->opt.n_levels;
-  const int nt = bb::synth_tile_pixels(d.K_alloc, h->opt.precision);
-  p.n_tiles = (h->n_pix + nt - 1) / nt;
+  p.img = images;
+  p.img_ld = n_pix;
+  p.n_levels = n_levels;
+  const int nt = bb::synth_tile_pixels(d.K_alloc, precision);
+  p.n_tiles = (n_pix + nt - 1) / nt;
   p.n_groups = 1;
-  BB_HIP(ctx, bb::launch_synth(p, d.K_alloc, h->opt.precision, nullptr, s));
-  BB_HIP(ctx, hipEventRecord(h->ev[3], s));
+  BB_HIP(ctx, bb::launch_synth(p, d.K_alloc, precision, nullptr, s));
+  if (ev_done) BB_HIP(ctx, hipEventRecord(ev_done, s));
+  return BB_OK;
+}
+
+// Single-instance calls on a handle: staging in the handle's workspace.
+bb_status run_single(bb_synth h, const InstDesc& d) {
+  bb_status st = launch_single(h->ctx, at<SingleMeta>(h, h->lay.meta), at<int>(h, h->lay.err), d, h->pix, h->n_pix,
+                               h->images, h->opt.n_levels, h->opt.precision, h->ev[2], h->ev[3]);
+  if (st != BB_OK) return st;
   h->timed = true;
   h->count += 1;
   return BB_OK;
@@ -373,6 +383,23 @@ bb_status bb_synth_collect_eig(bb_synth h, int32_t slot, int32_t n_ant, int32_t 
   return run_single(h, dsc);
 }
 
+// Host intervals (n_levels x 2, column-major [min, max]) into the kernels' form.
+// Intervals may touch (k-means bounds are shared); a positive-length overlap
+// is rejected.  A value on a shared bound goes to the first such level.
+static bb_status parse_intervals(bb_context ctx, const double* intervals, int nl, bb::Intervals& iv) {
+  for (int l = 0; l < nl; ++l) {
+    iv.lo[l] = intervals[l];
+    iv.hi[l] = intervals[l + nl];
+    if (std::isnan(iv.lo[l]) || std::isnan(iv.hi[l]) || iv.lo[l] > iv.hi[l])
+      return fail(ctx, BB_ERR_INVALID_ARG, "interval %d is not [min <= max]", l);
+  }
+  for (int a = 0; a < nl; ++a)
+    for (int b = a + 1; b < nl; ++b)
+      if (std::max(iv.lo[a], iv.lo[b]) < std::min(iv.hi[a], iv.hi[b]))
+        return fail(ctx, BB_ERR_INVALID_ARG, "intervals %d and %d overlap", a, b);
+  return BB_OK;
+}
+
 // FP64 pre-step shared by bb_synth_collect and bb_synth_prestep: Gram,
 // generalized eigensolve, selection; leaves weights / level ids / column map
 // in the workspace.  Waits for the eigensolver status.
@@ -392,18 +419,8 @@ static bb_status run_prestep(bb_synth h, int32_t n_ant, double wavelength_m, con
   if (!ant_xyz || !vis || !intervals) return fail(ctx, BB_ERR_INVALID_ARG, "null pointer");
   const int nl = h->opt.n_levels;
   bb::Intervals iv{};
-  for (int l = 0; l < nl; ++l) {
-    iv.lo[l] = intervals[l];
-    iv.hi[l] = intervals[l + nl];
-    if (std::isnan(iv.lo[l]) || std::isnan(iv.hi[l]) || iv.lo[l] > iv.hi[l])
-      return fail(ctx, BB_ERR_INVALID_ARG, "interval %d is not [min <= max]", l);
-  }
-  // Intervals may touch (k-means bounds are shared); a positive-length overlap
-  // is rejected.  A value on a shared bound goes to the first such level.
-  for (int a = 0; a < nl; ++a)
-    for (int b = a + 1; b < nl; ++b)
-      if (std::max(iv.lo[a], iv.lo[b]) < std::min(iv.hi[a], iv.hi[b]))
-        return fail(ctx, BB_ERR_INVALID_ARG, "intervals %d and %d overlap", a, b);
+  bb_status ist = parse_intervals(ctx, intervals, nl, iv);
+  if (ist != BB_OK) return ist;
   BB_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   const Layout& L = h->lay;
@@ -576,6 +593,151 @@ bb_status bb_synth_prestep(bb_synth h, int32_t n_ant, double wavelength_m, const
                                     d_out, level_out, ctx->stream));
   BB_HIP(ctx, hipEventRecord(h->ev[2], ctx->stream));
   BB_HIP(ctx, hipEventRecord(h->ev[3], ctx->stream));
+  h->timed = true;
+  return BB_OK;
+}
+
+// ---- batched pre-step ---------------------------------------------------------
+namespace {
+
+struct PrestepBatchLayout {  // byte offsets into the caller's workspace
+  size_t inv_wl, A, G, evals, E, info, herm, dsel, lsel, wcol, solver, solver_bytes, total;
+};
+
+size_t solver_query_batched(bb_context ctx, int n, int n_inst) {
+  size_t sz = 0;
+  if (rocblas_start_device_memory_size_query(ctx->rb) != rocblas_status_success) return 0;
+  rocsolver_zhegvd_strided_batched(ctx->rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, n, nullptr,
+                                   n, (rocblas_stride)n * n, nullptr, n, (rocblas_stride)n * n, nullptr, n, nullptr,
+                                   n, nullptr, n_inst);
+  if (rocblas_stop_device_memory_size_query(ctx->rb, &sz) != rocblas_status_success) return 0;
+  return sz;
+}
+
+PrestepBatchLayout prestep_batch_layout(int n_inst, int L, int K, size_t solver_bytes) {
+  PrestepBatchLayout b{};
+  const size_t n = (size_t)n_inst, Lm = (size_t)L;
+  size_t p = 0;
+  b.inv_wl = p;
+  p += align_up(8 * n);
+  b.A = p;
+  p += align_up(16 * Lm * Lm * n);
+  b.G = p;
+  p += align_up(16 * Lm * Lm * n);
+  b.evals = p;
+  p += align_up(8 * Lm * n);
+  b.E = p;
+  p += align_up(8 * Lm * n);
+  b.info = p;
+  p += align_up(4 * n);
+  b.herm = p;
+  p += align_up(16 * n);
+  b.dsel = p;
+  p += align_up(4 * (size_t)K * n);
+  b.lsel = p;
+  p += align_up(4 * (size_t)K * n);
+  b.wcol = p;
+  p += align_up(4 * (size_t)K * n);
+  b.solver = p;
+  b.solver_bytes = solver_bytes;
+  p += align_up(solver_bytes);
+  b.total = p;
+  return b;
+}
+
+bb_status check_prestep_batch(bb_synth h, int32_t n_inst, int32_t n_ant, int32_t n_eig) {
+  bb_context ctx = h->ctx;
+  if (n_inst < 1) return fail(ctx, BB_ERR_INVALID_ARG, "n_inst must be >= 1");
+  if (n_ant < 1) return fail(ctx, BB_ERR_INVALID_ARG, "n_ant must be >= 1");
+  if (n_ant > h->opt.n_ant_max) return fail(ctx, BB_ERR_SHAPE, "n_ant %d > n_ant_max %d", n_ant, h->opt.n_ant_max);
+  if (n_eig < 1 || n_eig > n_ant) return fail(ctx, BB_ERR_INVALID_ARG, "n_eig must be in [1, n_ant]");
+  if (n_eig > h->opt.k_max) return fail(ctx, BB_ERR_SHAPE, "n_eig %d > k_max %d", n_eig, h->opt.k_max);
+  return BB_OK;
+}
+
+}  // namespace
+
+bb_status bb_prestep_batched_workspace_size(bb_synth h, int32_t n_inst, int32_t n_ant, int32_t n_eig,
+                                            size_t* bytes) {
+  if (!h || !bytes) return BB_ERR_INVALID_ARG;
+  bb_status st = check_prestep_batch(h, n_inst, n_ant, n_eig);
+  if (st != BB_OK) return st;
+  if (hipSetDevice(h->ctx->device) != hipSuccess) return BB_ERR_DEVICE;
+  *bytes = prestep_batch_layout(n_inst, n_ant, n_eig, solver_query_batched(h->ctx, n_ant, n_inst)).total;
+  return BB_OK;
+}
+
+bb_status bb_synth_prestep_batched(bb_synth h, int32_t n_inst, int32_t n_ant, int32_t n_eig,
+                                   const double* wavelengths_m, const double* ant_xyz_packed, const double* vis_packed,
+                                   const double* intervals, void* W_out, double* lam_out, float* d_out,
+                                   int32_t* level_out, void* workspace, size_t ws_bytes) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  bb_status st = check_prestep_batch(h, n_inst, n_ant, n_eig);
+  if (st != BB_OK) return st;
+  if (!wavelengths_m || !intervals) return fail(ctx, BB_ERR_INVALID_ARG, "null host pointer");
+  if (!ant_xyz_packed || !vis_packed || !W_out || !lam_out || !d_out || !level_out || !workspace)
+    return fail(ctx, BB_ERR_INVALID_ARG, "null device pointer");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return fail(ctx, BB_ERR_INVALID_ARG, "workspace must be %zu-byte aligned", kAlign);
+  std::vector<double> inv_wl(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    if (!finite_pos(wavelengths_m[i]))
+      return fail(ctx, BB_ERR_INVALID_ARG, "instance %d: wavelength must be finite and > 0", i);
+    inv_wl[i] = 1.0 / wavelengths_m[i];
+  }
+  const int nl = h->opt.n_levels;
+  bb::Intervals iv{};
+  st = parse_intervals(ctx, intervals, nl, iv);
+  if (st != BB_OK) return st;
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  const PrestepBatchLayout B = prestep_batch_layout(n_inst, n_ant, n_eig, solver_query_batched(ctx, n_ant, n_inst));
+  if (ws_bytes < B.total) return fail(ctx, BB_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, B.total);
+  char* ws = static_cast<char*>(workspace);
+  hipStream_t s = ctx->stream;
+  BB_HIP(ctx, hipEventRecord(h->ev[0], s));
+  // pageable source: the copy is staged before the call returns
+  BB_HIP(ctx, hipMemcpyAsync(ws + B.inv_wl, inv_wl.data(), sizeof(double) * n_inst, hipMemcpyHostToDevice, s));
+  double* A = reinterpret_cast<double*>(ws + B.A);
+  double* G = reinterpret_cast<double*>(ws + B.G);
+  double* herm = reinterpret_cast<double*>(ws + B.herm);
+  BB_HIP(ctx, bb::launch_prestep_inputs_batched(ant_xyz_packed, (int64_t)n_inst * n_ant, n_ant,
+                                                reinterpret_cast<const double*>(ws + B.inv_wl), n_inst,
+                                                h->opt.gram == BB_GRAM_IDENTITY, vis_packed, A, G, herm, s));
+  rocblas_set_stream(ctx->rb, s);
+  if (B.solver_bytes > 0 && rocblas_set_workspace(ctx->rb, ws + B.solver, B.solver_bytes) != rocblas_status_success)
+    return fail(ctx, BB_ERR_DEVICE, "rocblas_set_workspace failed");
+  using cplx = rocblas_double_complex;
+  const rocblas_stride mstride = (rocblas_stride)n_ant * n_ant;
+  rocblas_status rs = rocsolver_zhegvd_strided_batched(
+      ctx->rb, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_lower, n_ant, reinterpret_cast<cplx*>(A), n_ant,
+      mstride, reinterpret_cast<cplx*>(G), n_ant, mstride, reinterpret_cast<double*>(ws + B.evals), n_ant,
+      reinterpret_cast<double*>(ws + B.E), n_ant, reinterpret_cast<rocblas_int*>(ws + B.info), n_inst);
+  if (B.solver_bytes > 0) rocblas_set_workspace(ctx->rb, nullptr, 0);
+  if (rs == rocblas_status_memory_error) return fail(ctx, BB_ERR_WORKSPACE, "rocSOLVER workspace too small");
+  if (rs != rocblas_status_success) return fail(ctx, BB_ERR_DEVICE, "rocsolver_zhegvd_strided_batched status %d", (int)rs);
+  BB_HIP(ctx, hipEventRecord(h->ev[1], s));
+  // one wait per call: every instance's solver status and Hermiticity sums
+  std::vector<rocblas_int> info(n_inst);
+  std::vector<double> hs(2 * (size_t)n_inst);
+  BB_HIP(ctx, hipMemcpyAsync(info.data(), ws + B.info, sizeof(rocblas_int) * n_inst, hipMemcpyDeviceToHost, s));
+  BB_HIP(ctx, hipMemcpyAsync(hs.data(), herm, sizeof(double) * 2 * n_inst, hipMemcpyDeviceToHost, s));
+  BB_HIP(ctx, hipStreamSynchronize(s));
+  for (int i = 0; i < n_inst; ++i) {
+    if (!(hs[2 * i] <= 1e-24 * hs[2 * i + 1]))
+      return fail(ctx, BB_ERR_INVALID_ARG, "instance %d: visibility matrix is not Hermitian (||V - V^H|| / ||V|| = %.3g)",
+                  i, std::sqrt(hs[2 * i] / hs[2 * i + 1]));
+    if (info[i] > n_ant)
+      return fail(ctx, BB_ERR_NOT_POSDEF, "instance %d: Gram matrix not positive definite (leading minor %d)", i,
+                  info[i] - n_ant);
+    if (info[i] != 0) return fail(ctx, BB_ERR_EIGEN, "instance %d: eigensolver did not converge (info %d)", i, info[i]);
+  }
+  BB_HIP(ctx, bb::launch_select_export_batched(A, reinterpret_cast<double*>(ws + B.evals), n_ant, n_eig, n_inst, iv,
+                                               nl, h->opt.filter, reinterpret_cast<float*>(ws + B.dsel),
+                                               reinterpret_cast<int*>(ws + B.lsel), reinterpret_cast<int*>(ws + B.wcol),
+                                               static_cast<float*>(W_out), lam_out, d_out, level_out, s));
+  BB_HIP(ctx, hipEventRecord(h->ev[2], s));
+  BB_HIP(ctx, hipEventRecord(h->ev[3], s));
   h->timed = true;
   return BB_OK;
 }

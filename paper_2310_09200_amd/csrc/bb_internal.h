@@ -96,6 +96,18 @@ struct Intervals {
 };
 hipError_t launch_select(const double* evals, int L, int K, Intervals iv, int n_levels, int filter,
                          float* d_out, int* lev_out, int* wcol_out, hipStream_t s);
+// Batched pre-step of n_inst instances with L antennas each: Gram matrices
+// (antennas of instance i at rows i L of a column-major array with leading
+// dimension ant_ld; 1/wavelength inv_wl[i], device), copies of the
+// visibilities into A, Hermiticity sums into herm[2 i, 2 i + 1]; then the
+// selection and export of each instance's K kept eigenpairs.  Matrices are
+// packed one after the other (2 L^2 doubles each).
+hipError_t launch_prestep_inputs_batched(const double* ant, int64_t ant_ld, int L, const double* inv_wl, int n_inst,
+                                         bool identity, const double* vis, double* A, double* G, double* herm,
+                                         hipStream_t s);
+hipError_t launch_select_export_batched(const double* A, const double* evals, int L, int K, int n_inst, Intervals iv,
+                                        int n_levels, int filter, float* dsel, int* lsel, int* wcol, float* W_out,
+                                        double* lam_out, float* d_out, int* lev_out, hipStream_t s);
 hipError_t launch_export_eig(const double* A_c128, const double* evals, int L, int K, const int* wcol,
                              const float* dsel, const int* lsel, float* W_out_c64, double* lam_out, float* d_out,
                              int* lev_out, hipStream_t s);

@@ -175,6 +175,39 @@ class StandardSynthesis:
         self._keep = [xc, Vc]
         return Wt.transpose(0, 1), lam, d, lev
 
+    def prestep_batched(self, xs, wavelengths, Vs, n_eig, intervals):
+        """FP64 pre-step of many instances with one antenna count (one batched eigensolve, one wait).
+
+        ``xs`` (n_inst, L, 3) f64, ``wavelengths`` (n_inst,), ``Vs`` (n_inst, L, L) complex128.
+        Returns device tensors (W (n_inst, L, K) complex64, lam (n_inst, K) f64, d (n_inst, K) f32,
+        level_of (n_inst, K) i32); their storage is the packed layout ``collect_eig_batched`` takes
+        (instance i's W column-major at element i L K).
+        """
+        dev = self.ctx.device
+        xs = torch.as_tensor(xs)
+        n_inst, L = int(xs.shape[0]), int(xs.shape[1])
+        K = int(n_eig)
+        x_cm = xs.to(device=dev, dtype=torch.float64).reshape(n_inst * L, 3).transpose(0, 1).contiguous()
+        V_cm = torch.as_tensor(Vs).to(device=dev, dtype=torch.complex128).transpose(1, 2).contiguous()
+        wl = np.ascontiguousarray(np.asarray(wavelengths, np.float64).reshape(n_inst))
+        iv = np.ascontiguousarray(np.asarray(intervals, np.float64).reshape(self.n_levels, 2).T).ravel()
+        dp = ctypes.POINTER(ctypes.c_double)
+        Wt = torch.empty((n_inst, K, L), dtype=torch.complex64, device=dev)   # instance i: column-major (L, K)
+        lam = torch.empty((n_inst, K), dtype=torch.float64, device=dev)
+        d = torch.empty((n_inst, K), dtype=torch.float32, device=dev)
+        lev = torch.empty((n_inst, K), dtype=torch.int32, device=dev)
+        sz = ctypes.c_size_t()
+        check(self.lib.bb_prestep_batched_workspace_size(self.handle, n_inst, L, K, ctypes.byref(sz)),
+              self.ctx.handle)
+        ws = torch.empty(int(sz.value) + 256, dtype=torch.uint8, device=dev)
+        ws_ptr = (ws.data_ptr() + 255) // 256 * 256
+        self.ctx.bind_current_stream()
+        check(self.lib.bb_synth_prestep_batched(self.handle, n_inst, L, K, wl.ctypes.data_as(dp), _ptr(x_cm),
+                                                _ptr(V_cm), iv.ctypes.data_as(dp), _ptr(Wt), _ptr(lam), _ptr(d),
+                                                _ptr(lev), ctypes.c_void_p(ws_ptr), sz.value), self.ctx.handle)
+        self._keep = [x_cm, V_cm, ws]
+        return Wt.transpose(1, 2), lam, d, lev
+
     def levels_kmeans(self, lam, negative_level=True):
         """Level intervals by exact k-means of the eigenvalues ``lam`` (n,), on the device.
 

@@ -138,6 +138,62 @@ def test_full_collect_prestep_on_gpu(ctx, precision):
     assert np.all(err[:, 0] <= TOL[precision]), err
 
 
+def test_prestep_batched_equals_single(ctx):
+    """bb_synth_prestep_batched over instances of one antenna count (different
+    array rotations and wavelengths) gives each instance's bb_synth_prestep
+    eigenvalues, weights and level ids; images from its packed outputs match
+    the oracle's full steps.  A non-Hermitian or coincident-antenna instance
+    fails the whole call, naming that instance."""
+    from paper_2310_09200_amd import Batch, BluebildError, StandardSynthesis, _lib
+    say("case batched pre-step vs single pre-step, C1 size")
+    w = configs.c1(n_ant=48, n_side=40)
+    base = w.instance(0)
+    insts = [(sims.earth_rotate(base.x, 0.25 * i), base.wl * (1.0 + 0.07 * i)) for i in range(5)]
+    g = np.random.default_rng(7)
+    Vs = []
+    for x, wl in insts:
+        src = w.pix[g.choice(w.n_pix, 4, replace=False)]
+        Vs.append(sims.add_noise_snr(sims.visibility(x, src, np.exp(g.normal(size=4)), wl), sims.psd_noise(48, g),
+                                     20.0))
+    lam0, A0 = ref.geneig(Vs[0], ref.gram(insts[0][0], insts[0][1]))
+    lam0, _ = ref.select_top(lam0, A0, 40)
+    iv = sims.kmeans1d_intervals(lam0, 3, negative_level=True)
+    s = StandardSynthesis(ctx, w.pix, 4, 1, 48, 48, "fp32_3m")
+    W, lam, d, lev = s.prestep_batched(np.stack([x for x, _ in insts]), [wl for _, wl in insts], np.stack(Vs), 40, iv)
+    want = np.zeros((4, w.n_pix))
+    for i, ((x, wl), V) in enumerate(zip(insts, Vs)):
+        W1, lam1, d1, lev1 = s.prestep(x, wl, V, 40, iv)
+        s.sync()
+        np.testing.assert_allclose(lam[i].cpu().numpy(), lam1.cpu().numpy(), rtol=1e-12, atol=1e-12 * float(
+            lam1.abs().max()))
+        assert torch.equal(lev[i], lev1) and torch.equal(d[i], d1)
+        # eigenvectors agree up to a phase per column
+        ov = torch.abs(torch.sum(torch.conj(W[i]) * W1, dim=0)) / (torch.linalg.norm(W[i], dim=0) *
+                                                                     torch.linalg.norm(W1, dim=0))
+        assert float(ov.min()) > 1 - 1e-5
+        want += ref.collect(V, x, wl, w.pix, 40, iv)[0]
+    s.collect_eig_batched(Batch([(0, insts[i][0], insts[i][1], W[i], d[i], lev[i]) for i in range(5)], ctx.device))
+    s.sync()
+    got = s.images[0].double().cpu().numpy()
+    assert np.all(level_errors(got, want)[:, 0] <= 1e-5)
+    before = s.images.clone()
+    Vb = [V.copy() for V in Vs]
+    Vb[3][0, 5] += 1e-3 * np.abs(Vb[3]).max()
+    with pytest.raises(BluebildError, match="instance 3"):
+        s.prestep_batched(np.stack([x for x, _ in insts]), [wl for _, wl in insts], np.stack(Vb), 40, iv)
+    xs = np.stack([x for x, _ in insts])
+    xs[2, 7] = xs[2, 6]
+    with pytest.raises(BluebildError, match="instance 2") as e:
+        s.prestep_batched(xs, [wl for _, wl in insts], np.stack(Vs), 40, iv)
+    assert e.value.status == _lib.BB_ERR_NOT_POSDEF
+    with pytest.raises(BluebildError) as e:
+        s.prestep_batched(np.stack([x for x, _ in insts]), [wl for _, wl in insts], np.stack(Vs), 49, iv)
+    assert e.value.status == _lib.BB_ERR_INVALID_ARG   # n_eig > n_ant
+    s.sync()
+    assert torch.equal(s.images, before)
+    s.close()
+
+
 def test_full_collect_truncated(ctx):
     """n_eig < L keeps the largest eigenvalues (signed), here with the standardized filter."""
     from paper_2310_09200_amd import StandardSynthesis

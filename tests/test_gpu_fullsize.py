@@ -181,3 +181,44 @@ def test_geocentric_translation_leaves_images_unchanged(ctx, precision):
     for img in imgs:
         e = level_errors(img[:, sel], want)
         assert np.all(e[:, 0] <= TOL[precision]), e
+
+
+def test_c2_batched_prestep_then_batched_synthesis(ctx):
+    """Algorithm 1 over several epochs with the pre-step batched: one
+    strided-batched FP64 eigensolve for all epochs (L = 512), then one batched
+    synthesis launch over its packed outputs.  Eigenvalues and level ids
+    against the oracle's per epoch; images against the oracle's full steps
+    summed over the epochs, on sampled pixels of the 1024^2 grid."""
+    from paper_2310_09200_amd import Batch, StandardSynthesis
+    w = configs.c2(n_steps=100)
+    epochs = [3, 41, 77, 98]
+    say(f"case C2 batched pre-step, epochs {epochs}")
+    sel = sims.sample_pixels(w.n_side, w.source_pixels(), 32)
+    insts = [w.instance(e) for e in epochs]
+    lam0, A0 = ref.geneig(insts[0].V, ref.gram(insts[0].x, insts[0].wl))
+    lam0, _ = ref.select_top(lam0, A0, 512)
+    iv = sims.kmeans1d_intervals(lam0, 8, negative_level=True)
+    want = np.zeros((9, sel.size))
+    lam_o = []
+    for inst in insts:
+        img, lam, _, _ = ref.collect(inst.V, inst.x, inst.wl, w.pix[sel], 512, iv)
+        want += img
+        lam_o.append(lam)
+    s = StandardSynthesis(ctx, w.pix, 9, 1, 512, 512, "fp32_3m")
+    W, lam_g, d, lev = s.prestep_batched(np.stack([i.x for i in insts]), [i.wl for i in insts],
+                                         np.stack([i.V for i in insts]), 512, iv)
+    s.sync()
+    t = s.timings()
+    say(f"batched pre-step of {len(epochs)} epochs: {t[0] + t[1]:.1f} ms")
+    lam_g = lam_g.cpu().numpy()
+    for e, lo in enumerate(lam_o):
+        assert np.max(np.abs(lam_g[e] - lo)) <= 1e-10 * np.max(np.abs(lo)), e
+        assert np.array_equal(lev[e].cpu().numpy(), sims.levels_from_intervals(lo, iv)), e
+    items = [(0, insts[e].x, insts[e].wl, W[e], d[e], lev[e]) for e in range(len(epochs))]
+    s.collect_eig_batched(Batch(items, ctx.device))
+    s.sync()
+    got = s.images[0][:, torch.as_tensor(sel, device=ctx.device)].double().cpu().numpy()
+    s.close()
+    err = level_errors(got, want)
+    say(f"C2 batched pre-step + synthesis per-level max err {err[:, 0]}")
+    assert np.all(err[:, 0] <= 1e-5), err

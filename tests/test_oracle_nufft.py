@@ -32,6 +32,31 @@ def test_nufft3_within_tolerance_of_exact_sum(eps):
     assert np.max(np.abs(got - want)) <= eps * np.sum(np.abs(c))
 
 
+@pytest.mark.parametrize("eps", [1e-3, 1e-5])
+def test_window_end_on_exact_ties_is_immaterial(eps):
+    """Targets at the field's edges land exactly half a support from a type-2
+    grid point (eta = +-M/4 with an even w): either end of the kernel window
+    may be kept there; the two choices differ, and both stay within the
+    tolerance of the exact sum (the bound the method states, Section 3.4)."""
+    c, x, _ = _problem(8, n_src=300)
+    g = np.random.default_rng(9)
+    D, S = np.array([0.25, -0.125, 0.875]), np.array([0.125, 0.0625, 0.0078125])
+    s = D + S * g.uniform(-1, 1, (60, 3))
+    corners = np.array([[a, b, e] for a in (-1, 1) for b in (-1, 1) for e in (-1, 1)], float)
+    s = np.concatenate([s, D + S * corners])
+    P = nf.plan_params(eps, np.max(np.abs(x), axis=0), s)
+    assert P["w"] % 2 == 0
+    eta = (s - P["D"]) * (P["h"] * P["M"])
+    assert np.any(eta - 0.5 * P["w"] == np.round(eta - 0.5 * P["w"]))   # exact ties are present
+    lo = nf.nufft3(c, x, s, eps, tie="low")[:, 0]
+    hi = nf.nufft3(c, x, s, eps, tie="high")[:, 0]
+    want = nf.nudft3(c, x, s)
+    bound = eps * np.sum(np.abs(c))
+    assert np.max(np.abs(lo - hi)) > 0.0
+    assert np.max(np.abs(lo - want)) <= bound
+    assert np.max(np.abs(hi - want)) <= bound
+
+
 def test_nudft3_is_the_sum():
     c, x, s = _problem(2, 7, 5)
     brute = np.array([sum(c[j] * np.exp(2j * np.pi * np.dot(s[k], x[j])) for j in range(7)) for k in range(5)])
