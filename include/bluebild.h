@@ -269,6 +269,34 @@ bb_status bb_synth_collect_eig(bb_synth h, int32_t slot, int32_t n_ant, int32_t 
                                const double* ant_xyz, const void* W, const float* d,
                                const int32_t* level_of);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): the hot path
+ * of bb_synth_collect_eig without a synthesis handle or a workspace.  The
+ * instance's metadata and staged operands go to a fixed scratch array inside
+ * the library, BB_NOALLOC_SCRATCH_BYTES per device, which each device holds
+ * from the first context created on it until the process ends.  The call
+ * itself makes no hipMalloc, hipFree or allocating library call.
+ *  precision  bb_precision of the contraction
+ *  n_levels   1..16, images per call
+ *  n_pix, pix_xyz  as bb_synth_create (device, n_pix x 3 float64 column-major)
+ *  images     device, float32 [n_levels][n_pix], accumulated into
+ *  n_ant, n_eig, wavelength_m, ant_xyz, W, d, level_of  as bb_synth_collect_eig
+ * The images equal those of bb_synth_collect_eig on a handle of the same
+ * precision and level count (same kernels).  Returns BB_ERR_WORKSPACE, having
+ * enqueued nothing, when the instance's staging (16 round_up(n_eig, 32)
+ * round_up(n_ant, 32) bytes plus about 1 KB) exceeds the scratch: for
+ * example n_ant = n_eig = 512 fits, n_ant = n_eig = 1024 does not.  Level
+ * ids outside [-1, n_levels) are treated as -1 without a report.
+ * Every call on one device shares that device's scratch and leaves its
+ * contents behind: calls ordered on one stream are safe; calls that can run
+ * at the same time on one device (several streams or host threads) race and
+ * give wrong images. */
+#define BB_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+bb_status bb_synth_collect_eig_noalloc(bb_context ctx, int32_t precision, int32_t n_levels, int64_t n_pix,
+                                       const double* pix_xyz, float* images, int32_t n_ant, int32_t n_eig,
+                                       double wavelength_m, const double* ant_xyz, const void* W, const float* d,
+                                       const int32_t* level_of);
+
 /* Many uneven instances in one launch (not in the paper, which takes one
  * instance per call).  inst is a host array of n_inst descriptors; the packed
  * device arrays hold every instance's data at the descriptor offsets:

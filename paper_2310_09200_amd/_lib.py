@@ -61,6 +61,8 @@ PROTOS = {
                                    c_void_p, c_void_p, c_void_p, c_void_p]),
     "bb_synth_collect_eig": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_double, c_void_p, c_void_p,
                                        c_void_p, c_void_p]),
+    "bb_synth_collect_eig_noalloc": (c_int32, [c_void_p, c_int32, c_int32, c_int64, c_void_p, c_void_p, c_int32,
+                                               c_int32, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
     "bb_batched_workspace_size": (c_int32, [c_void_p, c_int32, POINTER(bb_instance), POINTER(c_size_t)]),
     "bb_synth_collect_eig_batched": (c_int32, [c_void_p, c_int32, POINTER(bb_instance), c_int64, c_int64, c_int64,
                                                c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -236,6 +237,30 @@ bb_status run_single(bb_synth h, const InstDesc& d) {
   return BB_OK;
 }
 
+// Fixed scratch of the no-allocation entry point: metadata, error word, staging.
+static_assert(BB_NOALLOC_SCRATCH_BYTES == bb::kNoallocScratchBytes, "header and library agree on the scratch size");
+constexpr size_t kNoallocMeta = 0;
+constexpr size_t kNoallocErr = (sizeof(SingleMeta) + kAlign - 1) / kAlign * kAlign;
+constexpr size_t kNoallocStage = kNoallocErr + kAlign;
+
+// The scratch address of `device`, looked up once per device with that device
+// current (each device holds its own copy of the array).
+bb_status noalloc_lookup(bb_context ctx, int device, void** out) {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  if (device < 0 || device >= 64) return fail(ctx, BB_ERR_DEVICE, "device %d beyond the scratch table", device);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    hipError_t e = bb::noalloc_scratch_address(&p);
+    if (e != hipSuccess || !p)
+      return fail(ctx, BB_ERR_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return BB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -269,6 +294,12 @@ bb_status bb_context_create(int device, void* hip_stream, bb_context* out) {
     return BB_ERR_DEVICE;
   }
   rocblas_set_stream(c->rb, c->stream);
+  bb_status st = noalloc_lookup(c, device, &c->noalloc_scratch);
+  if (st != BB_OK) {
+    rocblas_destroy_handle(c->rb);
+    delete c;
+    return st;
+  }
   *out = c;
   return BB_OK;
 }
@@ -381,6 +412,46 @@ bb_status bb_synth_collect_eig(bb_synth h, int32_t slot, int32_t n_ant, int32_t 
   dsc.d = d;
   dsc.lev_in = level_of;
   return run_single(h, dsc);
+}
+
+bb_status bb_synth_collect_eig_noalloc(bb_context ctx, int32_t precision, int32_t n_levels, int64_t n_pix,
+                                       const double* pix_xyz, float* images, int32_t n_ant, int32_t n_eig,
+                                       double wavelength_m, const double* ant_xyz, const void* W, const float* d,
+                                       const int32_t* level_of) {
+  if (!ctx) return BB_ERR_INVALID_ARG;
+  if (precision < BB_PREC_FP32 || precision > BB_PREC_BF16X3_3M)
+    return fail(ctx, BB_ERR_INVALID_ARG, "unknown precision %d", precision);
+  if (n_levels < 1 || n_levels > bb::kMaxLevels)
+    return fail(ctx, BB_ERR_INVALID_ARG, "n_levels must be in [1, %d]", bb::kMaxLevels);
+  if (n_pix < 1) return fail(ctx, BB_ERR_INVALID_ARG, "n_pix must be >= 1");
+  if (n_ant < 1 || n_ant > bb::kMaxAnt) return fail(ctx, BB_ERR_SHAPE, "n_ant must be in [1, %d]", bb::kMaxAnt);
+  if (n_eig < 1 || n_eig > bb::kMaxEig) return fail(ctx, BB_ERR_SHAPE, "n_eig must be in [1, %d]", bb::kMaxEig);
+  if (!finite_pos(wavelength_m)) return fail(ctx, BB_ERR_INVALID_ARG, "wavelength must be finite and > 0");
+  if (!pix_xyz || !images || !ant_xyz || !W || !d || !level_of)
+    return fail(ctx, BB_ERR_INVALID_ARG, "null device pointer");
+  if (!ctx->noalloc_scratch) return fail(ctx, BB_ERR_STATE, "context has no scratch address");
+  const int L_pad = bb::round_up(n_ant, bb::kAntChunk), K_alloc = bb::round_up(n_eig, 32);
+  const size_t need = kNoallocStage + staging_bytes(L_pad, K_alloc);
+  if (need > bb::kNoallocScratchBytes)
+    return fail(ctx, BB_ERR_WORKSPACE, "n_ant %d x n_eig %d needs %zu bytes of scratch, more than the fixed %zu",
+                n_ant, n_eig, need, bb::kNoallocScratchBytes);
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  char* base = static_cast<char*>(ctx->noalloc_scratch);
+  int* err = reinterpret_cast<int*>(base + kNoallocErr);
+  // the error word keeps the previous call's bits: clear it (a kernel, not a memset node)
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, ctx->stream, err);
+  BB_HIP(ctx, hipGetLastError());
+  InstDesc dsc = staging_desc(nullptr, base + kNoallocStage, n_ant, n_eig, wavelength_m, 0);
+  dsc.ant = ant_xyz;
+  dsc.ant_ld = n_ant;
+  dsc.W = W;
+  dsc.W_ld = n_ant;
+  dsc.W_c128 = 0;
+  dsc.wcol = nullptr;
+  dsc.d = d;
+  dsc.lev_in = level_of;
+  return launch_single(ctx, reinterpret_cast<SingleMeta*>(base + kNoallocMeta), err, dsc, pix_xyz, n_pix, images,
+                       n_levels, precision, nullptr, nullptr);
 }
 
 // Host intervals (n_levels x 2, column-major [min, max]) into the kernels' form.

@@ -18,6 +18,9 @@ struct bb_context_ {
   rocblas_handle rb = nullptr;
   std::string err;
   int live = 0;
+  // device address of the library's fixed scratch on this device (looked up
+  // when the context is created; used by bb_synth_collect_eig_noalloc)
+  void* noalloc_scratch = nullptr;
 };
 
 namespace bb_host {

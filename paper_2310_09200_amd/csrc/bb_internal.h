@@ -14,6 +14,12 @@ constexpr int kMaxLevels = 16;
 constexpr int kMaxAnt = 1024;
 constexpr int kMaxEig = 1024;
 
+// Bytes of the fixed device scratch used by bb_synth_collect_eig_noalloc
+// (one instance's metadata, error word and staging; noalloc.hip).
+constexpr size_t kNoallocScratchBytes = (size_t)8 << 20;  // BB_NOALLOC_SCRATCH_BYTES
+// Device address of that scratch on the current device (hipGetSymbolAddress).
+hipError_t noalloc_scratch_address(void** out);
+
 // Bits of a handle's device error word (read and cleared by bb_synth_sync).
 constexpr int kErrLevelId = 1;        // a level id outside [-1, n_levels) was treated as -1
 constexpr int kErrKmeansTooFew = 2;   // k-means: fewer positive eigenvalues than positive levels
