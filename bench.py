@@ -165,6 +165,16 @@ def time_modes(args, torch, ctx, w, items, modes, n_levels, sel, steps=None, war
     L = max(int(i.n_ant) for i in batch.inst)
     K = max(int(i.n_eig) for i in batch.inst)
     handles = {m: StandardSynthesis(ctx, w.pix, n_levels, 1, L, K, m) for m in modes}
+    tune = {}
+    if not args.no_autotune:
+        # tile shapes timed on a few of the epochs (each epoch is the same work shape), fastest kept
+        sub = Batch(items[:min(8, len(items))], ctx.device)
+        for m in modes:
+            t0 = time.perf_counter()
+            table = handles[m].autotune_batched(sub, reps=1)
+            tune[m] = {"tiles": handles[m].tiles, "ms_per_launch_by_class_and_tile": table,
+                       "epochs_timed": len(sub.inst), "seconds": time.perf_counter() - t0}
+            log(f"{m}: autotuned tiles {handles[m].tiles} from {table}")
     for _ in range(warmup):
         for m in modes:
             handles[m].collect_eig_batched(batch)
@@ -193,7 +203,7 @@ def time_modes(args, torch, ctx, w, items, modes, n_levels, sel, steps=None, war
         stage = float(np.mean([k[1] for k in kern[m]]))
         synth = float(np.mean([k[2] for k in kern[m]]))
         log(f"{m}: {ms:.1f} ms/step, synthesis kernel {synth:.1f} ms, staging {stage:.2f} ms")
-        out[m] = (ms, synth, stage, batch.products, sampled)
+        out[m] = (ms, synth, stage, batch.products, sampled, tune.get(m))
     return out
 
 
@@ -260,6 +270,12 @@ def measure_c4(args, torch, ctx):
                       inst.level_of))
     batch = Batch(items, ctx.device)
     s = StandardSynthesis(ctx, w.pix, 4, 64, 512, 128, args.precision)
+    tune = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        table = s.autotune_batched(batch, reps=1)
+        tune = {"tiles": s.tiles, "ms_per_launch_by_class_and_tile": table, "seconds": time.perf_counter() - t0}
+        log(f"C4: autotuned tiles {s.tiles} from {table}")
     s.collect_eig_batched(batch)
     torch.cuda.synchronize()
     ms = []
@@ -275,7 +291,7 @@ def measure_c4(args, torch, ctx):
     log(f"C4 batched: {np.mean(ms):.1f} ms/call, synthesis {kern:.1f} ms, {prods / (np.mean(ms) / 1e3):.3e} products/s")
     return {"workload": "2048 uneven instances (64 channels x 32 epochs, L 200..512, K 16..128, 4 levels), "
                         "512x512 pixels, one batched call", "contraction": args.precision,
-            "products": prods, "ms_per_call": float(np.mean(ms)), "synthesis_kernels_ms": kern,
+            "products": prods, "ms_per_call": float(np.mean(ms)), "synthesis_kernels_ms": kern, "autotune": tune,
             "value": prods / (np.mean(ms) / 1e3), "unit": "products/s",
             "algorithmic_fp32_rate_over_peak": ALG_FLOP * prods / (np.mean(ms) / 1e3) / (FP32_PEAK_TFLOPS * 1e12),
             "mfma_fraction_of_own_peak": EXEC_FLOP[args.precision] * prods / (kern / 1e3) / (PEAK[args.precision] * 1e12)}
@@ -413,13 +429,14 @@ def measure_workload(args, torch, ctx, w, items, n_levels, modes, sel, steps, wa
     ref_img, dt, oprods = oracle_leg(items, w.pix[sel], n_levels, workers)
     out = {}
     for m in modes:
-        ms_m, kern_m, stage_m, prods_m, sampled = timing[m]
+        ms_m, kern_m, stage_m, prods_m, sampled, tune_m = timing[m]
         total = prods_m * w.n_pix
         mx, rms = level_errors(sampled, ref_img)
         out[m] = {"value": total / (ms_m / 1e3), "ms_per_step": ms_m, "kernel_ms": kern_m,
                   "algorithmic_fp32_rate_over_peak": ALG_FLOP * total / (kern_m / 1e3) / (FP32_PEAK_TFLOPS * 1e12),
                   "mfma_fraction_of_own_peak": EXEC_FLOP[m] * total / (kern_m / 1e3) / (PEAK[m] * 1e12),
-                  "level_max_rel_error": mx, "level_rms_rel_error": rms, "max_level_error": max(mx)}
+                  "level_max_rel_error": mx, "level_rms_rel_error": rms, "max_level_error": max(mx),
+                  "autotune": tune_m}
         log(f"  {m}: per-level max error vs oracle {max(mx):.2e}, rms {max(rms):.2e}")
     leg = {"seconds": dt, "products": oprods, "value": oprods / dt, "pixels": int(len(sel)),
            "epochs": len(items)}
@@ -534,6 +551,8 @@ def main():
                     help="image-domain partitions per axis of the NUFFT comparison")
     ap.add_argument("--only-nufft", action="store_true",
                     help="print only the NUFFT-vs-standard measurement (for profiling it alone)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tile shapes instead of timing the candidates before the timed steps")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="before timing, copy this many MiB device-to-device once (a kernel of known traffic "
                          "for scaling hardware byte counters)")
@@ -567,7 +586,7 @@ def main():
     sel = sims_sample(w)
 
     timing = time_modes(args, torch, ctx, w, items, modes, n_levels, sel)
-    ms, kern, stage, products, _ = timing[args.precision]
+    ms, kern, stage, products, _, _ = timing[args.precision]
     total_products = products * w.n_pix
     value = total_products / (ms / 1000.0)
 
@@ -650,8 +669,9 @@ def main():
         f"{100 * gen_pairs / (kern / 1000.0) / peak_pairs:.1f} %)")
     modes_out = {}
     for m in modes:
-        ms_m, kern_m, _, _, _ = timing[m]
+        ms_m, kern_m, _, _, _, tune_m = timing[m]
         modes_out[m] = {"value": total_products / (ms_m / 1000.0), "ms_per_step": ms_m, "kernel_ms": kern_m,
+                        "autotune": tune_m,
                         "algorithmic_fp32_rate_over_peak": ALG_FLOP * total_products / (kern_m / 1000.0)
                         / (FP32_PEAK_TFLOPS * 1e12),
                         "mfma_fraction_of_own_peak": EXEC_FLOP[m] * total_products / (kern_m / 1000.0)

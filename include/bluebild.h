@@ -297,6 +297,39 @@ bb_status bb_synth_collect_eig_noalloc(bb_context ctx, int32_t precision, int32_
                                        double wavelength_m, const double* ant_xyz, const void* W, const float* d,
                                        const int32_t* level_of);
 
+/* ---- tile shapes of the synthesis kernel (not in the paper) ----------------
+ * An instance's K class is its kept eigenpair count rounded up to 32: class
+ * 0, 1, 2, 3 for at most 32, 64, 128, or more.  Each precision has a list of
+ * tile shapes (ids 0 .. at most BB_MAX_TILES - 1): eigenpairs per pass x
+ * pixels per tile, with a wave count.  A handle holds one tile id per K class,
+ * initially the measured default; the batched call launches one persistent
+ * kernel per distinct tile among its instances.
+ * bb_tile_info: shape of tile `tile` of `precision` (BB_ERR_INVALID_ARG past the
+ *   end of the list); class_mask bit c is set when K class c may use it (its
+ *   eigenpairs per pass do not exceed the class's largest K).  Any out pointer may be NULL.
+ * bb_synth_get_tiles / bb_synth_set_tiles: the handle's table, BB_K_CLASSES
+ *   ids (host); -1 on set restores a class's default; a tile the class may not
+ *   use is rejected and the table left unchanged.
+ * bb_synth_autotune_batched: times every tile each K class present in the
+ *   batch may use, on that class's instances over the handle's pixels (one
+ *   warm-up, then `reps` launches, 1..100), and keeps the fastest in the
+ *   handle's table.  Arguments as bb_synth_collect_eig_batched, plus
+ *   scratch_images (device, float32 n_slots x n_levels x n_pix, overwritten;
+ *   the handle's images are not touched) and ms_out (host, BB_K_CLASSES x
+ *   BB_MAX_TILES doubles, row per class: mean milliseconds per launch, -1 where
+ *   not timed).  Waits for the device. */
+#define BB_K_CLASSES 4
+#define BB_MAX_TILES 8
+bb_status bb_tile_info(int32_t precision, int32_t tile, int32_t* eig_per_pass, int32_t* pix_per_tile, int32_t* waves,
+                       int32_t* class_mask);
+bb_status bb_synth_get_tiles(bb_synth h, int32_t* tiles);
+bb_status bb_synth_set_tiles(bb_synth h, const int32_t* tiles);
+bb_status bb_synth_autotune_batched(bb_synth h, int32_t n_inst, const bb_instance* inst, int64_t n_ant_rows,
+                                    int64_t n_w_elems, int64_t n_eig_elems, const double* ant_xyz_packed,
+                                    const void* W_packed, const float* d_packed, const int32_t* level_packed,
+                                    void* workspace, size_t ws_bytes, float* scratch_images, int32_t reps,
+                                    double* ms_out);
+
 /* Many uneven instances in one launch (not in the paper, which takes one
  * instance per call).  inst is a host array of n_inst descriptors; the packed
  * device arrays hold every instance's data at the descriptor offsets:

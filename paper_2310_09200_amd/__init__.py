@@ -11,7 +11,7 @@ from ._lib import BluebildError, load  # noqa: F401
 
 def __getattr__(name):
     # torch-dependent front end, imported lazily
-    if name in ("Context", "StandardSynthesis", "Batch", "NufftSynthesis", "phase_probe"):
+    if name in ("Context", "StandardSynthesis", "Batch", "NufftSynthesis", "phase_probe", "tile_shapes"):
         from . import synthesis
         return getattr(synthesis, name)
     if name in ("bluebild_image",):

@@ -23,6 +23,7 @@ BB_OK, BB_ERR_INVALID_ARG, BB_ERR_SHAPE, BB_ERR_NOT_POSDEF, BB_ERR_EIGEN, BB_ERR
 BB_PREC_FP32, BB_PREC_BF16X3, BB_PREC_FP32_3M, BB_PREC_BF16X3_3M = 0, 1, 2, 3
 BB_FILTER_LSQ, BB_FILTER_STD = 0, 1
 BB_GRAM_SINC, BB_GRAM_IDENTITY = 0, 1
+BB_K_CLASSES, BB_MAX_TILES = 4, 8
 
 
 class bb_options(ctypes.Structure):
@@ -63,6 +64,13 @@ PROTOS = {
                                        c_void_p, c_void_p]),
     "bb_synth_collect_eig_noalloc": (c_int32, [c_void_p, c_int32, c_int32, c_int64, c_void_p, c_void_p, c_int32,
                                                c_int32, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "bb_tile_info": (c_int32, [c_int32, c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
+                               POINTER(c_int32)]),
+    "bb_synth_get_tiles": (c_int32, [c_void_p, POINTER(c_int32)]),
+    "bb_synth_set_tiles": (c_int32, [c_void_p, POINTER(c_int32)]),
+    "bb_synth_autotune_batched": (c_int32, [c_void_p, c_int32, POINTER(bb_instance), c_int64, c_int64, c_int64,
+                                            c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p,
+                                            c_int32, POINTER(c_double)]),
     "bb_batched_workspace_size": (c_int32, [c_void_p, c_int32, POINTER(bb_instance), POINTER(c_size_t)]),
     "bb_synth_collect_eig_batched": (c_int32, [c_void_p, c_int32, POINTER(bb_instance), c_int64, c_int64, c_int64,
                                                c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),

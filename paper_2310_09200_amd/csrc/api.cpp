@@ -122,6 +122,7 @@ struct bb_synth_ {
   int64_t count = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool timed = false;
+  int tiles[bb::kKClasses] = {-1, -1, -1, -1};  // tile id per K class (set to the defaults at creation)
 };
 
 namespace {
@@ -200,7 +201,7 @@ InstDesc staging_desc(bb_synth h, char* base, int L, int K, double wl, int slot)
 // `meta` and the device error word at `err`; ev_staged / ev_done (may be
 // null) are recorded after staging and after the synthesis.
 bb_status launch_single(bb_context ctx, SingleMeta* meta, int* err, const InstDesc& d, const double* pix,
-                        int64_t n_pix, float* images, int n_levels, int precision, hipEvent_t ev_staged,
+                        int64_t n_pix, float* images, int n_levels, int precision, int tile, hipEvent_t ev_staged,
                         hipEvent_t ev_done) {
   hipStream_t s = ctx->stream;
   hipLaunchKernelGGL(write_meta_kernel, dim3(1), dim3(1), 0, s, meta, d, d.slot);
@@ -219,10 +220,12 @@ bb_status launch_single(bb_context ctx, SingleMeta* meta, int* err, const InstDe
   p.img = images;
   p.img_ld = n_pix;
   p.n_levels = n_levels;
-  const int nt = bb::synth_tile_pixels(d.K_alloc, precision);
+  int nt = 0;
+  if (!bb::synth_tile_info(precision, tile, nullptr, &nt, nullptr))
+    return fail(ctx, BB_ERR_INVALID_ARG, "unknown tile %d", tile);
   p.n_tiles = (n_pix + nt - 1) / nt;
   p.n_groups = 1;
-  BB_HIP(ctx, bb::launch_synth(p, d.K_alloc, precision, nullptr, s));
+  BB_HIP(ctx, bb::launch_synth_tile(p, precision, tile, s));
   if (ev_done) BB_HIP(ctx, hipEventRecord(ev_done, s));
   return BB_OK;
 }
@@ -230,7 +233,8 @@ bb_status launch_single(bb_context ctx, SingleMeta* meta, int* err, const InstDe
 // Single-instance calls on a handle: staging in the handle's workspace.
 bb_status run_single(bb_synth h, const InstDesc& d) {
   bb_status st = launch_single(h->ctx, at<SingleMeta>(h, h->lay.meta), at<int>(h, h->lay.err), d, h->pix, h->n_pix,
-                               h->images, h->opt.n_levels, h->opt.precision, h->ev[2], h->ev[3]);
+                               h->images, h->opt.n_levels, h->opt.precision, h->tiles[bb::synth_k_class(d.K_alloc)],
+                               h->ev[2], h->ev[3]);
   if (st != BB_OK) return st;
   h->timed = true;
   h->count += 1;
@@ -239,6 +243,7 @@ bb_status run_single(bb_synth h, const InstDesc& d) {
 
 // Fixed scratch of the no-allocation entry point: metadata, error word, staging.
 static_assert(BB_NOALLOC_SCRATCH_BYTES == bb::kNoallocScratchBytes, "header and library agree on the scratch size");
+static_assert(BB_K_CLASSES == bb::kKClasses, "header and library agree on the K classes");
 constexpr size_t kNoallocMeta = 0;
 constexpr size_t kNoallocErr = (sizeof(SingleMeta) + kAlign - 1) / kAlign * kAlign;
 constexpr size_t kNoallocStage = kNoallocErr + kAlign;
@@ -355,6 +360,7 @@ bb_status bb_synth_create(bb_context ctx, const bb_options* opt, int64_t n_pix, 
   h->ws = static_cast<char*>(workspace);
   h->ws_bytes = ws_bytes;
   h->lay = lay;
+  for (int c = 0; c < bb::kKClasses; ++c) h->tiles[c] = bb::synth_default_tile(opt->precision, c);
   for (auto& e : h->ev)
     if (hipEventCreate(&e) != hipSuccess) {
       delete h;
@@ -451,7 +457,8 @@ bb_status bb_synth_collect_eig_noalloc(bb_context ctx, int32_t precision, int32_
   dsc.d = d;
   dsc.lev_in = level_of;
   return launch_single(ctx, reinterpret_cast<SingleMeta*>(base + kNoallocMeta), err, dsc, pix_xyz, n_pix, images,
-                       n_levels, precision, nullptr, nullptr);
+                       n_levels, precision, bb::synth_default_tile(precision, bb::synth_k_class(dsc.K_alloc)), nullptr,
+                       nullptr);
 }
 
 // Host intervals (n_levels x 2, column-major [min, max]) into the kernels' form.
@@ -858,12 +865,14 @@ bb_status bb_synth_uniform_weighting(bb_synth h, int32_t n_ant, double wavelengt
 // ---- batched ----------------------------------------------------------------
 namespace {
 
-// Instances are grouped by the tile shape their eigenpair count selects (one
-// persistent launch per shape, largest first); inside a shape, by image slot
-// (slots in decreasing cost order).  Launches are stream-ordered, each has one
-// writer per image tile: the result is deterministic.
+// Instances are grouped by the tile shape of their K class (the handle's tile
+// table: one persistent launch per shape, the costliest shape first); inside a
+// shape, by image slot (slots in decreasing cost order).  Launches are
+// stream-ordered, each has one writer per image tile: the result is
+// deterministic.
 struct Bucket {
-  int kc = 0, max_K_alloc = 0, n_groups = 0;
+  int tile = 0, max_K_alloc = 0, n_groups = 0;
+  double cost = 0.0;
   size_t gslot_idx = 0, gbegin_idx = 0;
 };
 
@@ -877,12 +886,15 @@ struct BatchPlan {
 
 // n_w_elems / n_eig_elems: lengths of the packed W (complex elements) and of
 // the packed weights and level ids; negative skips those two checks (the
-// workspace-size query, which sees no arrays).
+// workspace-size query, which sees no arrays).  tiles: tile id per K class;
+// only_class >= 0 puts only that class's instances into the groups (the
+// workspace layout does not depend on it: group arrays are sized for n_inst).
 bb_status plan_batch(bb_synth h, int32_t n_inst, const bb_instance* inst, int64_t n_ant_rows, int64_t n_w_elems,
-                     int64_t n_eig_elems, BatchPlan& bp) {
+                     int64_t n_eig_elems, const int* tiles, int only_class, BatchPlan& bp) {
   bb_context ctx = h->ctx;
   if (n_inst < 1 || !inst) return fail(ctx, BB_ERR_INVALID_ARG, "empty instance table");
-  std::vector<int> kcs;
+  std::vector<Bucket> bks;
+  std::vector<int> tile_of(n_inst);
   for (int i = 0; i < n_inst; ++i) {
     const bb_instance& b = inst[i];
     bb_status st = check_instance_args(h, b.slot, b.n_ant, b.n_eig, b.wavelength_m);
@@ -898,21 +910,26 @@ bb_status plan_batch(bb_synth h, int32_t n_inst, const bb_instance* inst, int64_
     const int L_pad = bb::round_up(b.n_ant, bb::kAntChunk), K_alloc = bb::round_up(b.n_eig, 32);
     bp.max_K_alloc = std::max(bp.max_K_alloc, K_alloc);
     bp.max_L_pad = std::max(bp.max_L_pad, L_pad);
-    const int kc = bb::synth_tile_kc(K_alloc, h->opt.precision);
-    if (std::find(kcs.begin(), kcs.end(), kc) == kcs.end()) kcs.push_back(kc);
+    const int kcl = bb::synth_k_class(K_alloc);
+    tile_of[i] = (only_class >= 0 && kcl != only_class) ? -1 : tiles[kcl];
+    if (tile_of[i] < 0) continue;
+    auto it = std::find_if(bks.begin(), bks.end(), [&](const Bucket& x) { return x.tile == tile_of[i]; });
+    if (it == bks.end()) {
+      bks.push_back(Bucket{});
+      it = bks.end() - 1;
+      it->tile = tile_of[i];
+    }
+    it->max_K_alloc = std::max(it->max_K_alloc, K_alloc);
+    it->cost += (double)L_pad * K_alloc;
   }
-  std::sort(kcs.begin(), kcs.end(), [](int a, int b) { return a > b; });
-  for (int kc : kcs) {
-    Bucket bk;
-    bk.kc = kc;
+  std::stable_sort(bks.begin(), bks.end(), [](const Bucket& a, const Bucket& b) { return a.cost > b.cost; });
+  for (Bucket bk : bks) {
     std::vector<double> cost(h->opt.n_slots, 0.0);
     std::vector<std::vector<int>> by_slot(h->opt.n_slots);
     for (int i = 0; i < n_inst; ++i) {
+      if (tile_of[i] != bk.tile) continue;
       const bb_instance& b = inst[i];
-      const int K_alloc = bb::round_up(b.n_eig, 32);
-      if (bb::synth_tile_kc(K_alloc, h->opt.precision) != kc) continue;
-      bk.max_K_alloc = std::max(bk.max_K_alloc, K_alloc);
-      cost[b.slot] += (double)bb::round_up(b.n_ant, bb::kAntChunk) * K_alloc;
+      cost[b.slot] += (double)bb::round_up(b.n_ant, bb::kAntChunk) * bb::round_up(b.n_eig, 32);
       by_slot[b.slot].push_back(i);
     }
     std::vector<int> slots;
@@ -930,21 +947,89 @@ bb_status plan_batch(bb_synth h, int32_t n_inst, const bb_instance* inst, int64_
     bk.n_groups = (int)slots.size();
     bp.buckets.push_back(bk);
   }
+  // group arrays sized for the worst case (one group per instance, one more
+  // begin entry per bucket), so that the layout depends on n_inst only
   size_t p = 0;
   bp.off_descs = p;
   p += align_up(sizeof(InstDesc) * n_inst);
   bp.off_dyn = p;
   p += align_up(sizeof(InstDyn) * n_inst);
   bp.off_gslot = p;
-  p += align_up(sizeof(int) * bp.group_slot.size());
+  p += align_up(sizeof(int) * n_inst);
   bp.off_gbegin = p;
-  p += align_up(sizeof(int) * bp.group_begin.size());
+  p += align_up(sizeof(int) * ((size_t)n_inst + bb::kKClasses));
   bp.off_ilist = p;
-  p += align_up(sizeof(int) * bp.inst_list.size());
+  p += align_up(sizeof(int) * n_inst);
   bp.off_stage = p;
   for (int i = 0; i < n_inst; ++i)
     p += staging_bytes(bb::round_up(inst[i].n_ant, bb::kAntChunk), bb::round_up(inst[i].n_eig, 32));
   bp.total = p;
+  return BB_OK;
+}
+
+// Descriptors of every instance of a planned batch, their staging regions in `ws`.
+void batch_descs(bb_synth h, const bb_instance* inst, int32_t n_inst, int64_t n_ant_rows, const double* ant,
+                 const void* W, const float* d, const int32_t* lev, char* ws, BatchPlan& bp) {
+  size_t stage = bp.off_stage;
+  bp.descs.resize(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    const bb_instance& b = inst[i];
+    InstDesc dd = staging_desc(h, ws + stage, b.n_ant, b.n_eig, b.wavelength_m, b.slot);
+    stage += staging_bytes(dd.L_pad, dd.K_alloc);
+    dd.ant = ant + b.ant_off;
+    dd.ant_ld = n_ant_rows;
+    dd.W = static_cast<const float*>(W) + 2 * b.w_off;
+    dd.W_ld = b.n_ant;
+    dd.W_c128 = 0;
+    dd.wcol = nullptr;
+    dd.d = d + b.eig_off;
+    dd.lev_in = lev + b.eig_off;
+    bp.descs[i] = dd;
+  }
+}
+
+// Upload the group arrays of a plan and, with `descs`, the instance
+// descriptors.  The kept-eigenpair counts between the two regions (written by
+// the staging kernel) are left alone, so a plan of already staged instances
+// can be swapped in.
+bb_status upload_plan(bb_context ctx, const BatchPlan& bp, char* ws, int32_t n_inst, bool descs) {
+  std::vector<char> meta(bp.off_stage, 0);
+  std::memcpy(meta.data() + bp.off_descs, bp.descs.data(), sizeof(InstDesc) * n_inst);
+  std::memcpy(meta.data() + bp.off_gslot, bp.group_slot.data(), sizeof(int) * bp.group_slot.size());
+  std::memcpy(meta.data() + bp.off_gbegin, bp.group_begin.data(), sizeof(int) * bp.group_begin.size());
+  std::memcpy(meta.data() + bp.off_ilist, bp.inst_list.data(), sizeof(int) * bp.inst_list.size());
+  // pageable source: the copies are staged before the call returns
+  if (descs)
+    BB_HIP(ctx, hipMemcpyAsync(ws + bp.off_descs, meta.data() + bp.off_descs, bp.off_dyn - bp.off_descs,
+                               hipMemcpyHostToDevice, ctx->stream));
+  BB_HIP(ctx, hipMemcpyAsync(ws + bp.off_gslot, meta.data() + bp.off_gslot, bp.off_stage - bp.off_gslot,
+                             hipMemcpyHostToDevice, ctx->stream));
+  return BB_OK;
+}
+
+// One synthesis launch per bucket of a planned, staged batch into `images`.
+bb_status launch_buckets(bb_synth h, const BatchPlan& bp, char* ws, float* images) {
+  bb_context ctx = h->ctx;
+  for (const Bucket& bk : bp.buckets) {
+    bb::FwdParams p{};
+    p.pix = h->pix;
+    p.pix_ld = h->n_pix;
+    p.n_pix = h->n_pix;
+    p.descs = reinterpret_cast<InstDesc*>(ws + bp.off_descs);
+    p.dyn = reinterpret_cast<InstDyn*>(ws + bp.off_dyn);
+    p.group_slot = reinterpret_cast<int*>(ws + bp.off_gslot) + bk.gslot_idx;
+    p.group_begin = reinterpret_cast<int*>(ws + bp.off_gbegin) + bk.gbegin_idx;
+    p.inst_list = reinterpret_cast<int*>(ws + bp.off_ilist);
+    p.img = images;
+    p.img_ld = h->n_pix;
+    p.n_levels = h->opt.n_levels;
+    int nt = 0;
+    if (!bb::synth_tile_info(h->opt.precision, bk.tile, nullptr, &nt, nullptr))
+      return fail(ctx, BB_ERR_INVALID_ARG, "unknown tile %d", bk.tile);
+    p.n_tiles = (h->n_pix + nt - 1) / nt;
+    p.n_groups = bk.n_groups;
+    BB_HIP(ctx, bb::launch_synth_tile(p, h->opt.precision, bk.tile, ctx->stream));
+  }
   return BB_OK;
 }
 
@@ -955,7 +1040,7 @@ bb_status bb_batched_workspace_size(bb_synth h, int32_t n_inst, const bb_instanc
   BatchPlan bp;
   int64_t rows = 0;
   for (int i = 0; inst && i < n_inst; ++i) rows = std::max<int64_t>(rows, inst[i].ant_off + inst[i].n_ant);
-  bb_status st = plan_batch(h, n_inst, inst, rows, -1, -1, bp);
+  bb_status st = plan_batch(h, n_inst, inst, rows, -1, -1, h->tiles, -1, bp);
   if (st != BB_OK) return st;
   *bytes = bp.total;
   return BB_OK;
@@ -973,64 +1058,132 @@ bb_status bb_synth_collect_eig_batched(bb_synth h, int32_t n_inst, const bb_inst
     return fail(ctx, BB_ERR_INVALID_ARG, "workspace must be %zu-byte aligned", kAlign);
   BatchPlan bp;
   if (n_w_elems < 0 || n_eig_elems < 0) return fail(ctx, BB_ERR_INVALID_ARG, "packed array lengths must be >= 0");
-  bb_status st = plan_batch(h, n_inst, inst, n_ant_rows, n_w_elems, n_eig_elems, bp);
+  bb_status st = plan_batch(h, n_inst, inst, n_ant_rows, n_w_elems, n_eig_elems, h->tiles, -1, bp);
   if (st != BB_OK) return st;
   if (ws_bytes < bp.total) return fail(ctx, BB_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, bp.total);
   BB_HIP(ctx, hipSetDevice(ctx->device));
   char* ws = static_cast<char*>(workspace);
-  size_t stage = bp.off_stage;
-  bp.descs.resize(n_inst);
-  for (int i = 0; i < n_inst; ++i) {
-    const bb_instance& b = inst[i];
-    InstDesc d = staging_desc(h, ws + stage, b.n_ant, b.n_eig, b.wavelength_m, b.slot);
-    stage += staging_bytes(d.L_pad, d.K_alloc);
-    d.ant = ant_xyz_packed + b.ant_off;
-    d.ant_ld = n_ant_rows;
-    d.W = static_cast<const float*>(W_packed) + 2 * b.w_off;
-    d.W_ld = b.n_ant;
-    d.W_c128 = 0;
-    d.wcol = nullptr;
-    d.d = d_packed + b.eig_off;
-    d.lev_in = level_packed + b.eig_off;
-    bp.descs[i] = d;
-  }
-  // one host image of the metadata block, uploaded in one copy
-  std::vector<char> meta(bp.off_stage, 0);
-  std::memcpy(meta.data() + bp.off_descs, bp.descs.data(), sizeof(InstDesc) * n_inst);
-  std::memcpy(meta.data() + bp.off_gslot, bp.group_slot.data(), sizeof(int) * bp.group_slot.size());
-  std::memcpy(meta.data() + bp.off_gbegin, bp.group_begin.data(), sizeof(int) * bp.group_begin.size());
-  std::memcpy(meta.data() + bp.off_ilist, bp.inst_list.data(), sizeof(int) * bp.inst_list.size());
+  batch_descs(h, inst, n_inst, n_ant_rows, ant_xyz_packed, W_packed, d_packed, level_packed, ws, bp);
   hipStream_t s = ctx->stream;
   BB_HIP(ctx, hipEventRecord(h->ev[0], s));
   BB_HIP(ctx, hipEventRecord(h->ev[1], s));
-  // pageable source: the copy is staged before the call returns
-  BB_HIP(ctx, hipMemcpyAsync(ws, meta.data(), meta.size(), hipMemcpyHostToDevice, s));
-  InstDesc* d_descs = reinterpret_cast<InstDesc*>(ws + bp.off_descs);
-  InstDyn* d_dyn = reinterpret_cast<InstDyn*>(ws + bp.off_dyn);
-  BB_HIP(ctx, bb::launch_stage(d_descs, d_dyn, n_inst, bp.max_K_alloc, bp.max_L_pad, h->opt.n_levels,
-                               h->opt.precision, at<int>(h, h->lay.err), s));
+  st = upload_plan(ctx, bp, ws, n_inst, true);
+  if (st != BB_OK) return st;
+  BB_HIP(ctx, bb::launch_stage(reinterpret_cast<InstDesc*>(ws + bp.off_descs), reinterpret_cast<InstDyn*>(ws + bp.off_dyn),
+                               n_inst, bp.max_K_alloc, bp.max_L_pad, h->opt.n_levels, h->opt.precision,
+                               at<int>(h, h->lay.err), s));
   BB_HIP(ctx, hipEventRecord(h->ev[2], s));
-  for (const Bucket& bk : bp.buckets) {
-    bb::FwdParams p{};
-    p.pix = h->pix;
-    p.pix_ld = h->n_pix;
-    p.n_pix = h->n_pix;
-    p.descs = d_descs;
-    p.dyn = d_dyn;
-    p.group_slot = reinterpret_cast<int*>(ws + bp.off_gslot) + bk.gslot_idx;
-    p.group_begin = reinterpret_cast<int*>(ws + bp.off_gbegin) + bk.gbegin_idx;
-    p.inst_list = reinterpret_cast<int*>(ws + bp.off_ilist);
-    p.img = h->images;
-    p.img_ld = h->n_pix;
-    p.n_levels = h->opt.n_levels;
-    const int nt = bb::synth_tile_pixels(bk.max_K_alloc, h->opt.precision);
-    p.n_tiles = (h->n_pix + nt - 1) / nt;
-    p.n_groups = bk.n_groups;
-    BB_HIP(ctx, bb::launch_synth(p, bk.max_K_alloc, h->opt.precision, nullptr, s));
-  }
+  st = launch_buckets(h, bp, ws, h->images);
+  if (st != BB_OK) return st;
   BB_HIP(ctx, hipEventRecord(h->ev[3], s));
   h->timed = true;
   h->count += n_inst;
+  return BB_OK;
+}
+
+bb_status bb_tile_info(int32_t precision, int32_t tile, int32_t* eig_per_pass, int32_t* pix_per_tile, int32_t* waves,
+                       int32_t* class_mask) {
+  if (precision < BB_PREC_FP32 || precision > BB_PREC_BF16X3_3M) return BB_ERR_INVALID_ARG;
+  int kc = 0, nt = 0, wv = 0;
+  if (tile < 0 || !bb::synth_tile_info(precision, tile, &kc, &nt, &wv)) return BB_ERR_INVALID_ARG;
+  int mask = 0;
+  for (int c = 0; c < bb::kKClasses; ++c)
+    if (bb::synth_tile_allowed(precision, tile, c)) mask |= 1 << c;
+  if (eig_per_pass) *eig_per_pass = kc;
+  if (pix_per_tile) *pix_per_tile = nt;
+  if (waves) *waves = wv;
+  if (class_mask) *class_mask = mask;
+  return BB_OK;
+}
+
+bb_status bb_synth_get_tiles(bb_synth h, int32_t* tiles) {
+  if (!h || !tiles) return BB_ERR_INVALID_ARG;
+  for (int c = 0; c < bb::kKClasses; ++c) tiles[c] = h->tiles[c];
+  return BB_OK;
+}
+
+bb_status bb_synth_set_tiles(bb_synth h, const int32_t* tiles) {
+  if (!h || !tiles) return BB_ERR_INVALID_ARG;
+  int next[bb::kKClasses];
+  for (int c = 0; c < bb::kKClasses; ++c) {
+    next[c] = tiles[c] < 0 ? bb::synth_default_tile(h->opt.precision, c) : tiles[c];
+    if (!bb::synth_tile_allowed(h->opt.precision, next[c], c))
+      return fail(h->ctx, BB_ERR_INVALID_ARG, "tile %d is not a candidate for K class %d", tiles[c], c);
+  }
+  for (int c = 0; c < bb::kKClasses; ++c) h->tiles[c] = next[c];
+  return BB_OK;
+}
+
+bb_status bb_synth_autotune_batched(bb_synth h, int32_t n_inst, const bb_instance* inst, int64_t n_ant_rows,
+                                    int64_t n_w_elems, int64_t n_eig_elems, const double* ant_xyz_packed,
+                                    const void* W_packed, const float* d_packed, const int32_t* level_packed,
+                                    void* workspace, size_t ws_bytes, float* scratch_images, int32_t reps,
+                                    double* ms_out) {
+  if (!h) return BB_ERR_INVALID_ARG;
+  bb_context ctx = h->ctx;
+  if (!ant_xyz_packed || !W_packed || !d_packed || !level_packed || !workspace || !scratch_images)
+    return fail(ctx, BB_ERR_INVALID_ARG, "null device pointer");
+  if (!ms_out) return fail(ctx, BB_ERR_INVALID_ARG, "ms_out is NULL");
+  if (reps < 1 || reps > 100) return fail(ctx, BB_ERR_INVALID_ARG, "reps must be in [1, 100]");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+    return fail(ctx, BB_ERR_INVALID_ARG, "workspace must be %zu-byte aligned", kAlign);
+  if (n_w_elems < 0 || n_eig_elems < 0) return fail(ctx, BB_ERR_INVALID_ARG, "packed array lengths must be >= 0");
+  BatchPlan full;
+  bb_status st = plan_batch(h, n_inst, inst, n_ant_rows, n_w_elems, n_eig_elems, h->tiles, -1, full);
+  if (st != BB_OK) return st;
+  if (ws_bytes < full.total) return fail(ctx, BB_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, full.total);
+  const int n_tiles = bb::synth_n_tiles(h->opt.precision);
+  if (n_tiles > BB_MAX_TILES) return fail(ctx, BB_ERR_STATE, "more tile candidates than BB_MAX_TILES");
+  for (int i = 0; i < bb::kKClasses * BB_MAX_TILES; ++i) ms_out[i] = -1.0;
+  BB_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  char* ws = static_cast<char*>(workspace);
+  batch_descs(h, inst, n_inst, n_ant_rows, ant_xyz_packed, W_packed, d_packed, level_packed, ws, full);
+  st = upload_plan(ctx, full, ws, n_inst, true);
+  if (st != BB_OK) return st;
+  BB_HIP(ctx, bb::launch_stage(reinterpret_cast<InstDesc*>(ws + full.off_descs),
+                               reinterpret_cast<InstDyn*>(ws + full.off_dyn), n_inst, full.max_K_alloc,
+                               full.max_L_pad, h->opt.n_levels, h->opt.precision, at<int>(h, h->lay.err), s));
+  BB_HIP(ctx, bb::launch_fill_zero(scratch_images, (int64_t)h->opt.n_slots * h->opt.n_levels * h->n_pix, s));
+  bool present[bb::kKClasses] = {false, false, false, false};
+  for (int i = 0; i < n_inst; ++i) present[bb::synth_k_class(bb::round_up(inst[i].n_eig, 32))] = true;
+  int best[bb::kKClasses];
+  for (int c = 0; c < bb::kKClasses; ++c) best[c] = h->tiles[c];
+  for (int c = 0; c < bb::kKClasses; ++c) {
+    if (!present[c]) continue;
+    double best_ms = 0.0;
+    for (int t = 0; t < n_tiles; ++t) {
+      if (!bb::synth_tile_allowed(h->opt.precision, t, c)) continue;
+      int tiles[bb::kKClasses];
+      for (int q = 0; q < bb::kKClasses; ++q) tiles[q] = h->tiles[q];
+      tiles[c] = t;
+      BatchPlan bp;
+      st = plan_batch(h, n_inst, inst, n_ant_rows, n_w_elems, n_eig_elems, tiles, c, bp);
+      if (st != BB_OK) return st;
+      bp.descs = full.descs;
+      st = upload_plan(ctx, bp, ws, n_inst, false);
+      if (st != BB_OK) return st;
+      st = launch_buckets(h, bp, ws, scratch_images);  // warm-up
+      if (st != BB_OK) return st;
+      BB_HIP(ctx, hipEventRecord(h->ev[0], s));
+      for (int r = 0; r < reps; ++r) {
+        st = launch_buckets(h, bp, ws, scratch_images);
+        if (st != BB_OK) return st;
+      }
+      BB_HIP(ctx, hipEventRecord(h->ev[1], s));
+      BB_HIP(ctx, hipEventSynchronize(h->ev[1]));
+      float ms = 0.0f;
+      BB_HIP(ctx, hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+      const double per = ms / reps;
+      ms_out[c * BB_MAX_TILES + t] = per;
+      if (best_ms == 0.0 || per < best_ms) {
+        best_ms = per;
+        best[c] = t;
+      }
+    }
+  }
+  for (int c = 0; c < bb::kKClasses; ++c) h->tiles[c] = best[c];
+  h->timed = false;
   return BB_OK;
 }
 

@@ -78,12 +78,22 @@ struct FwdParams {
 hipError_t launch_stage(const InstDesc* d_descs, InstDyn* d_dyn, int n_inst, int max_K_alloc, int max_L_pad,
                         int n_levels, int precision, int* d_err, hipStream_t s);
 
-// Synthesis: picks a tile configuration from the largest K_alloc of the call.
+// Synthesis tiles.  K class of an instance: 0..3 for kept eigenpairs rounded
+// up to 32 of at most 32, 64, 128, or more.  Each precision has a list of
+// tile shapes (ids 0 .. synth_n_tiles - 1) and a default per class.
+constexpr int kKClasses = 4;
+int synth_k_class(int K_alloc);
+int synth_n_tiles(int precision);
+int synth_default_tile(int precision, int k_class);
+// Eigenpairs per pass, pixels per tile and waves of a tile; false for an unknown id.
+bool synth_tile_info(int precision, int id, int* kc, int* nt, int* waves);
+// Whether a class may use a tile (its eigenpairs per pass do not exceed the class's largest K).
+bool synth_tile_allowed(int precision, int id, int k_class);
+hipError_t launch_synth_tile(const FwdParams& p, int precision, int id, hipStream_t s);
+// The default tile for the largest K_alloc of the call.
 hipError_t launch_synth(const FwdParams& p, int max_K_alloc, int precision, int tile_pixels_out[1],
                         hipStream_t s);
 int synth_tile_pixels(int max_K_alloc, int precision);
-// Eigenpairs per pass of the tile shape picked for this K (identifies the shape).
-int synth_tile_kc(int max_K_alloc, int precision);
 
 // Zero-fill of a float buffer (graph-capture safe, no memset nodes).
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);

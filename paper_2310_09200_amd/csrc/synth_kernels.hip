@@ -795,98 +795,169 @@ static hipError_t launch_cfg(const FwdParams& p, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Tile shape per precision and largest K of the call (register budget: two
-// waves per SIMD, <= 256 VGPRs each).
-template <int PREC>
-struct Shapes;
-template <>
-struct Shapes<0> {  // 4 products: Er/Ei accumulators, 32 regs per output block
-  template <class F> static hipError_t pick(int K, F f) {
-    if (K > 128) return f(TileCfg<1, 4, 8, 1>{});  // (2 x 2 blocks per wave measured slower)
-    if (K > 64) return f(TileCfg<1, 4, 4, 2>{});
-    if (K > 32) return f(TileCfg<1, 2, 2, 4>{});
-    return f(TileCfg<1, 2, 1, 4>{});
-  }
-};
-template <>
-struct Shapes<1> : Shapes<0> {};
-template <>
-struct Shapes<2> {  // 3 products: k1/k2/k3 accumulators, 48 regs per output block
-  template <class F> static hipError_t pick(int K, F f) {
-    if (K > 128) return f(TileCfg<1, 2, 8, 1>{});
-    // 16 waves of one pixel block each: 3 active k-blocks (K <= 96) still
-    // spread evenly over the four SIMDs
-    if (K > 64) return f(TileCfg<1, 1, 4, 4>{});
-    if (K > 32) return f(TileCfg<1, 2, 2, 4>{});
-    return f(TileCfg<1, 1, 1, 8>{});  // one pixel block per wave: two waves per SIMD
-  }
-};
-
 template <int PREC, int MODE, int MB, int NB, int WK, int WN>
 static hipError_t launch_tc(const FwdParams& p, TileCfg<MB, NB, WK, WN>, hipStream_t s) {
   return launch_cfg<MB, NB, WK, WN, PREC, MODE>(p, s);
 }
 
+// ---------------------------------------------------------------------------
+// Tile candidates.  Each precision has a list of tile shapes (kernel
+// instantiations); a launch names one by its index in the list.  Instances
+// fall in K classes by their kept eigenpairs rounded up to 32: at most 32, 64,
+// 128, or more.  Each class has a default shape (the measured best on this
+// GPU) and may use every shape of the list whose eigenpairs per pass do not
+// exceed the class's largest K (so that no wave of a tile is idle at that K).
+// Register budget: 8-wave tiles run two waves per SIMD (<= 256 VGPRs each),
+// 16-wave tiles four (<= 128).
+template <class... T>
+struct TileList {};
+
+template <int PREC>
+struct Cands;
 template <>
-struct Shapes<3> {  // BF16 three products: in 16 waves its operand fragments would spill
-  template <class F> static hipError_t pick(int K, F f) {
-    if (K > 128) return f(TileCfg<1, 2, 8, 1>{});
-    if (K > 64) return f(TileCfg<1, 2, 4, 2>{});
-    if (K > 32) return f(TileCfg<1, 2, 2, 4>{});
-    return f(TileCfg<1, 1, 1, 8>{});
-  }
+struct Cands<0> {  // 4 products: Er/Ei accumulators, 32 regs per output block
+  using L = TileList<TileCfg<1, 4, 8, 1>,   // 0: 256 x 128  (2 x 2 blocks per wave measured slower)
+                     TileCfg<1, 4, 4, 2>,   // 1: 128 x 256
+                     TileCfg<1, 2, 2, 4>,   // 2: 64 x 256
+                     TileCfg<1, 2, 1, 4>,   // 3: 32 x 256, 4 waves
+                     TileCfg<1, 2, 4, 2>>;  // 4: 128 x 128
+  static constexpr int dflt[4] = {3, 2, 1, 0};
+};
+template <>
+struct Cands<1> {  // BF16 x3, 4 products: the shapes of the FP32 form, and narrower pixel tiles
+  using L = TileList<TileCfg<1, 4, 8, 1>,   // 0: 256 x 128
+                     TileCfg<1, 4, 4, 2>,   // 1: 128 x 256
+                     TileCfg<1, 2, 2, 4>,   // 2: 64 x 256
+                     TileCfg<1, 2, 1, 4>,   // 3: 32 x 256, 4 waves
+                     TileCfg<1, 2, 4, 2>,   // 4: 128 x 128
+                     TileCfg<1, 2, 8, 1>>;  // 5: 256 x 64
+  static constexpr int dflt[4] = {3, 2, 1, 0};
+};
+template <>
+struct Cands<2> {  // 3 products: k1/k2/k3 accumulators, 48 regs per output block
+  using L = TileList<TileCfg<1, 2, 8, 1>,   // 0: 256 x 64
+                     TileCfg<1, 1, 4, 4>,   // 1: 128 x 128, 16 waves: 3 active k-blocks (K <= 96) still
+                                            //    spread evenly over the four SIMDs
+                     TileCfg<1, 2, 2, 4>,   // 2: 64 x 256
+                     TileCfg<1, 1, 1, 8>,   // 3: 32 x 256, one pixel block per wave, two waves per SIMD
+                     TileCfg<1, 2, 4, 2>,   // 4: 128 x 128
+                     TileCfg<1, 1, 2, 8>>;  // 5: 64 x 256, 16 waves
+  static constexpr int dflt[4] = {3, 2, 1, 0};
+};
+template <>
+struct Cands<3> {  // BF16 three products: in 16 waves its operand fragments would spill
+  using L = TileList<TileCfg<1, 2, 8, 1>,   // 0: 256 x 64
+                     TileCfg<1, 2, 4, 2>,   // 1: 128 x 128
+                     TileCfg<1, 2, 2, 4>,   // 2: 64 x 256
+                     TileCfg<1, 1, 1, 8>,   // 3: 32 x 256
+                     TileCfg<1, 1, 4, 2>>;  // 4: 128 x 64
+  static constexpr int dflt[4] = {3, 2, 1, 0};
 };
 
-int synth_tile_pixels(int max_K_alloc, int precision) {
-  int nt = 0;
-  auto f = [&](auto cfg) {
-    nt = decltype(cfg)::NT;
-    return hipSuccess;
-  };
-  if (precision == 3)
-    Shapes<3>::pick(max_K_alloc, f);
-  else if (precision == 2)
-    Shapes<2>::pick(max_K_alloc, f);
+template <int I, class F, class T0, class... Ts>
+static hipError_t tile_at(int id, F&& f, TileList<T0, Ts...>) {
+  if (id == I) return f(T0{});
+  if constexpr (sizeof...(Ts) > 0)
+    return tile_at<I + 1>(id, f, TileList<Ts...>{});
   else
-    Shapes<0>::pick(max_K_alloc, f);
-  return nt;
+    return hipErrorInvalidValue;
 }
 
-int synth_tile_kc(int max_K_alloc, int precision) {
-  int kc = 0;
-  auto f = [&](auto cfg) {
-    kc = decltype(cfg)::KC;
+template <class... Ts>
+static constexpr int list_len(TileList<Ts...>) {
+  return (int)sizeof...(Ts);
+}
+
+// f(cfg) for tile `id` of `precision`; hipErrorInvalidValue for an unknown id.
+template <class F>
+static hipError_t with_tile(int precision, int id, F&& f) {
+  switch (precision) {
+    case 1: return tile_at<0>(id, f, Cands<1>::L{});
+    case 2: return tile_at<0>(id, f, Cands<2>::L{});
+    case 3: return tile_at<0>(id, f, Cands<3>::L{});
+    default: return tile_at<0>(id, f, Cands<0>::L{});
+  }
+}
+
+int synth_k_class(int K_alloc) { return K_alloc <= 32 ? 0 : (K_alloc <= 64 ? 1 : (K_alloc <= 128 ? 2 : 3)); }
+
+int synth_n_tiles(int precision) {
+  switch (precision) {
+    case 1: return list_len(Cands<1>::L{});
+    case 2: return list_len(Cands<2>::L{});
+    case 3: return list_len(Cands<3>::L{});
+    default: return list_len(Cands<0>::L{});
+  }
+}
+
+int synth_default_tile(int precision, int k_class) {
+  if (k_class < 0 || k_class > 3) return -1;
+  switch (precision) {
+    case 1: return Cands<1>::dflt[k_class];
+    case 2: return Cands<2>::dflt[k_class];
+    case 3: return Cands<3>::dflt[k_class];
+    default: return Cands<0>::dflt[k_class];
+  }
+}
+
+bool synth_tile_info(int precision, int id, int* kc, int* nt, int* waves) {
+  int a = 0, b = 0, c = 0;
+  const hipError_t e = with_tile(precision, id, [&](auto cfg) {
+    using C = decltype(cfg);
+    a = C::KC;
+    b = C::NT;
+    c = C::WAVES;
     return hipSuccess;
-  };
-  if (precision == 3)
-    Shapes<3>::pick(max_K_alloc, f);
-  else if (precision == 2)
-    Shapes<2>::pick(max_K_alloc, f);
-  else
-    Shapes<0>::pick(max_K_alloc, f);
-  return kc;
+  });
+  if (e != hipSuccess) return false;
+  if (kc) *kc = a;
+  if (nt) *nt = b;
+  if (waves) *waves = c;
+  return true;
+}
+
+bool synth_tile_allowed(int precision, int id, int k_class) {
+  static const int kmax[4] = {32, 64, 128, kMaxEig};
+  int kc = 0;
+  if (k_class < 0 || k_class > 3 || !synth_tile_info(precision, id, &kc, nullptr, nullptr)) return false;
+  return kc <= kmax[k_class];
 }
 
 template <int PREC>
-static hipError_t launch_prec(const FwdParams& p, int max_K_alloc, hipStream_t s) {
-  return Shapes<PREC>::pick(max_K_alloc, [&](auto cfg) { return launch_tc<PREC, 0>(p, cfg, s); });
+static hipError_t launch_prec_tile(const FwdParams& p, int id, hipStream_t s) {
+  return tile_at<0>(id, [&](auto cfg) { return launch_tc<PREC, 0>(p, cfg, s); }, typename Cands<PREC>::L{});
+}
+
+hipError_t launch_synth_tile(const FwdParams& p, int precision, int id, hipStream_t s) {
+  switch (precision) {
+    case 1: return launch_prec_tile<1>(p, id, s);
+    case 2: return launch_prec_tile<2>(p, id, s);
+    case 3: return launch_prec_tile<3>(p, id, s);
+    default: return launch_prec_tile<0>(p, id, s);
+  }
+}
+
+int synth_tile_pixels(int max_K_alloc, int precision) {
+  int nt = 0;
+  synth_tile_info(precision, synth_default_tile(precision, synth_k_class(max_K_alloc)), nullptr, &nt, nullptr);
+  return nt;
 }
 
 hipError_t launch_synth(const FwdParams& p, int max_K_alloc, int precision, int tile_pixels_out[1],
                         hipStream_t s) {
   if (tile_pixels_out) tile_pixels_out[0] = synth_tile_pixels(max_K_alloc, precision);
-  if (precision == 1) return launch_prec<1>(p, max_K_alloc, s);
-  if (precision == 2) return launch_prec<2>(p, max_K_alloc, s);
-  if (precision == 3) return launch_prec<3>(p, max_K_alloc, s);
-  return launch_prec<0>(p, max_K_alloc, s);
+  return launch_synth_tile(p, precision, synth_default_tile(precision, synth_k_class(max_K_alloc)), s);
 }
 
 int fields_tile_pixels(int K_alloc) { return synth_tile_pixels(K_alloc, 0); }
 
 hipError_t launch_fields(const FwdParams& p, int K_alloc, hipStream_t s) {
   // FP32 recompute of E for the backward pass (the handle's precision does not
-  // apply), in the forward's tile shape for this K: no idle k-block waves
-  return Shapes<0>::pick(K_alloc, [&](auto cfg) { return launch_tc<0, 1>(p, cfg, s); });
+  // apply), in the forward's default tile shape for this K: no idle k-block waves
+  using FieldsL = TileList<TileCfg<1, 4, 8, 1>, TileCfg<1, 4, 4, 2>, TileCfg<1, 2, 2, 4>, TileCfg<1, 2, 1, 4>>;
+  static_assert(Cands<0>::dflt[0] == 3 && Cands<0>::dflt[3] == 0, "the defaults of 4-product tiles lead the list");
+  return tile_at<0>(synth_default_tile(0, synth_k_class(K_alloc)), [&](auto cfg) { return launch_tc<0, 1>(p, cfg, s); },
+                    FieldsL{});
 }
 
 // Phase-generation throughput probe (measurement only): every thread takes one

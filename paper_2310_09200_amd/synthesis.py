@@ -57,6 +57,19 @@ class Context:
             pass
 
 
+def tile_shapes(precision):
+    """Tile shapes of a contraction mode: [(id, eigenpairs per pass, pixels per tile, waves, K classes)]."""
+    lib = load()
+    out = []
+    for t in range(_lib.BB_MAX_TILES):
+        kc, nt, wv, mask = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        if lib.bb_tile_info(_PREC[precision], t, ctypes.byref(kc), ctypes.byref(nt), ctypes.byref(wv),
+                            ctypes.byref(mask)) != _lib.BB_OK:
+            break
+        out.append((t, kc.value, nt.value, wv.value, [c for c in range(_lib.BB_K_CLASSES) if mask.value >> c & 1]))
+    return out
+
+
 def phase_probe(ctx, ant_xyz, wavelength_m, pix, reps=1, out=None):
     """Phase-generation throughput probe (measurement only; ``bb_phase_probe``).
 
@@ -268,6 +281,45 @@ class StandardSynthesis:
             self.handle, len(batch.inst), arr, batch.n_ant_rows, batch.n_w, batch.n_eig_rows, _ptr(batch.ant),
             _ptr(batch.W), _ptr(batch.d), _ptr(batch.lev), ctypes.c_void_p(ws_ptr), sz.value), self.ctx.handle)
         self._keep = [ws]
+
+    @property
+    def tiles(self):
+        """Tile id per K class (K rounded up to 32: <= 32, <= 64, <= 128, more) used by the synthesis launches."""
+        t = (ctypes.c_int32 * _lib.BB_K_CLASSES)()
+        check(self.lib.bb_synth_get_tiles(self.handle, t), self.ctx.handle)
+        return list(t)
+
+    @tiles.setter
+    def tiles(self, ids):
+        t = (ctypes.c_int32 * _lib.BB_K_CLASSES)(*[int(i) for i in ids])
+        check(self.lib.bb_synth_set_tiles(self.handle, t), self.ctx.handle)
+
+    def autotune_batched(self, batch, reps=2, return_scratch=False):
+        """Time every tile each K class of ``batch`` may use and keep the fastest (images untouched).
+
+        Returns {k_class: {tile_id: ms per launch}} (and, with ``return_scratch``, the scratch
+        images every timed launch accumulated into).
+        """
+        arr = (bb_instance * len(batch.inst))(*batch.inst)
+        sz = ctypes.c_size_t()
+        check(self.lib.bb_batched_workspace_size(self.handle, len(batch.inst), arr, ctypes.byref(sz)),
+              self.ctx.handle)
+        ws = torch.empty(int(sz.value) + 256, dtype=torch.uint8, device=self.ctx.device)
+        ws_ptr = (ws.data_ptr() + 255) // 256 * 256
+        scratch = torch.empty_like(self.images)
+        ms = (ctypes.c_double * (_lib.BB_K_CLASSES * _lib.BB_MAX_TILES))()
+        self.ctx.bind_current_stream()
+        check(self.lib.bb_synth_autotune_batched(
+            self.handle, len(batch.inst), arr, batch.n_ant_rows, batch.n_w, batch.n_eig_rows, _ptr(batch.ant),
+            _ptr(batch.W), _ptr(batch.d), _ptr(batch.lev), ctypes.c_void_p(ws_ptr), sz.value, _ptr(scratch),
+            int(reps), ms), self.ctx.handle)
+        out = {}
+        for c in range(_lib.BB_K_CLASSES):
+            row = {t: ms[c * _lib.BB_MAX_TILES + t] for t in range(_lib.BB_MAX_TILES)
+                   if ms[c * _lib.BB_MAX_TILES + t] >= 0}
+            if row:
+                out[c] = row
+        return (out, scratch) if return_scratch else out
 
     def eig_backward(self, x, wavelength, W, d, level_of, grad_images):
         """Gradient of sum(grad_images * I) for one instance's images I (before accumulation).

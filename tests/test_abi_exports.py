@@ -43,3 +43,27 @@ def test_missing_library_fails_loudly(tmp_path):
     from paper_2310_09200_amd import _lib
     with pytest.raises(RuntimeError):
         _lib.load(str(tmp_path / "nope.so"))
+
+
+def test_tile_table_of_every_precision():
+    """Every contraction mode lists tile shapes; each K class has at least one
+    candidate, the default among them; the ids past the end are rejected (host
+    only: bb_tile_info touches no device)."""
+    from paper_2310_09200_amd import _lib
+    from paper_2310_09200_amd.synthesis import tile_shapes
+    lib = _lib.load()
+    for prec in ("fp32", "bf16x3", "fp32_3m", "bf16x3_3m"):
+        shapes = tile_shapes(prec)
+        assert 4 <= len(shapes) <= _lib.BB_MAX_TILES
+        kmax = [32, 64, 128, 1024]
+        for t, kc, nt, waves, classes in shapes:
+            assert kc % 32 == 0 and nt % 32 == 0 and waves in (4, 8, 16)
+            assert classes == [c for c in range(4) if kc <= kmax[c]]
+        for c in range(4):
+            assert any(c in cl for *_, cl in shapes)
+        # the defaults: one k-block of 32 per wave-row covering the class's largest K in one pass
+        assert [s[1] for s in shapes[:4]] == [256, 128, 64, 32]
+    kc = ctypes.c_int32()
+    assert lib.bb_tile_info(2, _lib.BB_MAX_TILES, ctypes.byref(kc), None, None, None) == _lib.BB_ERR_INVALID_ARG
+    assert lib.bb_tile_info(2, -1, None, None, None, None) == _lib.BB_ERR_INVALID_ARG
+    assert lib.bb_tile_info(9, 0, None, None, None, None) == _lib.BB_ERR_INVALID_ARG

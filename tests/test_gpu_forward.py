@@ -300,6 +300,84 @@ def test_batched_uneven_instances(ctx, precision):
 
 
 @pytest.fixture(scope="module")
+def tile_case():
+    """Instances of every K class (K = 20, 50, 100, 200) over two slots, ragged antenna and pixel counts."""
+    g = np.random.default_rng(77)
+    pix = sims.pixel_grid(45, 6.0, 60.0)
+    wl = sims.wavelength_m(150e6)
+    items, want = [], np.zeros((2, 3, pix.shape[0]))
+    for i, (L, K) in enumerate([(70, 20), (90, 50), (60, 100), (130, 200), (45, 33)]):
+        x = sims.disk_layout(L, 3000.0, g, z_sigma_m=2.0)
+        W = sims.random_eigvecs(L, K, g).astype(np.complex64)
+        d = g.normal(0, 1, K).astype(np.float32)
+        lev = g.integers(-1, 3, K).astype(np.int32)
+        items.append((i % 2, x, wl, W, d, lev))
+        want[i % 2] += oracle_images(W.astype(np.complex128), d.astype(np.float64), lev, x, wl, pix, 3)
+    return pix, items, want
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_3m", "bf16x3", "bf16x3_3m"])
+def test_every_tile_shape(ctx, tile_case, precision):
+    """Every tile shape each K class may use images a mixed batch within the oracle tolerance."""
+    from paper_2310_09200_amd import Batch, StandardSynthesis, tile_shapes
+    pix, items, want = tile_case
+    shapes = tile_shapes(precision)
+    allowed = [[t for t, *_, cl in shapes if c in cl] for c in range(4)]
+    for j in range(max(len(a) for a in allowed)):
+        tiles = [a[j % len(a)] for a in allowed]
+        say(f"case tiles precision={precision} tiles={tiles}")
+        s = StandardSynthesis(ctx, pix, 3, 2, 130, 200, precision)
+        s.tiles = tiles
+        assert s.tiles == tiles
+        s.collect_eig_batched(Batch(items, ctx.device))
+        s.sync()
+        got = s.images.double().cpu().numpy()
+        s.close()
+        for sl in range(2):
+            err = level_errors(got[sl], want[sl])
+            assert np.all(err[:, 0] <= TOL[precision]), (tiles, sl, err)
+
+
+def test_autotune_keeps_images_and_picks_candidates(ctx, tile_case):
+    """Autotuning times the candidates on the batch without touching the handle's images; the chosen
+    tiles are candidates of their class, and the handle then images the batch correctly."""
+    from paper_2310_09200_amd import Batch, BluebildError, StandardSynthesis, tile_shapes
+    say("case autotune")
+    pix, items, want = tile_case
+    s = StandardSynthesis(ctx, pix, 3, 2, 130, 200, "fp32_3m")
+    b = Batch(items, ctx.device)
+    reps = 2
+    ms, scratch = s.autotune_batched(b, reps=reps, return_scratch=True)
+    s.sync()
+    assert torch.count_nonzero(s.images).item() == 0
+    shapes = tile_shapes("fp32_3m")
+    assert sorted(ms) == [0, 1, 2, 3]
+    for c, row in ms.items():
+        assert set(row) == {t for t, *_, cl in shapes if c in cl} and min(row.values()) > 0
+        assert s.tiles[c] == min(row, key=row.get)
+    # every timed launch (one warm-up + reps per candidate) imaged its class's instances into the scratch
+    kclass = [min(3, (int(np.ceil(W.shape[1] / 32)) * 32 > 32) + (int(np.ceil(W.shape[1] / 32)) * 32 > 64)
+                  + (int(np.ceil(W.shape[1] / 32)) * 32 > 128)) for _, _, _, W, _, _ in items]
+    want_scr = np.zeros_like(want)
+    for (slot, x, wl, W, d, lev), c in zip(items, kclass):
+        want_scr[slot] += (reps + 1) * len(ms[c]) * oracle_images(W.astype(np.complex128), d.astype(np.float64),
+                                                                   lev, x, wl, pix, 3)
+    got_scr = scratch.double().cpu().numpy()
+    for sl in range(2):
+        assert np.all(level_errors(got_scr[sl], want_scr[sl])[:, 0] <= 1e-5)
+    s.collect_eig_batched(b)
+    s.sync()
+    got = s.images.double().cpu().numpy()
+    for sl in range(2):
+        assert np.all(level_errors(got[sl], want[sl])[:, 0] <= 1e-5)
+    with pytest.raises(BluebildError):
+        s.tiles = [0, 0, 0, 0]        # a 256-eigenpair tile is not a candidate for K <= 32
+    s.tiles = [-1, -1, -1, -1]        # defaults
+    assert s.tiles == [3, 2, 1, 0]
+    s.close()
+
+
+@pytest.fixture(scope="module")
 def c2_case():
     """Twelve C2 epochs spread over the 6 h track, FP64 oracle eigenpairs, sampled pixels.
 
