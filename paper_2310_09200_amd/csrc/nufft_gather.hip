@@ -60,8 +60,14 @@ struct ColBlock {
 };
 
 // Word n (0..15) of each row of 16 lanes, to every lane of that row.  The
-// empty asm keeps the broadcast a v_mov_b32_dpp of its own: folded into the
-// consumer (a VOP2 with a row_newbcast source) it gave wrong values.
+// empty asm keeps the broadcast a v_mov_b32_dpp of its own.  Left alone, the
+// compiler folds the broadcast into its consumer as a DPP operand, among
+// others into v_subrev_u32_dpp for the integer grid index; on gfx950 that
+// opcode applies the DPP lane control to src1 instead of src0 (measured with
+// one-wave checks: v_subrev_u32_dpp with row_newbcast or row_shr selects the
+// lanes of src1, while v_sub_u32_dpp, v_sub_f32_dpp, v_subrev_f32_dpp and
+// v_mul_f32_dpp select those of src0), so the folded code read the wrong
+// lanes.  A plain v_mov_b32_dpp behaves as documented.
 template <int N>
 __device__ __forceinline__ float row_bcast(int v) {
   int r = __builtin_amdgcn_mov_dpp(v, 0x150 + N, 0xF, 0xF, true);
