@@ -368,7 +368,7 @@ def measure_nufft(args, torch, ctx):
 
     s = StandardSynthesis(ctx, w.pix, n_levels, 1, 512, 512, args.precision)
     plan = NufftSynthesis(ctx, w.pix, n_levels, 512, 512, args.nufft_eps, frame, uvw, transform=args.nufft_transform,
-                          partitions=args.nufft_partitions)
+                          partitions=args.nufft_partitions, uvw_partitions=args.nufft_uvw_partitions)
     N, M, kw = plan.shape
     s.collect_eig_batched(batch)
     plan.collect_eig_batched(batch)
@@ -404,7 +404,8 @@ def measure_nufft(args, torch, ctx):
     s.close()
     plan.close()
     prods = batch.products * w.n_pix
-    log(f"NUFFT {side}^2 ({args.nufft_partitions}x{args.nufft_partitions} partitions): standard {np.mean(std_ms):.1f} ms, NUFFT {np.mean(nu_ms):.1f} ms "
+    log(f"NUFFT {side}^2 ({args.nufft_partitions}x{args.nufft_partitions} image, {args.nufft_uvw_partitions}x"
+        f"{args.nufft_uvw_partitions} uvw partitions): standard {np.mean(std_ms):.1f} ms, NUFFT {np.mean(nu_ms):.1f} ms "
         f"(spread {np.mean(spread_ms):.1f}, emit {np.mean(emit_ms):.1f}), grid {N} fft {M} w={kw}, "
         f"max level diff {max(errs):.2e}")
     return {"workload": f"SKA-Low-like 512 stations (65 km), 50 epochs over 6 h, {side}x{side} pixels of 4 arcsec "
@@ -414,10 +415,59 @@ def measure_nufft(args, torch, ctx):
             "nufft_ms": float(np.mean(nu_ms)), "nufft_spread_ms": float(np.mean(spread_ms)),
             "nufft_emit_ms": float(np.mean(emit_ms)), "speedup_nufft_over_standard": float(np.mean(std_ms) / np.mean(nu_ms)),
             "products": prods, "standard_products_per_s": prods / (np.mean(std_ms) / 1e3),
-            "partitions": args.nufft_partitions,
+            "partitions": args.nufft_partitions, "uvw_partitions": args.nufft_uvw_partitions,
             "transform": {"auto": "pruned, own LDS line FFTs where every axis fits, else rocFFT",
                           "rocfft": "pruned, rocFFT"}[args.nufft_transform],
             "max_level_diff_nufft_vs_standard": max(errs)}
+
+
+def measure_nufft_memory(args, torch, ctx):
+    """Device memory of NUFFT plans for the widest field here (the SKA-Low-like C3 field: 8 deg, 2048^2 pixels,
+    65 km baselines over 50 epochs, 8+1 levels, eps 1e-5), one grid against image x uvw partitions (Section 3.4.1).
+
+    Partitioned plans: bb_nufft_workspace_size of the library (one shared grid and transform buffers for the
+    largest (tile, cell) pair, plus each tile's tables, pixels and images).  One grid: its n_levels N0 N1 N2
+    complex64 cells from the same grid rules (the pruned transform's stage buffers come on top).
+    """
+    import ctypes
+    from paper_2310_09200_amd import _lib
+    from sims import configs, tangent_basis
+    from oracle import nufft_ref
+    w = configs.c3(n_steps=50, n_side=2048)
+    frame = np.array(tangent_basis(w.dec0_deg))
+    uvw = np.zeros(3)
+    for i in range(w.n_steps):
+        inst = w.instance(i)
+        li, mi = np.triu_indices(inst.x.shape[0], k=1)
+        uvw = np.maximum(uvw, np.max(np.abs((inst.x[li] - inst.x[mi]) @ frame.T / inst.wl), axis=0))
+    uvw = uvw * 1.001
+    n_levels, eps = 9, 1e-5
+    N = nufft_ref.plan_params(eps, uvw, nufft_ref.rotate(w.pix, frame))["N"]
+    one_grid = 8.0 * float(np.prod(N)) * n_levels
+    pix_cm = np.ascontiguousarray(np.asarray(w.pix, np.float64).T)
+    out = {"workload": "SKA-Low-like 512 stations (65 km), 50 epochs, 2048x2048 pixels over 8 deg, 8+1 levels, "
+                       "eps 1e-5",
+           "uvw_max": list(uvw), "one_grid": {"spread_grid": [int(n) for n in N], "grid_bytes": one_grid,
+                                              "source": "grid rules (oracle plan_params)"},
+           "partitioned": []}
+    log(f"NUFFT memory, 8 deg 2048^2 field: one grid {N} = {one_grid / 1e9:.0f} GB of grid cells")
+    for P, Q in [(8, 1), (8, 2), (8, 4)]:
+        opt = _lib.bb_nufft_options(n_levels=n_levels, n_ant_max=512, k_max=512, transform=0, epsilon=eps,
+                                    partitions=P, uvw_partitions=Q)
+        fr = frame.reshape(9)
+        for i in range(9):
+            opt.frame[i] = float(fr[i])
+        for i in range(3):
+            opt.uvw_max[i] = float(uvw[i])
+        sz = ctypes.c_size_t()
+        st = ctx.lib.bb_nufft_workspace_size(ctx.handle, ctypes.byref(opt), pix_cm.shape[1],
+                                             ctypes.c_void_p(pix_cm.ctypes.data), ctypes.byref(sz))
+        rec = {"partitions": P, "uvw_partitions": Q, "status": _lib.STATUS.get(st, st),
+               "workspace_bytes": int(sz.value) if st == 0 else None, "source": "bb_nufft_workspace_size"}
+        out["partitioned"].append(rec)
+        log(f"NUFFT memory, {P}x{P} image x {Q}x{Q} uvw partitions: "
+            f"{(sz.value / 1e9) if st == 0 else float('nan'):.1f} GB workspace")
+    return out
 
 
 def measure_workload(args, torch, ctx, w, items, n_levels, modes, sel, steps, warmup, workers):
@@ -549,6 +599,8 @@ def main():
                     help="type-2 transform of the NUFFT comparison")
     ap.add_argument("--nufft-partitions", type=int, default=1,
                     help="image-domain partitions per axis of the NUFFT comparison")
+    ap.add_argument("--nufft-uvw-partitions", type=int, default=1,
+                    help="uvw-domain partitions per axis of the NUFFT comparison")
     ap.add_argument("--only-nufft", action="store_true",
                     help="print only the NUFFT-vs-standard measurement (for profiling it alone)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -717,6 +769,7 @@ def main():
         out["batched_c4"] = measure_c4(args, torch, ctx)
         out["backward_c5"] = measure_c5_backward(args, torch, ctx)
         out["nufft_vs_standard"] = measure_nufft(args, torch, ctx)
+        out["nufft_memory"] = measure_nufft_memory(args, torch, ctx)
     print(json.dumps(out), flush=True)
 
 

@@ -395,13 +395,24 @@ typedef struct {
   double uvw_max[3];  /* bound on |<x_q - x_r, frame row d>| / lambda_w over every baseline
                          to be collected (wavelengths); a baseline beyond it is skipped and
                          reported by bb_nufft_sync */
-  int32_t partitions; /* image-domain partitions per axis, 0..8 (0 and 1: one grid).  With
+  int32_t partitions; /* image-domain partitions per axis, 0..8 (0 and 1: one tile).  With
                          P > 1 the pixels are split into P x P tiles of the (e_u, e_v)
-                         extent, each imaged by its own NUFFT (grid sized to the tile;
-                         Section 3.4.1): every baseline is spread once per tile, and a wide
-                         field gets thinner, smaller grids */
-  int32_t reserved;   /* must be 0 */
+                         extent, each imaged by its own NUFFTs (grids sized to the tile) */
+  int32_t uvw_partitions; /* uvw-domain partitions per axis, 0..16 (0 and 1: one cell).  With
+                         Q > 1 the baselines are split into Q x Q cells of
+                         [-uvw_max[0], uvw_max[0]] x [-uvw_max[1], uvw_max[1]] along e_u and e_v
+                         (cell of b: floor((b + X) Q / (2 X)), clamped to [0, Q - 1]); each
+                         cell's baselines are shifted by the cell centre C and transformed on a
+                         grid sized by the cell's half-width (X / Q) (1 + 1e-9), and the result
+                         multiplied by exp(2 pi i <p, C>) */
 } bb_nufft_options;
+/* Partitioned plans (partitions > 1 or uvw_partitions > 1; Section 3.4.1) run one
+ * NUFFT per (image tile, uvw cell) pair, one after another on the stream, all on
+ * one grid and one set of transform buffers sized for the largest pair: memory
+ * is bounded by the largest pair, not the sum.  Each bb_nufft_collect_eig_batched
+ * call of a partitioned plan spreads, transforms and interpolates right away
+ * (Algorithm 3 adds one NUFFT per step), so its bb_nufft_emit has nothing left to
+ * do; the images are the same up to rounding. */
 
 /* Workspace bytes of a plan.  pix_host: host, n_pix x 3 float64 column-major,
  * the pixels the plan will be created with (their extents fix the grid). */

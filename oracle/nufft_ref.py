@@ -58,7 +58,7 @@ import math
 import numpy as np
 
 __all__ = ["level_visibilities", "nudft3", "kernel_width", "plan_params", "rotate", "es_kernel", "kernel_ft",
-           "nufft3", "nufft_image", "nufft_images", "smooth_size"]
+           "nufft3", "nufft3_uvw_cells", "nufft_image", "nufft_images", "smooth_size", "uvw_cell", "uvw_cell_centre"]
 
 SIGMA = 2
 QUAD_NODES = 100
@@ -232,12 +232,53 @@ def nufft3(c, x, s, eps, X=None, tie="low"):
     return F / phi_hat[:, None]
 
 
-def nufft_images(instances, pix, eps, X=None, frame=None, tie="low"):
+def uvw_cell(b, X, q):
+    """uvw cell of baseline coordinates b along one axis: floor((b + X) q / (2 X)), clamped to [0, q - 1]."""
+    c = np.floor((np.asarray(b, np.float64) + X) * (q / (2.0 * X))).astype(np.int64)
+    return np.clip(c, 0, q - 1)
+
+
+def uvw_cell_centre(i, X, q):
+    """Centre of cell i of q along an axis of half-width X: (i + 1/2) (2 X / q) - X."""
+    return (i + 0.5) * (2.0 * X / q) - X
+
+
+def nufft3_uvw_cells(c, x, s, eps, X, q, tie="low"):
+    """nufft3 with the sources split into q x q cells along axes 0 and 1 (Section 3.4.1).
+
+    The sum over all sources is the sum over the cells; a cell's sources are
+    shifted by its centre C (the sum then gains the factor exp(2 pi i <s, C>))
+    and transformed with the cell's half-width (X / q)(1 + 1e-9) on axes 0, 1.
+    """
+    c = np.asarray(c, np.complex128)
+    if c.ndim == 1:
+        c = c[:, None]
+    x = np.asarray(x, np.float64)
+    s = np.asarray(s, np.float64)
+    X = np.asarray(X, np.float64)
+    iu, iv = uvw_cell(x[:, 0], X[0], q), uvw_cell(x[:, 1], X[1], q)
+    Xc = X.copy()
+    Xc[:2] = (X[:2] / q) * (1.0 + 1e-9)
+    out = np.zeros((s.shape[0], c.shape[1]), np.complex128)
+    for a in range(q):
+        for b in range(q):
+            sel = (iu == a) & (iv == b)
+            if not np.any(sel):
+                continue
+            C = np.array([uvw_cell_centre(a, X[0], q), uvw_cell_centre(b, X[1], q), 0.0])
+            t = s @ C
+            out += nufft3(c[sel], x[sel] - C, s, eps, X=Xc, tie=tie) * np.exp(2j * np.pi * (t - np.rint(t)))[:, None]
+    return out
+
+
+def nufft_images(instances, pix, eps, X=None, frame=None, tie="low", uvw_cells=1):
     """Level images summed over instances by NUFFT synthesis.
 
     instances: iterable of (x (L, 3) metres, wavelength, W (L, K), d (K,), member (N_L, K) bool).
     frame: rows e_u, e_v, p0 (default: the identity); X: per-axis bound on |b| in
-    wavelengths in that frame (default: the largest over the instances); tie: as in nufft3.
+    wavelengths in that frame (default: the largest over the instances); tie: as in nufft3;
+    uvw_cells: q > 1 splits the baselines into q x q cells of [-X, X] along e_u, e_v
+    (nufft3_uvw_cells).
     Returns (N_L, N_pix) float64.
     """
     R = np.eye(3) if frame is None else np.asarray(frame, np.float64)
@@ -250,7 +291,12 @@ def nufft_images(instances, pix, eps, X=None, frame=None, tie="low"):
         diag = diag + np.real(np.einsum("nll->n", Vp))
     pos = np.concatenate(pos)
     val = np.concatenate(val)
-    f = nufft3(val, pos, rotate(pix, R), eps, X=X, tie=tie)    # (N_pix, N_L)
+    if uvw_cells > 1:
+        if X is None:
+            X = np.max(np.abs(pos), axis=0)
+        f = nufft3_uvw_cells(val, pos, rotate(pix, R), eps, X, uvw_cells, tie=tie)
+    else:
+        f = nufft3(val, pos, rotate(pix, R), eps, X=X, tie=tie)    # (N_pix, N_L)
     return (2.0 * np.real(f)).T + np.asarray(diag)[:, None]
 
 

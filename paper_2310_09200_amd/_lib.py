@@ -34,7 +34,7 @@ class bb_options(ctypes.Structure):
 class bb_nufft_options(ctypes.Structure):
     _fields_ = [("n_levels", c_int32), ("n_ant_max", c_int32), ("k_max", c_int32), ("transform", c_int32),
                 ("epsilon", c_double), ("frame", c_double * 9), ("uvw_max", c_double * 3),
-                ("partitions", c_int32), ("reserved", c_int32)]
+                ("partitions", c_int32), ("uvw_partitions", c_int32)]
 
 
 class bb_instance(ctypes.Structure):

@@ -153,7 +153,23 @@ struct NufftGeom {
   int win_len[3];   // number of type-2 grid points the pixels need per axis
   int w;            // kernel support in grid points
   float beta;       // kernel shape
+  // uvw-domain partitions (Section 3.4.1): a plan may transform only the
+  // baselines of one cell of a cell_q x cell_q split of [-Xf, Xf] along e_u
+  // and e_v, shifted by the cell's centre C (its grid is sized by the cell's
+  // half-width X); the interpolation multiplies by exp(2 pi i <s, C>).
+  double C[3];      // source shift, wavelengths (zero without cells)
+  double Xf[3];     // bound on |baseline| of every source (the plan's uvw_max)
+  int cell_q;       // cells per axis along e_u and e_v (<= 1: a single cell, no shift)
+  int cell_i[2];    // this plan's cell along e_u and e_v
+  int use_diag;     // the interpolation adds sum_q V'_qq (one plan per set of pixels)
 };
+
+// uvw cell of a baseline coordinate b along one axis: floor((b + X) q / (2 X)),
+// clamped to [0, q - 1] (so b = X falls in the last cell).
+__host__ __device__ inline int uvw_cell(double b, double X, int q) {
+  const int c = (int)floor((b + X) * (q / (2.0 * X)));
+  return c < 0 ? 0 : (c >= q ? q - 1 : c);
+}
 struct NufftInst {
   int n_ant, n_eig;
   double wavelength_m;
@@ -176,6 +192,8 @@ struct InterpLayout {
   int64_t s1, s2;
   int lo0, len0;
 };
+// Adds 2 Re(exp(2 pi i <s, C>) interpolated value) * corr (+ diag[lv] when
+// g.use_diag) to each pixel's level image.
 hipError_t launch_nufft_interp(const NufftGeom& g, const InterpLayout& lay, const double* pix, int64_t pix_ld,
                                int64_t n_pix, const float* u, const double* corr, const double* diag, int lv,
                                float* image, hipStream_t s);

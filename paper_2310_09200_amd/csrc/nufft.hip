@@ -112,35 +112,27 @@ __global__ __launch_bounds__(256) void nufft_spread_kernel(NufftGeom g, const Nu
   const int q = (int)(pair % L), r = (int)(pair / L);  // consecutive lanes: consecutive q, same r
   if (q >= r) return;
 
-  const double* A = ant + I.ant_off;
-  double b[3];
-  {
-#pragma clang fp contract(off)
-    const double d0 = A[q] - A[r];
-    const double d1 = A[q + ant_ld] - A[r + ant_ld];
-    const double d2 = A[q + 2 * ant_ld] - A[r + 2 * ant_ld];
-    for (int d = 0; d < 3; ++d) b[d] = frame_coord(g, d, d0, d1, d2) / I.wavelength_m;
-  }
-  if (!(fabs(b[0]) <= g.X[0]) || !(fabs(b[1]) <= g.X[1]) || !(fabs(b[2]) <= g.X[2])) {
-    atomicOr(err, kErrNufftExtent);
+  double xi[3], t;
+  const int where = source_coords(g, I, ant, ant_ld, q, r, xi, t);
+  if (where != 0) {
+    if (where == 1) atomicOr(err, kErrNufftExtent);
     return;
   }
   // pre-phase exp(2 pi i <b, D>) centres the targets; turns reduced exactly in FP64
-  const double t = b[0] * g.D[0] + b[1] * g.D[1] + b[2] * g.D[2];
   const float f = (float)(t - rint(t));
   const float pc = __builtin_amdgcn_cosf(f), ps = __builtin_amdgcn_sinf(f);
 
   // axis 0 is walked at run time (its kernel value computed per step), axes 1
   // and 2 are unrolled from precomputed rows: keeps the w^2 addresses of a
   // step in registers without spilling
-  const double xi0 = b[0] * g.inv_h[0];
+  const double xi0 = xi[0];
   const double first0 = ceil(xi0 - 0.5 * W);
   int64_t j0 = (int64_t)first0 % g.N[0];
   if (j0 < 0) j0 += g.N[0];
   float k1[W], k2[W];
   int i1[W], i2[W];
-  kernel_row<W>(b[1] * g.inv_h[1], g.N[1], g.beta, k1, i1);
-  kernel_row<W>(b[2] * g.inv_h[2], g.N[2], g.beta, k2, i2);
+  kernel_row<W>(xi[1], g.N[1], g.beta, k1, i1);
+  kernel_row<W>(xi[2], g.N[2], g.beta, k2, i2);
   const float inv_half = 2.0f / (float)W;
 
   const float2* Wi = Wp + I.w_off;
@@ -272,8 +264,9 @@ __global__ __launch_bounds__(256) void nufft_bin_kernel(NufftGeom g, const Nufft
   const int q = (int)(pair % L), r = (int)(pair / L);
   if (q >= r) return;
   double xi[3], td;
-  if (!source_coords(g, I, ant, ld, q, r, xi, td)) {
-    if (pass == 0) atomicOr(err, kErrNufftExtent);
+  const int where = source_coords(g, I, ant, ld, q, r, xi, td);
+  if (where != 0) {  // beyond the extent (reported once), or another uvw cell's
+    if (where == 1 && pass == 0) atomicOr(err, kErrNufftExtent);
     return;
   }
   const int b = (first_cell(xi[0], g.w, g.N[0]) / bin) * nb1 + first_cell(xi[1], g.w, g.N[1]) / bin;
@@ -459,7 +452,7 @@ __global__ __launch_bounds__(256) void nufft_spread_tile_kernel(NufftGeom g, con
           const int inst = (int)(key >> 32), q = (int)((key >> 16) & 0xffff), r = (int)(key & 0xffff);
           const NufftInst I = insts[inst];
           double xi[3], td;
-          if (!source_coords(g, I, ant, ld, q, r, xi, td)) continue;
+          if (source_coords(g, I, ant, ld, q, r, xi, td) != 0) continue;
           const int L = I.n_ant;
           const float2 v = vp[I.vp_off + (int64_t)lv * L * L + q + (int64_t)r * L];
           const float f = (float)(td - rint(td));
@@ -597,7 +590,7 @@ __global__ __launch_bounds__(256) void nufft_gather_c_kernel(NufftGeom g, const 
 
 // ---------------------------------------------------------------------------
 // Interpolation at the pixels, correction and accumulation into one level's image.
-template <int W>
+template <int W, bool SHIFT>
 __global__ __launch_bounds__(256) void nufft_interp_kernel(NufftGeom g, InterpLayout lay,
                                                            const double* __restrict__ pix, int64_t pix_ld,
                                                            int64_t n_pix, const float* __restrict__ u,
@@ -607,11 +600,13 @@ __global__ __launch_bounds__(256) void nufft_interp_kernel(NufftGeom g, InterpLa
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_pix) return;
   const double a0 = pix[p], a1 = pix[p + pix_ld], a2 = pix[p + 2 * pix_ld];
+  const double s0 = frame_coord(g, 0, a0, a1, a2), s1 = frame_coord(g, 1, a0, a1, a2),
+               s2 = frame_coord(g, 2, a0, a1, a2);
   float k0[W], k1[W], k2[W];
   int i0[W], i1[W], i2[W];
-  kernel_row<W>((frame_coord(g, 0, a0, a1, a2) - g.D[0]) * g.hM[0], g.M[0], g.beta, k0, i0);
-  kernel_row<W>((frame_coord(g, 1, a0, a1, a2) - g.D[1]) * g.hM[1], g.M[1], g.beta, k1, i1);
-  kernel_row<W>((frame_coord(g, 2, a0, a1, a2) - g.D[2]) * g.hM[2], g.M[2], g.beta, k2, i2);
+  kernel_row<W>((s0 - g.D[0]) * g.hM[0], g.M[0], g.beta, k0, i0);
+  kernel_row<W>((s1 - g.D[1]) * g.hM[1], g.M[1], g.beta, k1, i1);
+  kernel_row<W>((s2 - g.D[2]) * g.hM[2], g.M[2], g.beta, k2, i2);
   // window offsets; points outside the windows (pixels other than the ones
   // planned for) contribute nothing
   int w0[W], w1[W], w2[W];
@@ -624,7 +619,7 @@ __global__ __launch_bounds__(256) void nufft_interp_kernel(NufftGeom g, InterpLa
     w2[t] = i2[t] - g.win_lo[2];
     if (w2[t] < 0) w2[t] += g.M[2];
   }
-  float fr = 0.0f;
+  float fr = 0.0f, fi = 0.0f;
 #pragma unroll
   for (int c = 0; c < W; ++c) {
     if (w1[c] >= g.win_len[1]) continue;
@@ -632,14 +627,26 @@ __global__ __launch_bounds__(256) void nufft_interp_kernel(NufftGeom g, InterpLa
     for (int e = 0; e < W; ++e) {
       if (w2[e] >= g.win_len[2]) continue;
       const int64_t base = (int64_t)w1[c] * lay.s1 + (int64_t)w2[e] * lay.s2;
-      float s = 0.0f;
+      float sr = 0.0f, si = 0.0f;
 #pragma unroll
       for (int a = 0; a < W; ++a)
-        if (w0[a] < lay.len0) s += u[2 * (base + w0[a])] * k0[a];  // real part only: the image is 2 Re(.)
-      fr += s * k1[c] * k2[e];
+        if (w0[a] < lay.len0) {
+          sr += u[2 * (base + w0[a])] * k0[a];
+          if (SHIFT) si += u[2 * (base + w0[a]) + 1] * k0[a];
+        }
+      fr += sr * k1[c] * k2[e];
+      if (SHIFT) fi += si * k1[c] * k2[e];
     }
   }
-  image[p] += (float)(2.0 * (double)fr * corr[p] + diag[lv]);
+  // the image is 2 Re(.); a uvw cell's sources were shifted by C, which the
+  // factor exp(2 pi i <s, C>) restores (turns reduced exactly in FP64)
+  double val = fr;
+  if (SHIFT) {
+    const double t = s0 * g.C[0] + s1 * g.C[1] + s2 * g.C[2];
+    const float f = (float)(t - rint(t));
+    val = (double)fr * (double)__builtin_amdgcn_cosf(f) - (double)fi * (double)__builtin_amdgcn_sinf(f);
+  }
+  image[p] += (float)(2.0 * val * corr[p] + (g.use_diag ? diag[lv] : 0.0));
 }
 
 // Per-pixel correction 1 / prod_d (phi_hat_d(2 pi s_d) / h_d), by quadrature:
@@ -824,8 +831,12 @@ hipError_t launch_nufft_interp(const NufftGeom& g, const InterpLayout& lay, cons
   const dim3 grd((unsigned)((n_pix + 255) / 256));
   return with_width(g.w, [&](auto wc) {
     constexpr int KW = decltype(wc)::value;
-    hipLaunchKernelGGL(nufft_interp_kernel<KW>, grd, dim3(256), 0, s, g, lay, pix, pix_ld, n_pix, u, corr, diag, lv,
-                       image);
+    if (g.cell_q > 1)
+      hipLaunchKernelGGL((nufft_interp_kernel<KW, true>), grd, dim3(256), 0, s, g, lay, pix, pix_ld, n_pix, u, corr,
+                         diag, lv, image);
+    else
+      hipLaunchKernelGGL((nufft_interp_kernel<KW, false>), grd, dim3(256), 0, s, g, lay, pix, pix_ld, n_pix, u, corr,
+                         diag, lv, image);
     return hipGetLastError();
   });
 }

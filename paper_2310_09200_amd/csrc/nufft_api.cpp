@@ -26,12 +26,25 @@ namespace {
 constexpr int kSigma = 2;        // type-2 grid upsampling
 constexpr int kQuadNodes = 100;  // Gauss-Legendre nodes for kernel transforms
 
-struct NufftLayout {  // byte offsets into a plan's workspace
-  size_t grid, work, psi0, psi1, psi2, corr, quad_t, quad_wphi, diag, err, total;
-  size_t work_bytes;
-  size_t stage_ac, stage_b;  // the pruned transform's two stage regions
-  size_t perm[3];            // line FFTs: digit-reversed load position per input index (int32, M_d)
-  size_t tw[3];              // line FFTs: the passes' twiddles (complex64, M_d - 1)
+// Byte offsets of a plan's two regions.  The transient region (grid, the
+// pruned transform's stages, rocFFT's work area) holds data only from a spread
+// to the end of the next emit, so the plans of a partitioned plan, run one
+// after another, share one; the persistent region (tables, corrections, level
+// diagonals, error word) is each plan's own.  A single plan's workspace is the
+// transient region followed by the persistent one.
+struct NufftLayout {
+  size_t grid, stage_ac, stage_b, work, work_bytes, t_total;  // from the transient base
+  size_t perm[3];  // line FFTs: digit-reversed load position per input index (int32, M_d)
+  size_t tw[3];    // line FFTs: the passes' twiddles (complex64, M_d - 1)
+  size_t psi0, psi1, psi2, corr, quad_t, quad_wphi, diag, err, p_total;  // from the persistent base
+  size_t total;    // t_total + p_total
+};
+
+// Which uvw cell a plan transforms (cells of 1: every baseline, no shift), and
+// whether its interpolation adds the level diagonals.
+struct CellSpec {
+  int q = 1, iu = 0, iv = 0;
+  bool use_diag = true;
 };
 
 // The pruned type-2 transform runs as the library's own LDS line FFTs when
@@ -117,7 +130,7 @@ int smooth_size(int64_t n) {
 // Plan geometry (the same rules, in the same arithmetic order, as the
 // grid-size rules documented in the header).
 bb_status nufft_geometry(bb_context ctx, const bb_nufft_options* o, int64_t n_pix, const double* pix_host,
-                         bb::NufftGeom& g) {
+                         bb::NufftGeom& g, const CellSpec& cell = CellSpec{}) {
 #pragma clang fp contract(off)
   if (!o) return fail(ctx, BB_ERR_INVALID_ARG, "options is NULL");
   if (o->n_levels < 1 || o->n_levels > bb::kMaxLevels)
@@ -127,7 +140,8 @@ bb_status nufft_geometry(bb_context ctx, const bb_nufft_options* o, int64_t n_pi
   if (o->k_max < 1 || o->k_max > bb::kMaxEig) return fail(ctx, BB_ERR_INVALID_ARG, "k_max must be in [1, %d]", bb::kMaxEig);
   if (o->transform != 0 && o->transform != 1) return fail(ctx, BB_ERR_INVALID_ARG, "transform must be 0 or 1");
   if (o->partitions < 0 || o->partitions > 8) return fail(ctx, BB_ERR_INVALID_ARG, "partitions must be in [0, 8]");
-  if (o->reserved != 0) return fail(ctx, BB_ERR_INVALID_ARG, "reserved must be 0");
+  if (o->uvw_partitions < 0 || o->uvw_partitions > 16)
+    return fail(ctx, BB_ERR_INVALID_ARG, "uvw_partitions must be in [0, 16]");
   if (!(o->epsilon >= 1e-7 && o->epsilon <= 1e-2)) return fail(ctx, BB_ERR_INVALID_ARG, "epsilon must be in [1e-7, 1e-2]");
   for (int i = 0; i < 3; ++i)
     if (!finite_pos(o->uvw_max[i])) return fail(ctx, BB_ERR_INVALID_ARG, "uvw_max must be finite and > 0");
@@ -156,10 +170,21 @@ bb_status nufft_geometry(bb_context ctx, const bb_nufft_options* o, int64_t n_pi
   }
   g.w = kernel_width(o->epsilon);
   g.beta = (float)(2.30 * g.w);
+  g.cell_q = cell.q;
+  g.cell_i[0] = cell.iu;
+  g.cell_i[1] = cell.iv;
+  g.use_diag = cell.use_diag ? 1 : 0;
   for (int d = 0; d < 3; ++d) {
     g.D[d] = 0.5 * (lo[d] + hi[d]);
     const double S = std::max(0.5 * (hi[d] - lo[d]), 1e-12);
+    g.Xf[d] = o->uvw_max[d];
     g.X[d] = o->uvw_max[d];
+    g.C[d] = 0.0;
+    if (cell.q > 1 && d < 2) {  // a cell of the uvw split: its half-width, and its centre as the source shift
+      const int i = d == 0 ? cell.iu : cell.iv;
+      g.X[d] = (g.Xf[d] / cell.q) * (1.0 + 1e-9);
+      g.C[d] = (i + 0.5) * (2.0 * g.Xf[d] / cell.q) - g.Xf[d];
+    }
     g.h[d] = 1.0 / (2.0 * kSigma * S);
     g.inv_h[d] = 1.0 / g.h[d];
     const double need = std::ceil(8.0 * g.X[d] * S) + g.w;
@@ -226,7 +251,7 @@ size_t rocfft_work_bytes(const bb::NufftGeom& g, FftPlans* keep) {
 NufftLayout nufft_layout(const bb::NufftGeom& g, int n_levels, int64_t n_pix, size_t work_bytes, bool line_fft) {
   NufftLayout l{};
   const size_t n_cell = (size_t)g.N[0] * g.N[1] * g.N[2];
-  size_t p = 0;
+  size_t p = 0;  // transient region
   l.grid = p;
   p += align_up(8 * n_cell * (size_t)n_levels);
   if (line_fft) {
@@ -235,12 +260,6 @@ NufftLayout nufft_layout(const bb::NufftGeom& g, int n_levels, int64_t n_pix, si
     p += align_up(8 * std::max(st.a, st.b));
     l.stage_b = p;
     p += align_up(8 * std::max(st.b, st.c));
-    for (int d = 0; d < 3; ++d) {
-      l.perm[d] = p;
-      p += align_up(4 * (size_t)g.M[d]);
-      l.tw[d] = p;
-      p += align_up(8 * (size_t)g.M[d]);
-    }
   } else {
     const StageSizes st = stage_sizes(g);
     l.stage_ac = p;
@@ -251,6 +270,15 @@ NufftLayout nufft_layout(const bb::NufftGeom& g, int n_levels, int64_t n_pix, si
   l.work = p;
   l.work_bytes = work_bytes;
   p += align_up(std::max<size_t>(work_bytes, 1));
+  l.t_total = p;
+  p = 0;  // persistent region
+  if (line_fft)
+    for (int d = 0; d < 3; ++d) {
+      l.perm[d] = p;
+      p += align_up(4 * (size_t)g.M[d]);
+      l.tw[d] = p;
+      p += align_up(8 * (size_t)g.M[d]);
+    }
   l.psi0 = p;
   p += align_up(4 * (size_t)g.N[0]);
   l.psi1 = p;
@@ -267,7 +295,8 @@ NufftLayout nufft_layout(const bb::NufftGeom& g, int n_levels, int64_t n_pix, si
   p += align_up(8 * bb::kMaxLevels);
   l.err = p;
   p += bb_host::kAlign;
-  l.total = p;
+  l.p_total = p;
+  l.total = l.t_total + l.p_total;
   return l;
 }
 
@@ -276,8 +305,9 @@ rocfft_status g_rocfft_setup = rocfft_status_success;
 
 }  // namespace
 
-// One image-domain partition of a plan: an ordinary plan over its pixels,
-// whose images are added into the partitioned plan's images after each emit.
+// A tile of a partitioned plan's pixels (image-domain partition): its own
+// plan (grid sized to the tile), whose images are moved into the partitioned
+// plan's images after each call.
 struct NufftPart {
   bb_nufft sub = nullptr;
   int64_t n = 0;    // pixels
@@ -288,12 +318,14 @@ struct NufftPart {
 struct bb_nufft_ {
   bb_context ctx = nullptr;
   std::vector<NufftPart> parts;  // non-empty: a partitioned plan (the fields below describe its largest part)
+  int cells = 1;                 // uvw cells per axis of every part's plan
   bb_nufft_options opt{};
   bb::NufftGeom g{};
   int64_t n_pix = 0;
   const double* pix = nullptr;
   float* images = nullptr;
-  char* ws = nullptr;
+  char* tws = nullptr;  // transient region (shared by the parts of a partitioned plan)
+  char* pws = nullptr;  // persistent region
   NufftLayout lay{};
   bool line_fft = false;
   bb::LineFft lf[3]{};  // line-FFT stages: axis 2, axis 1, axis 0
@@ -307,20 +339,57 @@ struct bb_nufft_ {
 namespace {
 
 template <class T>
-T* nat(bb_nufft h, size_t off) {
-  return reinterpret_cast<T*>(h->ws + off);
+T* tnat(bb_nufft h, size_t off) {
+  return reinterpret_cast<T*>(h->tws + off);
+}
+template <class T>
+T* pnat(bb_nufft h, size_t off) {
+  return reinterpret_cast<T*>(h->pws + off);
 }
 
-// ---- image-domain partitions (Section 3.4.1) --------------------------------
+// Point a plan made for uvw cells at cell (iu, iv): its source shift and
+// whether its interpolation adds the level diagonals (the first cell does).
+void set_cell(bb::NufftGeom& g, int iu, int iv) {
+#pragma clang fp contract(off)
+  const int idx[2] = {iu, iv};
+  for (int d = 0; d < 2; ++d) g.C[d] = (idx[d] + 0.5) * (2.0 * g.Xf[d] / g.cell_q) - g.Xf[d];
+  g.C[2] = 0.0;
+  g.cell_i[0] = iu;
+  g.cell_i[1] = iv;
+  g.use_diag = (iu == 0 && iv == 0) ? 1 : 0;
+}
+
+bb_status plan_size(bb_context ctx, const bb_nufft_options* o, int64_t n_pix, const double* pix_host,
+                    const CellSpec& cell, bb::NufftGeom& g, bool& line_fft, NufftLayout& lay) {
+  bb_status st = nufft_geometry(ctx, o, n_pix, pix_host, g, cell);
+  if (st != BB_OK) return st;
+  line_fft = use_line_fft(g, o->transform, ctx->device);
+  size_t work = 0;
+  if (!line_fft) {
+    std::call_once(g_rocfft_once, [] { g_rocfft_setup = rocfft_setup(); });
+    if (g_rocfft_setup != rocfft_status_success) return fail(ctx, BB_ERR_DEVICE, "rocfft_setup failed");
+    work = rocfft_work_bytes(g, nullptr);
+    if (work == (size_t)-1) return fail(ctx, BB_ERR_DEVICE, "rocfft_plan_create failed");
+  }
+  lay = nufft_layout(g, o->n_levels, n_pix, work, line_fft);
+  return BB_OK;
+}
+
+bb_status create_one(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix, const double* pix_host,
+                     const double* pix_xyz, float* images, char* tws, char* pws, const CellSpec& cell,
+                     bb_nufft* out);
+
+// ---- partitions (Section 3.4.1) ----------------------------------------------
 // The pixels are split into P x P tiles of their extent along e_u and e_v;
-// each nonempty tile gets an ordinary plan (grid sized to the tile) with its
-// own pixel array, images and workspace, all carved from the caller's
-// workspace.
+// each nonempty tile gets a plan (grid sized to the tile, and to one uvw cell
+// when the baselines are split too) with its own pixel array, images and
+// persistent region, carved from the caller's workspace after one transient
+// region sized for the largest tile, which every tile's plan uses in turn.
 struct PartLayout {
   std::vector<std::vector<int64_t>> tiles;  // pixel indices per nonempty tile
   std::vector<std::vector<double>> pix;     // host copy of each tile's pixels (column-major)
-  std::vector<size_t> idx, px, img, ws, ws_bytes;
-  size_t total = 0;
+  std::vector<size_t> idx, px, img, pers;
+  size_t trans_bytes = 0, total = 0;
 };
 
 bb_status part_layout(bb_context ctx, const bb_nufft_options* o, int64_t n_pix, const double* pix_host,
@@ -328,10 +397,16 @@ bb_status part_layout(bb_context ctx, const bb_nufft_options* o, int64_t n_pix, 
 #pragma clang fp contract(off)
   bb_nufft_options one = *o;
   one.partitions = 1;
+  one.uvw_partitions = 1;
   bb::NufftGeom g;
   bb_status st = nufft_geometry(ctx, &one, n_pix, pix_host, g);  // validates the options and every pixel
   if (st != BB_OK) return st;
-  const int P = o->partitions;
+  if (o->partitions < 0 || o->partitions > 8) return fail(ctx, BB_ERR_INVALID_ARG, "partitions must be in [0, 8]");
+  if (o->uvw_partitions < 0 || o->uvw_partitions > 16)
+    return fail(ctx, BB_ERR_INVALID_ARG, "uvw_partitions must be in [0, 16]");
+  const int P = std::max(1, o->partitions);
+  CellSpec cell;
+  cell.q = std::max(1, o->uvw_partitions);
   std::vector<double> u(n_pix), v(n_pix);
   double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
   for (int64_t p = 0; p < n_pix; ++p) {
@@ -343,34 +418,41 @@ bb_status part_layout(bb_context ctx, const bb_nufft_options* o, int64_t n_pix, 
     lo[1] = std::min(lo[1], v[p]);
     hi[1] = std::max(hi[1], v[p]);
   }
-  auto cell = [&](double x, int d) {
+  auto tile_of = [&](double x, int d) {
     const double span = hi[d] - lo[d];
     if (!(span > 0.0)) return 0;
     return std::min(P - 1, std::max(0, (int)((x - lo[d]) / span * P)));
   };
   std::vector<std::vector<int64_t>> t(P * P);
-  for (int64_t p = 0; p < n_pix; ++p) t[cell(u[p], 0) * P + cell(v[p], 1)].push_back(p);
-  size_t off = 0;
+  for (int64_t p = 0; p < n_pix; ++p) t[tile_of(u[p], 0) * P + tile_of(v[p], 1)].push_back(p);
+  std::vector<NufftLayout> lays;
   for (auto& tile : t) {
     if (tile.empty()) continue;
     const int64_t n = (int64_t)tile.size();
     std::vector<double> px(3 * n);
     for (int64_t i = 0; i < n; ++i)
       for (int d = 0; d < 3; ++d) px[i + d * n] = pix_host[tile[i] + d * n_pix];
-    size_t b = 0;
-    st = bb_nufft_workspace_size(ctx, &one, n, px.data(), &b);
+    bb::NufftGeom gt;
+    bool line = false;
+    NufftLayout lay;
+    st = plan_size(ctx, &one, n, px.data(), cell, gt, line, lay);
     if (st != BB_OK) return st;
+    L.trans_bytes = std::max(L.trans_bytes, lay.t_total);
+    lays.push_back(lay);
+    L.tiles.push_back(std::move(tile));
+    L.pix.push_back(std::move(px));
+  }
+  size_t off = align_up(L.trans_bytes);
+  for (size_t k = 0; k < L.tiles.size(); ++k) {
+    const int64_t n = (int64_t)L.tiles[k].size();
     L.idx.push_back(off);
     off += align_up(8 * (size_t)n);
     L.px.push_back(off);
     off += align_up(24 * (size_t)n);
     L.img.push_back(off);
     off += align_up(4 * (size_t)o->n_levels * n);
-    L.ws.push_back(off);
-    L.ws_bytes.push_back(b);
-    off += align_up(b);
-    L.tiles.push_back(std::move(tile));
-    L.pix.push_back(std::move(px));
+    L.pers.push_back(off);
+    off += align_up(lays[k].p_total);
   }
   L.total = off;
   return BB_OK;
@@ -405,7 +487,9 @@ bb_status part_create(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix
   h->n_pix = n_pix;
   h->pix = pix_xyz;
   h->images = images;
-  h->ws = static_cast<char*>(workspace);
+  h->cells = std::max(1, opt->uvw_partitions);
+  h->tws = static_cast<char*>(workspace);
+  h->pws = static_cast<char*>(workspace);
   for (hipEvent_t& e : h->ev)
     if (hipEventCreate(&e) != hipSuccess) {
       part_destroy(h);
@@ -413,14 +497,17 @@ bb_status part_create(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix
     }
   bb_nufft_options one = *opt;
   one.partitions = 1;
+  one.uvw_partitions = 1;
+  CellSpec cell;
+  cell.q = h->cells;
   hipStream_t s = ctx->stream;
   int64_t biggest = -1;
   for (size_t t = 0; t < L.tiles.size(); ++t) {
     NufftPart q;
     q.n = (int64_t)L.tiles[t].size();
-    q.idx = nat<int64_t>(h, L.idx[t]);
-    q.img = nat<float>(h, L.img[t]);
-    double* px = nat<double>(h, L.px[t]);
+    q.idx = pnat<int64_t>(h, L.idx[t]);
+    q.img = pnat<float>(h, L.img[t]);
+    double* px = pnat<double>(h, L.px[t]);
     // pageable source: the copy is staged before the call returns
     if (hipMemcpyAsync(q.idx, L.tiles[t].data(), 8 * (size_t)q.n, hipMemcpyHostToDevice, s) != hipSuccess ||
         bb::launch_nufft_gather_pix(pix_xyz, n_pix, q.idx, q.n, px, s) != hipSuccess ||
@@ -428,7 +515,7 @@ bb_status part_create(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix
       part_destroy(h);
       return fail(ctx, BB_ERR_DEVICE, "partition set-up failed");
     }
-    st = bb_nufft_create(ctx, &one, q.n, L.pix[t].data(), px, q.img, h->ws + L.ws[t], L.ws_bytes[t], &q.sub);
+    st = create_one(ctx, &one, q.n, L.pix[t].data(), px, q.img, h->tws, h->pws + L.pers[t], cell, &q.sub);
     if (st != BB_OK) {
       part_destroy(h);
       return st;
@@ -445,46 +532,15 @@ bb_status part_create(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix
   return BB_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-bb_status bb_nufft_workspace_size(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix, const double* pix_host,
-                                  size_t* bytes) {
-  if (!ctx || !bytes) return BB_ERR_INVALID_ARG;
-  if (opt && opt->partitions > 1) {
-    PartLayout L;
-    const bb_status st = part_layout(ctx, opt, n_pix, pix_host, L);
-    if (st == BB_OK) *bytes = L.total;
-    return st;
-  }
-  bb::NufftGeom g;
-  bb_status st = nufft_geometry(ctx, opt, n_pix, pix_host, g);
-  if (st != BB_OK) return st;
-  const bool line_fft = use_line_fft(g, opt->transform, ctx->device);
-  size_t work = 0;
-  if (!line_fft) {
-    std::call_once(g_rocfft_once, [] { g_rocfft_setup = rocfft_setup(); });
-    if (g_rocfft_setup != rocfft_status_success) return fail(ctx, BB_ERR_DEVICE, "rocfft_setup failed");
-    work = rocfft_work_bytes(g, nullptr);
-    if (work == (size_t)-1) return fail(ctx, BB_ERR_DEVICE, "rocfft_plan_create failed");
-  }
-  *bytes = nufft_layout(g, opt->n_levels, n_pix, work, line_fft).total;
-  return BB_OK;
-}
-
-bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix, const double* pix_host,
-                          const double* pix_xyz, float* images, void* workspace, size_t ws_bytes, bb_nufft* out) {
-  if (!ctx || !out) return BB_ERR_INVALID_ARG;
+// A plan over the given pixels whose transient region is at tws and
+// persistent region at pws (sized by plan_size for the same arguments).
+bb_status create_one(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix, const double* pix_host,
+                     const double* pix_xyz, float* images, char* tws, char* pws, const CellSpec& cell,
+                     bb_nufft* out) {
   *out = nullptr;
-  if (opt && opt->partitions > 1)
-    return part_create(ctx, opt, n_pix, pix_host, pix_xyz, images, workspace, ws_bytes, out);
   bb::NufftGeom g;
-  bb_status st = nufft_geometry(ctx, opt, n_pix, pix_host, g);
+  bb_status st = nufft_geometry(ctx, opt, n_pix, pix_host, g, cell);
   if (st != BB_OK) return st;
-  if (!pix_xyz || !images || !workspace) return fail(ctx, BB_ERR_INVALID_ARG, "null device pointer");
-  if (reinterpret_cast<uintptr_t>(workspace) % bb_host::kAlign)
-    return fail(ctx, BB_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
   const bool line_fft = use_line_fft(g, opt->transform, ctx->device);
   BB_HIP(ctx, hipSetDevice(ctx->device));
   FftPlans plans;
@@ -496,10 +552,6 @@ bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n
     if (work == (size_t)-1) return fail(ctx, BB_ERR_DEVICE, "rocfft_plan_create failed");
   }
   const NufftLayout lay = nufft_layout(g, opt->n_levels, n_pix, work, line_fft);
-  if (ws_bytes < lay.total) {
-    plans.destroy();
-    return fail(ctx, BB_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, lay.total);
-  }
   bb_nufft h = new (std::nothrow) bb_nufft_;
   if (!h) {
     plans.destroy();
@@ -511,7 +563,8 @@ bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n
   h->n_pix = n_pix;
   h->pix = pix_xyz;
   h->images = images;
-  h->ws = static_cast<char*>(workspace);
+  h->tws = tws;
+  h->pws = pws;
   h->lay = lay;
   h->plans = plans;
   h->line_fft = line_fft;
@@ -547,7 +600,7 @@ bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n
   if (!line_fft) {
     if (rocfft_execution_info_create(&h->info) != rocfft_status_success)
       return bail("rocfft_execution_info_create failed");
-    if (work > 0 && rocfft_execution_info_set_work_buffer(h->info, h->ws + lay.work, work) != rocfft_status_success)
+    if (work > 0 && rocfft_execution_info_set_work_buffer(h->info, h->tws + lay.work, work) != rocfft_status_success)
       return bail("rocfft_execution_info_set_work_buffer failed");
     if (rocfft_execution_info_set_stream(h->info, ctx->stream) != rocfft_status_success)
       return bail("rocfft_execution_info_set_stream failed");
@@ -583,28 +636,68 @@ bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n
     }
   hipStream_t s = ctx->stream;
   for (int d = 0; d < 3 && line_fft; ++d)
-    if (hipMemcpyAsync(nat<int>(h, lay.perm[d]), perm[d].data(), 4 * perm[d].size(), hipMemcpyHostToDevice, s) !=
+    if (hipMemcpyAsync(pnat<int>(h, lay.perm[d]), perm[d].data(), 4 * perm[d].size(), hipMemcpyHostToDevice, s) !=
             hipSuccess ||
-        hipMemcpyAsync(nat<float>(h, lay.tw[d]), tw[d].data(), 4 * tw[d].size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        hipMemcpyAsync(pnat<float>(h, lay.tw[d]), tw[d].data(), 4 * tw[d].size(), hipMemcpyHostToDevice, s) != hipSuccess)
       return bail("table upload failed");
   // pageable sources: each copy is staged before the call returns
-  if (hipMemcpyAsync(nat<float>(h, lay.psi0), psi[0].data(), 4 * psi[0].size(), hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(nat<float>(h, lay.psi1), psi[1].data(), 4 * psi[1].size(), hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(nat<float>(h, lay.psi2), psi[2].data(), 4 * psi[2].size(), hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(nat<double>(h, lay.quad_t), qt.data(), 8 * kQuadNodes, hipMemcpyHostToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(nat<double>(h, lay.quad_wphi), wphi.data(), 8 * kQuadNodes, hipMemcpyHostToDevice, s) != hipSuccess)
+  if (hipMemcpyAsync(pnat<float>(h, lay.psi0), psi[0].data(), 4 * psi[0].size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(pnat<float>(h, lay.psi1), psi[1].data(), 4 * psi[1].size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(pnat<float>(h, lay.psi2), psi[2].data(), 4 * psi[2].size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(pnat<double>(h, lay.quad_t), qt.data(), 8 * kQuadNodes, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(pnat<double>(h, lay.quad_wphi), wphi.data(), 8 * kQuadNodes, hipMemcpyHostToDevice, s) != hipSuccess)
     return bail("table upload failed");
-  if (bb::launch_nufft_corr(g, pix_xyz, n_pix, n_pix, nat<double>(h, lay.quad_t), nat<double>(h, lay.quad_wphi),
-                            kQuadNodes, nat<double>(h, lay.corr), s) != hipSuccess ||
-      bb::launch_fill_zero(nat<float>(h, lay.grid), (int64_t)2 * g.N[0] * g.N[1] * g.N[2] * opt->n_levels, s) !=
+  if (bb::launch_nufft_corr(g, pix_xyz, n_pix, n_pix, pnat<double>(h, lay.quad_t), pnat<double>(h, lay.quad_wphi),
+                            kQuadNodes, pnat<double>(h, lay.corr), s) != hipSuccess ||
+      bb::launch_fill_zero(tnat<float>(h, lay.grid), (int64_t)2 * g.N[0] * g.N[1] * g.N[2] * opt->n_levels, s) !=
           hipSuccess ||
-      bb::launch_fill_zero_f64(nat<double>(h, lay.diag), bb::kMaxLevels, s) != hipSuccess ||
-      bb::launch_fill_zero(nat<float>(h, lay.err), 1, s) != hipSuccess)
+      bb::launch_fill_zero_f64(pnat<double>(h, lay.diag), bb::kMaxLevels, s) != hipSuccess ||
+      bb::launch_fill_zero(pnat<float>(h, lay.err), 1, s) != hipSuccess)
     return bail("plan set-up launch failed");
   if (hipStreamSynchronize(s) != hipSuccess) return bail("plan set-up failed on the device");
   ctx->live += 1;
   *out = h;
   return BB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bb_status bb_nufft_workspace_size(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix, const double* pix_host,
+                                  size_t* bytes) {
+  if (!ctx || !bytes) return BB_ERR_INVALID_ARG;
+  if (opt && (opt->partitions > 1 || opt->uvw_partitions > 1)) {
+    PartLayout L;
+    const bb_status st = part_layout(ctx, opt, n_pix, pix_host, L);
+    if (st == BB_OK) *bytes = L.total;
+    return st;
+  }
+  bb::NufftGeom g;
+  bool line_fft = false;
+  NufftLayout lay;
+  const bb_status st = plan_size(ctx, opt, n_pix, pix_host, CellSpec{}, g, line_fft, lay);
+  if (st == BB_OK) *bytes = lay.total;
+  return st;
+}
+
+bb_status bb_nufft_create(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix, const double* pix_host,
+                          const double* pix_xyz, float* images, void* workspace, size_t ws_bytes, bb_nufft* out) {
+  if (!ctx || !out) return BB_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (opt && (opt->partitions > 1 || opt->uvw_partitions > 1))
+    return part_create(ctx, opt, n_pix, pix_host, pix_xyz, images, workspace, ws_bytes, out);
+  bb::NufftGeom g;
+  bool line_fft = false;
+  NufftLayout lay;
+  bb_status st = plan_size(ctx, opt, n_pix, pix_host, CellSpec{}, g, line_fft, lay);
+  if (st != BB_OK) return st;
+  if (!pix_xyz || !images || !workspace) return fail(ctx, BB_ERR_INVALID_ARG, "null device pointer");
+  if (reinterpret_cast<uintptr_t>(workspace) % bb_host::kAlign)
+    return fail(ctx, BB_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < lay.total) return fail(ctx, BB_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, lay.total);
+  char* ws = static_cast<char*>(workspace);
+  return create_one(ctx, opt, n_pix, pix_host, pix_xyz, images, ws, ws + lay.t_total, CellSpec{}, out);
 }
 
 bb_status bb_nufft_shape(bb_nufft h, int32_t* spread_grid, int32_t* fft_grid, int32_t* kernel_width_out) {
@@ -710,13 +803,27 @@ bb_status bb_nufft_collect_eig_batched(bb_nufft h, int32_t n_inst, const bb_inst
   if (!h) return BB_ERR_INVALID_ARG;
   bb_context ctx = h->ctx;
   if (!h->parts.empty()) {
+    // one NUFFT per (tile, uvw cell), one after another on the shared grid:
+    // spread the cell's baselines, transform, interpolate into the tile's
+    // images; then move the tile's images into the plan's
     BB_HIP(ctx, hipSetDevice(ctx->device));
     BB_HIP(ctx, hipEventRecord(h->ev[0], ctx->stream));
     for (NufftPart& q : h->parts) {
-      const bb_status st = bb_nufft_collect_eig_batched(q.sub, n_inst, inst, n_ant_rows, n_w_elems, n_eig_elems,
-                                                        ant_xyz_packed, W_packed, d_packed, level_packed, workspace,
-                                                        ws_bytes);
-      if (st != BB_OK) return st;
+      const bb::NufftGeom& gq = q.sub->g;
+      const int64_t grid_floats = 2 * (int64_t)gq.N[0] * gq.N[1] * gq.N[2] * h->opt.n_levels;
+      for (int iu = 0; iu < h->cells; ++iu)
+        for (int iv = 0; iv < h->cells; ++iv) {
+          if (h->cells > 1) set_cell(q.sub->g, iu, iv);
+          // the other tiles' transform stages share this region: clear the grid first
+          BB_HIP(ctx, bb::launch_fill_zero(tnat<float>(q.sub, q.sub->lay.grid), grid_floats, ctx->stream));
+          bb_status st = bb_nufft_collect_eig_batched(q.sub, n_inst, inst, n_ant_rows, n_w_elems, n_eig_elems,
+                                                      ant_xyz_packed, W_packed, d_packed, level_packed, workspace,
+                                                      ws_bytes);
+          if (st == BB_OK) st = bb_nufft_emit(q.sub);
+          if (st != BB_OK) return st;
+        }
+      BB_HIP(ctx, bb::launch_nufft_scatter_images(q.img, q.n, h->opt.n_levels, q.idx, h->images, h->n_pix,
+                                                  ctx->stream));
     }
     BB_HIP(ctx, hipEventRecord(h->ev[1], ctx->stream));
     h->spread_timed = true;
@@ -770,7 +877,7 @@ bb_status bb_nufft_collect_eig_batched(bb_nufft h, int32_t n_inst, const bb_inst
   // pageable source: the copy is staged before the call returns
   BB_HIP(ctx, hipMemcpyAsync(d_inst, ni.data(), sizeof(bb::NufftInst) * n_inst, hipMemcpyHostToDevice, s));
   BB_HIP(ctx, bb::launch_nufft_prep(d_inst, n_inst, W_packed, d_packed, level_packed, n_levels, d_order, d_lstart,
-                                    nat<double>(h, h->lay.diag), nat<int>(h, h->lay.err), s));
+                                    pnat<double>(h, h->lay.diag), pnat<int>(h, h->lay.err), s));
   const int64_t n_cell = (int64_t)h->g.N[0] * h->g.N[1] * h->g.N[2];
   if (cl.mode > 0) {
     BB_HIP(ctx, bb::launch_nufft_vprime(d_inst, n_inst, max_ant, W_packed, d_packed, d_order, d_lstart, n_levels,
@@ -781,7 +888,7 @@ bb_status bb_nufft_collect_eig_batched(bb_nufft h, int32_t n_inst, const bb_inst
     uint64_t* list = reinterpret_cast<uint64_t*>(ws + cl.list);
     int* scan_tmp = reinterpret_cast<int*>(ws + cl.scan_tmp);
     BB_HIP(ctx, bb::launch_nufft_bin(h->g, d_inst, n_inst, max_ant, ant_xyz_packed, n_ant_rows, cl.bin, count, offset,
-                                     cursor, list, nat<int>(h, h->lay.err), scan_tmp, s));
+                                     cursor, list, pnat<int>(h, h->lay.err), scan_tmp, s));
   }
   if (cl.mode == 2) {
     BB_HIP(ctx, bb::launch_nufft_spread_gather(h->g, d_inst, cl.pairs, ant_xyz_packed, n_ant_rows, ws + cl.vp,
@@ -789,19 +896,19 @@ bb_status bb_nufft_collect_eig_batched(bb_nufft h, int32_t n_inst, const bb_inst
                                                reinterpret_cast<uint64_t*>(ws + cl.list), n_levels, ws + cl.rec,
                                                ws + cl.cv, reinterpret_cast<int*>(ws + cl.nparts),
                                                reinterpret_cast<int*>(ws + cl.part_off),
-                                               reinterpret_cast<int*>(ws + cl.scan_tmp), nat<float>(h, h->lay.grid),
+                                               reinterpret_cast<int*>(ws + cl.scan_tmp), tnat<float>(h, h->lay.grid),
                                                n_cell, s));
   } else if (cl.mode == 1) {
     const int* offset = reinterpret_cast<int*>(ws + cl.offset);
     const uint64_t* list = reinterpret_cast<uint64_t*>(ws + cl.list);
     BB_HIP(ctx, bb::launch_nufft_spread_tiles(h->g, d_inst, ant_xyz_packed, n_ant_rows, ws + cl.vp, offset, list,
                                               cl.bin, n_levels, reinterpret_cast<int*>(ws + cl.nch),
-                                              reinterpret_cast<int*>(ws + cl.choff), nat<float>(h, h->lay.grid), n_cell,
+                                              reinterpret_cast<int*>(ws + cl.choff), tnat<float>(h, h->lay.grid), n_cell,
                                               s));
   } else {
     BB_HIP(ctx, bb::launch_nufft_spread(h->g, d_inst, n_inst, max_ant, ant_xyz_packed, n_ant_rows, W_packed, d_packed,
-                                        d_order, d_lstart, n_levels, nat<float>(h, h->lay.grid), n_cell,
-                                        nat<int>(h, h->lay.err), s));
+                                        d_order, d_lstart, n_levels, tnat<float>(h, h->lay.grid), n_cell,
+                                        pnat<int>(h, h->lay.err), s));
   }
   BB_HIP(ctx, hipEventRecord(h->ev[1], s));
   h->spread_timed = true;
@@ -812,15 +919,9 @@ bb_status bb_nufft_collect_eig_batched(bb_nufft h, int32_t n_inst, const bb_inst
 bb_status bb_nufft_emit(bb_nufft h) {
   if (!h) return BB_ERR_INVALID_ARG;
   bb_context ctx = h->ctx;
-  if (!h->parts.empty()) {
+  if (!h->parts.empty()) {  // each collect call already transformed its instances
     BB_HIP(ctx, hipSetDevice(ctx->device));
     BB_HIP(ctx, hipEventRecord(h->ev[2], ctx->stream));
-    for (NufftPart& q : h->parts) {
-      const bb_status st = bb_nufft_emit(q.sub);
-      if (st != BB_OK) return st;
-      BB_HIP(ctx, bb::launch_nufft_scatter_images(q.img, q.n, h->opt.n_levels, q.idx, h->images, h->n_pix,
-                                                  ctx->stream));
-    }
     BB_HIP(ctx, hipEventRecord(h->ev[3], ctx->stream));
     h->emit_timed = true;
     h->count = 0;
@@ -830,26 +931,26 @@ bb_status bb_nufft_emit(bb_nufft h) {
   hipStream_t s = ctx->stream;
   const bb::NufftGeom& g = h->g;
   const int64_t n_cell = (int64_t)g.N[0] * g.N[1] * g.N[2];
-  void* ac = h->ws + h->lay.stage_ac;
-  void* b = h->ws + h->lay.stage_b;
-  const float* psi[3] = {nat<float>(h, h->lay.psi0), nat<float>(h, h->lay.psi1), nat<float>(h, h->lay.psi2)};
+  void* ac = h->tws + h->lay.stage_ac;
+  void* b = h->tws + h->lay.stage_b;
+  const float* psi[3] = {pnat<float>(h, h->lay.psi0), pnat<float>(h, h->lay.psi1), pnat<float>(h, h->lay.psi2)};
   // the context's stream may have been rebound since the plan was made
   if (!h->line_fft && rocfft_execution_info_set_stream(h->info, s) != rocfft_status_success)
     return fail(ctx, BB_ERR_DEVICE, "rocfft_execution_info_set_stream failed");
   BB_HIP(ctx, hipEventRecord(h->ev[2], s));
   for (int lv = 0; lv < h->opt.n_levels; ++lv) {
-    const float* level_grid = nat<float>(h, h->lay.grid) + 2 * (int64_t)lv * n_cell;
+    const float* level_grid = tnat<float>(h, h->lay.grid) + 2 * (int64_t)lv * n_cell;
     bb::InterpLayout il;
     const void* u;
     if (h->line_fft) {
       // axis 2: grid -> A'; axis 1: A' -> B; B -> B' (transpose); axis 0: B' -> C
       const int64_t w1 = g.win_len[1], w2 = g.win_len[2];
-      BB_HIP(ctx, bb::launch_line_fft(h->lf[0], level_grid, psi[2], nat<int>(h, h->lay.perm[2]),
-                                      nat<float2>(h, h->lay.tw[2]), ac, s));
-      BB_HIP(ctx, bb::launch_line_fft(h->lf[1], ac, psi[1], nat<int>(h, h->lay.perm[1]), nat<float2>(h, h->lay.tw[1]),
+      BB_HIP(ctx, bb::launch_line_fft(h->lf[0], level_grid, psi[2], pnat<int>(h, h->lay.perm[2]),
+                                      pnat<float2>(h, h->lay.tw[2]), ac, s));
+      BB_HIP(ctx, bb::launch_line_fft(h->lf[1], ac, psi[1], pnat<int>(h, h->lay.perm[1]), pnat<float2>(h, h->lay.tw[1]),
                                       b, s));
       BB_HIP(ctx, bb::launch_transpose_c64(b, g.N[0], w2 * w1, ac, s));
-      BB_HIP(ctx, bb::launch_line_fft(h->lf[2], ac, psi[0], nat<int>(h, h->lay.perm[0]), nat<float2>(h, h->lay.tw[0]),
+      BB_HIP(ctx, bb::launch_line_fft(h->lf[2], ac, psi[0], pnat<int>(h, h->lay.perm[0]), pnat<float2>(h, h->lay.tw[0]),
                                       b, s));
       il = {(int64_t)g.win_len[0], w1 * g.win_len[0], g.win_lo[0], g.win_len[0]};
       u = b;
@@ -867,11 +968,11 @@ bb_status bb_nufft_emit(bb_nufft h) {
       u = ac;
     }
     BB_HIP(ctx, bb::launch_nufft_interp(g, il, h->pix, h->n_pix, h->n_pix, static_cast<const float*>(u),
-                                        nat<double>(h, h->lay.corr), nat<double>(h, h->lay.diag), lv,
+                                        pnat<double>(h, h->lay.corr), pnat<double>(h, h->lay.diag), lv,
                                         h->images + (int64_t)lv * h->n_pix, s));
   }
-  BB_HIP(ctx, bb::launch_fill_zero(nat<float>(h, h->lay.grid), 2 * n_cell * h->opt.n_levels, s));
-  BB_HIP(ctx, bb::launch_fill_zero_f64(nat<double>(h, h->lay.diag), bb::kMaxLevels, s));
+  BB_HIP(ctx, bb::launch_fill_zero(tnat<float>(h, h->lay.grid), 2 * n_cell * h->opt.n_levels, s));
+  BB_HIP(ctx, bb::launch_fill_zero_f64(pnat<double>(h, h->lay.diag), bb::kMaxLevels, s));
   BB_HIP(ctx, hipEventRecord(h->ev[3], s));
   h->emit_timed = true;
   h->count = 0;
@@ -892,9 +993,9 @@ bb_status bb_nufft_sync(bb_nufft h) {
   BB_HIP(ctx, hipSetDevice(ctx->device));
   BB_HIP(ctx, hipStreamSynchronize(ctx->stream));
   int err = 0;
-  BB_HIP(ctx, hipMemcpy(&err, nat<int>(h, h->lay.err), sizeof err, hipMemcpyDeviceToHost));
+  BB_HIP(ctx, hipMemcpy(&err, pnat<int>(h, h->lay.err), sizeof err, hipMemcpyDeviceToHost));
   if (err) {
-    BB_HIP(ctx, bb::launch_fill_zero(nat<float>(h, h->lay.err), 1, ctx->stream));
+    BB_HIP(ctx, bb::launch_fill_zero(pnat<float>(h, h->lay.err), 1, ctx->stream));
     BB_HIP(ctx, hipStreamSynchronize(ctx->stream));
     std::string msg;
     if (err & bb::kErrLevelId) msg += "a level id outside [-1, n_levels) was treated as -1; ";

@@ -37,10 +37,12 @@ __device__ __forceinline__ double frame_coord(const NufftGeom& g, int d, double 
   return (a0 * g.R[d][0] + a1 * g.R[d][1]) + a2 * g.R[d][2];
 }
 
-// Baseline (q, r) of an instance in spread-grid units; false (and the error
-// bit) when it lies beyond the planned extent.
-__device__ __forceinline__ bool source_coords(const NufftGeom& g, const NufftInst& I, const double* __restrict__ ant,
-                                              int64_t ld, int q, int r, double (&xi)[3], double& turns_d) {
+// Baseline (q, r) of an instance in spread-grid units of the plan: returns
+// 0 when the plan transforms it, 1 when it lies beyond the planned extent (an
+// error), 2 when it belongs to another uvw cell (shifted by the cell centre
+// when cells are in use).
+__device__ __forceinline__ int source_coords(const NufftGeom& g, const NufftInst& I, const double* __restrict__ ant,
+                                             int64_t ld, int q, int r, double (&xi)[3], double& turns_d) {
   const double* A = ant + I.ant_off;
   double b[3];
   {
@@ -50,10 +52,14 @@ __device__ __forceinline__ bool source_coords(const NufftGeom& g, const NufftIns
     const double d2 = A[q + 2 * ld] - A[r + 2 * ld];
     for (int d = 0; d < 3; ++d) b[d] = frame_coord(g, d, d0, d1, d2) / I.wavelength_m;
   }
-  if (!(fabs(b[0]) <= g.X[0]) || !(fabs(b[1]) <= g.X[1]) || !(fabs(b[2]) <= g.X[2])) return false;
+  if (!(fabs(b[0]) <= g.Xf[0]) || !(fabs(b[1]) <= g.Xf[1]) || !(fabs(b[2]) <= g.Xf[2])) return 1;
+  if (g.cell_q > 1) {
+    if (uvw_cell(b[0], g.Xf[0], g.cell_q) != g.cell_i[0] || uvw_cell(b[1], g.Xf[1], g.cell_q) != g.cell_i[1]) return 2;
+    for (int d = 0; d < 3; ++d) b[d] -= g.C[d];
+  }
   for (int d = 0; d < 3; ++d) xi[d] = b[d] * g.inv_h[d];
   turns_d = b[0] * g.D[0] + b[1] * g.D[1] + b[2] * g.D[2];
-  return true;
+  return 0;
 }
 
 __device__ __forceinline__ int first_cell(double xi, int w, int n) {

@@ -392,11 +392,13 @@ class NufftSynthesis:
     Instances go in with :meth:`collect_eig_batched` (a :class:`Batch` with slot 0
     everywhere); :meth:`emit` transforms what was collected into ``images`` (n_levels, n_pix).
     ``transform``: ``"auto"`` (the library's own line FFTs where every axis fits, else
-    rocFFT) or ``"rocfft"``.  ``partitions``: image-domain tiles per axis (one NUFFT
-    per tile of the field).
+    rocFFT) or ``"rocfft"``.  ``partitions``: image-domain tiles per axis;
+    ``uvw_partitions``: uvw-domain cells per axis (one NUFFT per (tile, cell) pair,
+    one after another on one shared grid; each collect then transforms right away).
     """
 
-    def __init__(self, ctx, pix, n_levels, n_ant_max, k_max, eps, frame, uvw_max, transform="auto", partitions=1):
+    def __init__(self, ctx, pix, n_levels, n_ant_max, k_max, eps, frame, uvw_max, transform="auto", partitions=1,
+                 uvw_partitions=1):
         self.ctx = ctx
         self.lib = ctx.lib
         dev = ctx.device
@@ -406,7 +408,7 @@ class NufftSynthesis:
         self.pix_cm = torch.as_tensor(pix_np).to(dev)
         self.opt = _lib.bb_nufft_options(n_levels=int(n_levels), n_ant_max=int(n_ant_max), k_max=int(k_max),
                                          transform={"auto": 0, "rocfft": 1}[transform], epsilon=float(eps),
-                                         partitions=int(partitions))
+                                         partitions=int(partitions), uvw_partitions=int(uvw_partitions))
         fr = np.asarray(frame, np.float64).reshape(9)
         um = np.asarray(uvw_max, np.float64).reshape(3)
         for i in range(9):

@@ -57,6 +57,31 @@ def test_window_end_on_exact_ties_is_immaterial(eps):
     assert np.max(np.abs(hi - want)) <= bound
 
 
+@pytest.mark.parametrize("q", [2, 3, 5])
+def test_uvw_cells_within_tolerance_of_exact_sum(q):
+    """Splitting the sources into q x q uvw cells (shift by the cell centre,
+    transform, multiply by exp(2 pi i <s, C>)) still meets the tolerance
+    against the exact sum, with every cell's grid smaller than the whole's."""
+    c, x, s = _problem(10)
+    X = np.max(np.abs(x), axis=0) * 1.001
+    eps = 1e-5
+    got = nf.nufft3_uvw_cells(c, x, s, eps, X, q)[:, 0]
+    want = nf.nudft3(c, x, s)
+    assert np.max(np.abs(got - want)) <= eps * np.sum(np.abs(c))
+    whole = nf.plan_params(eps, X, s)["N"]
+    Xc = X.copy()
+    Xc[:2] = X[:2] / q * (1 + 1e-9)
+    part = nf.plan_params(eps, Xc, s)["N"]
+    assert part[0] < whole[0] and part[1] < whole[1] and part[2] == whole[2]
+
+
+def test_uvw_cell_rule():
+    X, q = 10.0, 4
+    b = np.array([-10.0, -5.0 - 1e-9, -5.0, -0.0, 0.0, 4.999999, 5.0, 9.9, 10.0])
+    assert list(nf.uvw_cell(b, X, q)) == [0, 0, 1, 2, 2, 2, 3, 3, 3]
+    assert [nf.uvw_cell_centre(i, X, q) for i in range(q)] == [-7.5, -2.5, 2.5, 7.5]
+
+
 def test_nudft3_is_the_sum():
     c, x, s = _problem(2, 7, 5)
     brute = np.array([sum(c[j] * np.exp(2j * np.pi * np.dot(s[k], x[j])) for j in range(7)) for k in range(5)])
