@@ -35,6 +35,15 @@
  *    bb_synth_sync.  No C++ exception crosses this interface.
  *  - Calls on one handle, or on handles sharing a context, must not be made
  *    concurrently from several host threads.
+ *  - Checkpoint / resume: the accumulated images and the instance count
+ *    (bb_synth_get_count / bb_synth_set_count) are the whole state of a run;
+ *    a handle created over restored images, with the count set, continues it
+ *    bitwise (standard synthesis adds in a fixed order, with no atomics).
+ *  - Debug aid: with the environment variable BB_DEBUG_FILL set to a value
+ *    other than "0", every workspace handed to the library is filled with
+ *    0xFF bytes (NaN as float32 / float64) before use, at handle or plan
+ *    creation and at each call that takes a workspace, so that a read of
+ *    unwritten workspace memory shows in the results.
  */
 #ifndef BLUEBILD_H
 #define BLUEBILD_H

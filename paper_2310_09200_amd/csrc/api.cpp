@@ -366,6 +366,11 @@ bb_status bb_synth_create(bb_context ctx, const bb_options* opt, int64_t n_pix, 
       delete h;
       return fail(ctx, BB_ERR_DEVICE, "hipEventCreate failed");
     }
+  if (bb_host::debug_fill() && bb::launch_fill_poison(h->ws, lay.total, ctx->stream) != hipSuccess) {
+    for (auto& e : h->ev) (void)hipEventDestroy(e);
+    delete h;
+    return fail(ctx, BB_ERR_DEVICE, "launch failed");
+  }
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, ctx->stream, at<int>(h, h->lay.err));
   if (hipGetLastError() != hipSuccess) {
     for (auto& e : h->ev) (void)hipEventDestroy(e);
@@ -773,6 +778,7 @@ bb_status bb_synth_prestep_batched(bb_synth h, int32_t n_inst, int32_t n_ant, in
   if (ws_bytes < B.total) return fail(ctx, BB_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, B.total);
   char* ws = static_cast<char*>(workspace);
   hipStream_t s = ctx->stream;
+  if (bb_host::debug_fill()) BB_HIP(ctx, bb::launch_fill_poison(ws, B.total, s));
   BB_HIP(ctx, hipEventRecord(h->ev[0], s));
   // pageable source: the copy is staged before the call returns
   BB_HIP(ctx, hipMemcpyAsync(ws + B.inv_wl, inv_wl.data(), sizeof(double) * n_inst, hipMemcpyHostToDevice, s));
@@ -1065,6 +1071,7 @@ bb_status bb_synth_collect_eig_batched(bb_synth h, int32_t n_inst, const bb_inst
   char* ws = static_cast<char*>(workspace);
   batch_descs(h, inst, n_inst, n_ant_rows, ant_xyz_packed, W_packed, d_packed, level_packed, ws, bp);
   hipStream_t s = ctx->stream;
+  if (bb_host::debug_fill()) BB_HIP(ctx, bb::launch_fill_poison(ws, bp.total, s));
   BB_HIP(ctx, hipEventRecord(h->ev[0], s));
   BB_HIP(ctx, hipEventRecord(h->ev[1], s));
   st = upload_plan(ctx, bp, ws, n_inst, true);
@@ -1139,6 +1146,7 @@ bb_status bb_synth_autotune_batched(bb_synth h, int32_t n_inst, const bb_instanc
   hipStream_t s = ctx->stream;
   char* ws = static_cast<char*>(workspace);
   batch_descs(h, inst, n_inst, n_ant_rows, ant_xyz_packed, W_packed, d_packed, level_packed, ws, full);
+  if (bb_host::debug_fill()) BB_HIP(ctx, bb::launch_fill_poison(ws, full.total, s));
   st = upload_plan(ctx, full, ws, n_inst, true);
   if (st != BB_OK) return st;
   BB_HIP(ctx, bb::launch_stage(reinterpret_cast<InstDesc*>(ws + full.off_descs),
@@ -1247,6 +1255,7 @@ bb_status bb_synth_eig_backward(bb_synth h, int32_t n_ant, int32_t n_eig, double
   BB_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   char* ws = static_cast<char*>(workspace);
+  if (bb_host::debug_fill()) BB_HIP(ctx, bb::launch_fill_poison(ws, bp.total, s));
   InstDesc dsc = staging_desc(h, h->ws + h->lay.apack, n_ant, n_eig, wavelength_m, 0);
   dsc.ant = ant_xyz;
   dsc.ant_ld = n_ant;

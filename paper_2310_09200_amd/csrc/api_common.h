@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <string>
 
 #include "bluebild.h"
@@ -41,6 +42,15 @@ inline bb_status fail(bb_context ctx, bb_status s, const char* fmt, ...) {
 }
 
 inline bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Debug aid: with BB_DEBUG_FILL set (and not "0") in the environment, the
+// library fills every workspace it is given with 0xFF bytes (a NaN in float32
+// and float64, -1 in integers) before using it, so that a read of workspace
+// memory that no kernel wrote shows up in the results.
+inline bool debug_fill() {
+  const char* v = std::getenv("BB_DEBUG_FILL");
+  return v && v[0] && !(v[0] == '0' && v[1] == 0);
+}
 
 }  // namespace bb_host
 

@@ -97,6 +97,8 @@ int synth_tile_pixels(int max_K_alloc, int precision);
 
 // Zero-fill of a float buffer (graph-capture safe, no memset nodes).
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
+// Fill n bytes with 0xFF (the workspace poison of BB_DEBUG_FILL).
+hipError_t launch_fill_poison(void* p, size_t n, hipStream_t s);
 hipError_t launch_phase_probe(const double* ant, int n_ant, double inv_wl, const double* pix, int64_t n_pix, int reps,
                               float* out, hipStream_t s);
 

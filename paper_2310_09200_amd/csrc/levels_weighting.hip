@@ -278,4 +278,18 @@ hipError_t launch_uniform_weighting(const double* ant, int64_t ld, int L, const 
   return hipGetLastError();
 }
 
+// Byte fill with 0xFF: the workspace poison of the BB_DEBUG_FILL debug mode.
+__global__ void fill_poison_kernel(unsigned char* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0xFF;
+}
+
+hipError_t launch_fill_poison(void* p, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(fill_poison_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (unsigned char*)p, n);
+  return hipGetLastError();
+}
+
 }  // namespace bb

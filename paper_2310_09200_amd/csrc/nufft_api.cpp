@@ -635,6 +635,9 @@ bb_status create_one(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix,
       bb::line_fft_twiddles(h->lf[2 - d], tw[d].data());
     }
   hipStream_t s = ctx->stream;
+  if (bb_host::debug_fill() && (bb::launch_fill_poison(h->tws, lay.t_total, s) != hipSuccess ||
+                                bb::launch_fill_poison(h->pws, lay.p_total, s) != hipSuccess))
+    return bail("debug fill failed");
   for (int d = 0; d < 3 && line_fft; ++d)
     if (hipMemcpyAsync(pnat<int>(h, lay.perm[d]), perm[d].data(), 4 * perm[d].size(), hipMemcpyHostToDevice, s) !=
             hipSuccess ||
@@ -873,6 +876,7 @@ bb_status bb_nufft_collect_eig_batched(bb_nufft h, int32_t n_inst, const bb_inst
   int* d_lstart = reinterpret_cast<int*>(ws + cl.lstart);
   BB_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
+  if (bb_host::debug_fill()) BB_HIP(ctx, bb::launch_fill_poison(ws, cl.total, s));
   BB_HIP(ctx, hipEventRecord(h->ev[0], s));
   // pageable source: the copy is staged before the call returns
   BB_HIP(ctx, hipMemcpyAsync(d_inst, ni.data(), sizeof(bb::NufftInst) * n_inst, hipMemcpyHostToDevice, s));
