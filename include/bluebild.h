@@ -328,7 +328,7 @@ bb_status bb_synth_collect_eig_noalloc(bb_context ctx, int32_t precision, int32_
  *   BB_MAX_TILES doubles, row per class: mean milliseconds per launch, -1 where
  *   not timed).  Waits for the device. */
 #define BB_K_CLASSES 4
-#define BB_MAX_TILES 8
+#define BB_MAX_TILES 12
 bb_status bb_tile_info(int32_t precision, int32_t tile, int32_t* eig_per_pass, int32_t* pix_per_tile, int32_t* waves,
                        int32_t* class_mask);
 bb_status bb_synth_get_tiles(bb_synth h, int32_t* tiles);

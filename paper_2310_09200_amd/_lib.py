@@ -23,7 +23,7 @@ BB_OK, BB_ERR_INVALID_ARG, BB_ERR_SHAPE, BB_ERR_NOT_POSDEF, BB_ERR_EIGEN, BB_ERR
 BB_PREC_FP32, BB_PREC_BF16X3, BB_PREC_FP32_3M, BB_PREC_BF16X3_3M = 0, 1, 2, 3
 BB_FILTER_LSQ, BB_FILTER_STD = 0, 1
 BB_GRAM_SINC, BB_GRAM_IDENTITY = 0, 1
-BB_K_CLASSES, BB_MAX_TILES = 4, 8
+BB_K_CLASSES, BB_MAX_TILES = 4, 12
 
 
 class bb_options(ctypes.Structure):

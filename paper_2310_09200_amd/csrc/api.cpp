@@ -56,7 +56,7 @@ size_t staging_bytes(int L_pad, int K_alloc, size_t* off_xs = nullptr, size_t* o
   if (off_levs) *off_levs = o;
   o += align_up((size_t)K_alloc * 4);
   if (off_kbr) *off_kbr = o;
-  o += align_up((size_t)(K_alloc / 32) * 8);
+  o += align_up((size_t)(K_alloc / 32 + K_alloc / 16) * 8);
   if (off_perm) *off_perm = o;
   o += align_up((size_t)K_alloc * 4);
   return o;
@@ -204,7 +204,12 @@ bb_status launch_single(bb_context ctx, SingleMeta* meta, int* err, const InstDe
                         int64_t n_pix, float* images, int n_levels, int precision, int tile, hipEvent_t ev_staged,
                         hipEvent_t ev_done) {
   hipStream_t s = ctx->stream;
-  hipLaunchKernelGGL(write_meta_kernel, dim3(1), dim3(1), 0, s, meta, d, d.slot);
+  int nt = 0;
+  if (!bb::synth_tile_info(precision, tile, nullptr, &nt, nullptr))
+    return fail(ctx, BB_ERR_INVALID_ARG, "unknown tile %d", tile);
+  InstDesc dd = d;
+  dd.rows16 = bb::synth_tile_rows(precision, tile) == 16 ? 1 : 0;  // operand order of the tile
+  hipLaunchKernelGGL(write_meta_kernel, dim3(1), dim3(1), 0, s, meta, dd, dd.slot);
   BB_HIP(ctx, hipGetLastError());
   BB_HIP(ctx, bb::launch_stage(&meta->desc, &meta->dyn, 1, d.K_alloc, d.L_pad, n_levels, precision, err, s));
   if (ev_staged) BB_HIP(ctx, hipEventRecord(ev_staged, s));
@@ -220,9 +225,6 @@ bb_status launch_single(bb_context ctx, SingleMeta* meta, int* err, const InstDe
   p.img = images;
   p.img_ld = n_pix;
   p.n_levels = n_levels;
-  int nt = 0;
-  if (!bb::synth_tile_info(precision, tile, nullptr, &nt, nullptr))
-    return fail(ctx, BB_ERR_INVALID_ARG, "unknown tile %d", tile);
   p.n_tiles = (n_pix + nt - 1) / nt;
   p.n_groups = 1;
   BB_HIP(ctx, bb::launch_synth_tile(p, precision, tile, s));
@@ -973,9 +975,10 @@ bb_status plan_batch(bb_synth h, int32_t n_inst, const bb_instance* inst, int64_
   return BB_OK;
 }
 
-// Descriptors of every instance of a planned batch, their staging regions in `ws`.
+// Descriptors of every instance of a planned batch, their staging regions in
+// `ws`, each staged in the operand order of its K class's tile in `tiles`.
 void batch_descs(bb_synth h, const bb_instance* inst, int32_t n_inst, int64_t n_ant_rows, const double* ant,
-                 const void* W, const float* d, const int32_t* lev, char* ws, BatchPlan& bp) {
+                 const void* W, const float* d, const int32_t* lev, char* ws, const int* tiles, BatchPlan& bp) {
   size_t stage = bp.off_stage;
   bp.descs.resize(n_inst);
   for (int i = 0; i < n_inst; ++i) {
@@ -990,6 +993,7 @@ void batch_descs(bb_synth h, const bb_instance* inst, int32_t n_inst, int64_t n_
     dd.wcol = nullptr;
     dd.d = d + b.eig_off;
     dd.lev_in = lev + b.eig_off;
+    dd.rows16 = bb::synth_tile_rows(h->opt.precision, tiles[bb::synth_k_class(dd.K_alloc)]) == 16 ? 1 : 0;
     bp.descs[i] = dd;
   }
 }
@@ -1069,7 +1073,7 @@ bb_status bb_synth_collect_eig_batched(bb_synth h, int32_t n_inst, const bb_inst
   if (ws_bytes < bp.total) return fail(ctx, BB_ERR_WORKSPACE, "workspace %zu < required %zu", ws_bytes, bp.total);
   BB_HIP(ctx, hipSetDevice(ctx->device));
   char* ws = static_cast<char*>(workspace);
-  batch_descs(h, inst, n_inst, n_ant_rows, ant_xyz_packed, W_packed, d_packed, level_packed, ws, bp);
+  batch_descs(h, inst, n_inst, n_ant_rows, ant_xyz_packed, W_packed, d_packed, level_packed, ws, h->tiles, bp);
   hipStream_t s = ctx->stream;
   if (bb_host::debug_fill()) BB_HIP(ctx, bb::launch_fill_poison(ws, bp.total, s));
   BB_HIP(ctx, hipEventRecord(h->ev[0], s));
@@ -1145,7 +1149,7 @@ bb_status bb_synth_autotune_batched(bb_synth h, int32_t n_inst, const bb_instanc
   BB_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   char* ws = static_cast<char*>(workspace);
-  batch_descs(h, inst, n_inst, n_ant_rows, ant_xyz_packed, W_packed, d_packed, level_packed, ws, full);
+  batch_descs(h, inst, n_inst, n_ant_rows, ant_xyz_packed, W_packed, d_packed, level_packed, ws, h->tiles, full);
   if (bb_host::debug_fill()) BB_HIP(ctx, bb::launch_fill_poison(ws, full.total, s));
   st = upload_plan(ctx, full, ws, n_inst, true);
   if (st != BB_OK) return st;
@@ -1168,9 +1172,21 @@ bb_status bb_synth_autotune_batched(bb_synth h, int32_t n_inst, const bb_instanc
       BatchPlan bp;
       st = plan_batch(h, n_inst, inst, n_ant_rows, n_w_elems, n_eig_elems, tiles, c, bp);
       if (st != BB_OK) return st;
+      // restage this class's instances when the tile takes the other operand order
+      const int rows16 = bb::synth_tile_rows(h->opt.precision, t) == 16 ? 1 : 0;
+      bool restage = false;
+      for (int i = 0; i < n_inst; ++i)
+        if (bb::synth_k_class(full.descs[i].K_alloc) == c && full.descs[i].rows16 != rows16) {
+          full.descs[i].rows16 = rows16;
+          restage = true;
+        }
       bp.descs = full.descs;
-      st = upload_plan(ctx, bp, ws, n_inst, false);
+      st = upload_plan(ctx, bp, ws, n_inst, restage);
       if (st != BB_OK) return st;
+      if (restage)
+        BB_HIP(ctx, bb::launch_stage(reinterpret_cast<InstDesc*>(ws + full.off_descs),
+                                     reinterpret_cast<InstDyn*>(ws + full.off_dyn), n_inst, full.max_K_alloc,
+                                     full.max_L_pad, h->opt.n_levels, h->opt.precision, at<int>(h, h->lay.err), s));
       st = launch_buckets(h, bp, ws, scratch_images);  // warm-up
       if (st != BB_OK) return st;
       BB_HIP(ctx, hipEventRecord(h->ev[0], s));

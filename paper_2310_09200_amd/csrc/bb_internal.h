@@ -40,13 +40,16 @@ struct InstDesc {
   const int* lev_in;     // level id per eigenpair, -1 = unused
   double scale;          // 1 / wavelength: positions in turns per unit direction
   int L, K, L_pad, K_alloc;
-  int slot, W_c128, pad0, pad1;
+  int slot, W_c128;
+  int rows16;            // staged operand order: 1 = 16-row blocks (tiles on 16x16x4 MFMAs), 0 = 32-row
+  int pad1;
   // workspace regions owned by this instance
   void* apack;           // packed real-embedded W^H, MFMA operand order
   double* xs;            // [L_pad][4] scaled positions
   float* wts;            // [K_alloc] weights after level sort (0 beyond K_eff)
   int* levs;             // [K_alloc] level ids after sort (-1 beyond K_eff)
-  int2* kbr;             // [K_alloc/32] (lowest, highest) level of each 32-block
+  int2* kbr;             // [K_alloc/32] (lowest, highest) level of each 32-block, then
+                         // [K_alloc/16] the same for each 16-block
   int* perm;             // [K_alloc] source eigenpair of each sorted position (-1 = pad)
 };
 
@@ -89,6 +92,9 @@ int synth_default_tile(int precision, int k_class);
 bool synth_tile_info(int precision, int id, int* kc, int* nt, int* waves);
 // Whether a class may use a tile (its eigenpairs per pass do not exceed the class's largest K).
 bool synth_tile_allowed(int precision, int id, int k_class);
+// Rows of a tile's eigenpair blocks (32, or 16 for tiles on 16x16x4 MFMAs); the
+// instances a tile runs must be staged in that order (InstDesc::rows16).
+int synth_tile_rows(int precision, int id);
 hipError_t launch_synth_tile(const FwdParams& p, int precision, int id, hipStream_t s);
 // The default tile for the largest K_alloc of the call.
 hipError_t launch_synth(const FwdParams& p, int max_K_alloc, int precision, int tile_pixels_out[1],

@@ -25,12 +25,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "bb_internal.h"
 
 namespace bb {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -113,12 +116,15 @@ __global__ __launch_bounds__(256) void stage_meta_kernel(const InstDesc* __restr
     D.levs[pos] = -1;
   }
   __syncthreads();
-  // level range of each 32-block of sorted positions (levels are non-decreasing)
-  for (int kb = tid; kb < D.K_alloc / 32; kb += blockDim.x) {
+  // level range of each 32-block, then of each 16-block, of sorted positions
+  // (levels are non-decreasing; (1, 0) for a block with no kept eigenpair)
+  const int nb32 = D.K_alloc / 32;
+  for (int i = tid; i < nb32 + D.K_alloc / 16; i += blockDim.x) {
+    const int rows = i < nb32 ? 32 : 16;
+    const int p0 = (i < nb32 ? i : i - nb32) * rows;
     int lo = 1, hi = 0;
-    const int p0 = kb * 32;
     if (p0 < K_eff) {
-      const int p1 = min(p0 + 31, K_eff - 1);
+      const int p1 = min(p0 + rows - 1, K_eff - 1);
       // sorted positions: find their levels through the base offsets
       int l0 = 0, l1 = 0;
       for (int l = 0; l < n_levels; ++l) {
@@ -128,7 +134,7 @@ __global__ __launch_bounds__(256) void stage_meta_kernel(const InstDesc* __restr
       lo = l0;
       hi = l1;
     }
-    D.kbr[kb] = make_int2(lo, hi);
+    D.kbr[i] = make_int2(lo, hi);
   }
   for (int l = tid; l < D.L_pad; l += blockDim.x) {
     double v0 = 0.0, v1 = 0.0, v2 = 0.0;
@@ -221,27 +227,52 @@ __global__ __launch_bounds__(256) void stage_pack_bf16_kernel(const InstDesc* __
 
 // Staging, part 2, FP32 with three real products per complex product (Gauss):
 // conj(W) B = (k1 - k3) + j (k1 + k2) with k1 = (Wr - Wi) Br, k2 = Wr (Bi - Br),
-// k3 = -Wi (Br + Bi).  Three planes (Wr - Wi, Wr, -Wi); 32x32x2 operand order
-// with the two contraction rows of an MFMA step being two antennas:
-// lane = row + 32 * (antenna parity), float4 = 4 steps = 8 antennas.
+// k3 = -Wi (Br + Bi).  Three planes (Wr - Wi, Wr, -Wi), 12 bytes per
+// (eigenpair, antenna) in either operand order:
+//  - 32-row blocks (32x32x2 operands, the two contraction rows of an MFMA step
+//    being two antennas): lane = row + 32 * (antenna parity), float4 = 4 steps
+//    = 8 antennas, vectors ordered (32-block, plane, 8-antenna group, lane);
+//  - 16-row blocks (16x16x4 operands, four antennas per step): lane = row +
+//    16 * (antenna mod 4), float2 = 2 steps = 8 antennas, vectors ordered
+//    (16-block, 8-antenna group, plane, lane).
 __global__ __launch_bounds__(256) void stage_pack_f32g_kernel(const InstDesc* __restrict__ descs) {
   const InstDesc D = descs[blockIdx.y];
-  const int G8 = D.L_pad / 8;
-  const int64_t total = (int64_t)(D.K_alloc / 32) * 3 * G8 * 64;
+  const int64_t total = (int64_t)D.K_alloc * 3 * D.L_pad / 4;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
   const int lane = (int)(idx % 64);
   int64_t rest = idx / 64;
+  if (D.rows16) {  // two float2 vectors: 8-antenna groups 2 gg and 2 gg + 1
+    const int q = (int)(rest % 3);
+    rest /= 3;
+    const int G16 = D.L_pad / 16;
+    const int gg = (int)(rest % G16);
+    const int blk = (int)(rest / G16);
+    const int k = blk * 16 + (lane & 15);
+    const int src = D.perm[k];
+    for (int h = 0; h < 2; ++h) {
+      const int g8 = 2 * gg + h;
+      f32x2 out;
+      for (int s = 0; s < 2; ++s) {
+        const int l = 8 * g8 + 4 * s + (lane >> 4);
+        float wr = 0.0f, wi = 0.0f;
+        if (src >= 0 && l < D.L) load_w(D, l, D.wcol ? D.wcol[src] : src, wr, wi);
+        out[s] = q == 0 ? wr - wi : (q == 1 ? wr : -wi);
+      }
+      ((f32x2*)D.apack)[(((int64_t)blk * (D.L_pad / 8) + g8) * 3 + q) * 64 + lane] = out;
+    }
+    return;
+  }
+  const int G8 = D.L_pad / 8;
   const int g = (int)(rest % G8);
   rest /= G8;
   const int q = (int)(rest % 3);
   const int kb = (int)(rest / 3);
   const int k = kb * 32 + (lane & 31);
-  const int h = lane >> 5;
   const int src = D.perm[k];
   f32x4 out;
   for (int s = 0; s < 4; ++s) {
-    const int l = 8 * g + 2 * s + h;
+    const int l = 8 * g + 2 * s + (lane >> 5);
     float wr = 0.0f, wi = 0.0f;
     if (src >= 0 && l < D.L) load_w(D, l, D.wcol ? D.wcol[src] : src, wr, wi);
     out[s] = q == 0 ? wr - wi : (q == 1 ? wr : -wi);
@@ -315,6 +346,7 @@ hipError_t launch_stage(const InstDesc* d_descs, InstDyn* d_dyn, int n_inst, int
 //   WK x WN: waves along k and along pixels.
 template <int MB, int NB, int WK, int WN>
 struct TileCfg {
+  static constexpr int ROWS = 32;
   static constexpr int WAVES = WK * WN;
   static constexpr int THREADS = 64 * WAVES;
   static constexpr int KC = 32 * MB * WK;      // eigenpairs per pass
@@ -772,6 +804,279 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
   }
 }
 
+// ---------------------------------------------------------------------------
+// Tiles of 16-row eigenpair blocks for the three-product FP32 form, on
+// v_mfma_f32_16x16x4f32 (the same matrix rate as 32x32x2): kept eigenpairs are
+// padded to 16 rather than 32, which is what small K loses most to.
+//   MR x NP: 16x16 output blocks per wave (eigenpair blocks x pixel blocks);
+//   WK x WN: waves along eigenpairs and along pixels.  Eigenpair block m of
+//   k-group wk in pass p is block p * MR * WK + m * WK + wk (interleaved), so the
+//   blocks that exist at a given K fall evenly on the k-groups, and with WN a
+//   multiple of 4 each SIMD holds one wave of every k-group.
+// MFMA operand order (64 lanes): A lane l = row l % 16 of antenna l / 16 of the
+// step, B lane l = pixel l % 16 of antenna l / 16; result register r of lane l
+// = row 4 (l / 16) + r, pixel l % 16.  Operand vectors are float2 (two steps,
+// 8 antennas): a group of MFMAs covers 8 antennas, which keeps the A operand
+// and its prefetch within the register budget of two waves per SIMD.
+template <int MR, int NP, int WK, int WN>
+struct Tile16 {
+  static constexpr int ROWS = 16;
+  static constexpr int WAVES = WK * WN;
+  static constexpr int THREADS = 64 * WAVES;
+  static constexpr int KC = 16 * MR * WK;       // eigenpairs per pass
+  static constexpr int NT = 16 * NP * WN;       // pixels per tile
+  static constexpr int NPB = NT / 16;           // 16-pixel blocks per tile
+  static constexpr int LCH = 32;                // antennas per LDS chunk
+  static constexpr int NG = LCH / 8;            // MFMA groups (2 steps of 4 antennas) per chunk
+  static constexpr int TASKS = NT * (LCH / 4);  // (pixel, 4-antenna) phase tasks per chunk
+  static constexpr int JT = TASKS / THREADS;
+  static constexpr int CHUNK_VEC = 3 * LCH * NT / 2;  // float2 vectors per chunk buffer
+  static constexpr int PPG = 4 * JT / NG;       // phase pairs per MFMA group
+  static_assert(WN % 4 == 0, "every SIMD holds one wave of each k-group");
+  static_assert(THREADS % NT == 0, "a thread keeps one pixel");
+  static_assert(JT >= 1 && TASKS % THREADS == 0, "whole tasks per thread");
+  static_assert(PPG * NG == 4 * JT, "pairs split evenly over the groups");
+  static_assert(kAntChunk % LCH == 0, "antenna padding covers the chunk");
+};
+
+// Task j of a thread: pixel (tid + j THREADS) mod NT and antenna group
+// gk = t / NT = 2 g8 + h; its four pairs are antennas 8 g8 + 4 s + kk for
+// s = 0, 1 and kk = 2 h, 2 h + 1: two float2 operand vectors.
+template <class C>
+__device__ __forceinline__ int gen_antenna16(int gk, int q) {
+  return 8 * (gk >> 1) + 4 * (q & 1) + 2 * (gk & 1) + ((q >> 1) & 1);
+}
+
+template <class C>
+__device__ __forceinline__ void gen_pairs16(float (&cr)[4 * C::JT], float (&ci)[4 * C::JT],
+                                            const BB_LDS double* __restrict__ xs_chunk, double px, double py,
+                                            double pz, int tid, int first, int count) {
+#pragma unroll
+  for (int q = 0; q < 4 * C::JT; ++q)
+    if (q >= first && q < first + count)
+      phase_pair(xs_chunk + 4 * gen_antenna16<C>(gen_group<C>(tid, q >> 2), q & 3), px, py, pz, cr[q], ci[q]);
+}
+
+// B planes Br, Bi - Br, Br + Bi of this thread's tasks into the chunk buffer,
+// float2 vectors ordered (8-antenna group, plane, pixel block, lane).
+template <class C>
+__device__ __forceinline__ void gen_store16(f32x2* __restrict__ buf, const float (&pr)[4 * C::JT],
+                                            const float (&pi)[4 * C::JT], int tid) {
+#pragma unroll
+  for (int j = 0; j < C::JT; ++j) {
+    const int pl = (tid + j * C::THREADS) % C::NT;
+    const int gk = gen_group<C>(tid, j);
+    const int g8 = gk >> 1, h = gk & 1;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {  // kk = 2 h + e: pairs 2 e (s = 0) and 2 e + 1 (s = 1)
+      const int o = (g8 * 3 * C::NPB + (pl >> 4)) * 64 + (2 * h + e) * 16 + (pl & 15);
+      const float r0 = pr[4 * j + 2 * e], r1 = pr[4 * j + 2 * e + 1];
+      const float i0 = pi[4 * j + 2 * e], i1 = pi[4 * j + 2 * e + 1];
+      buf[o] = f32x2{r0, r1};
+      buf[o + C::NPB * 64] = f32x2{i0 - r0, i1 - r1};
+      buf[o + 2 * C::NPB * 64] = f32x2{r0 + i0, r1 + i1};
+    }
+  }
+}
+
+template <int NV>
+struct AFrag16 {  // three planes of NV eigenpair blocks, 8 antennas
+  f32x2 v[3][NV];
+};
+
+// A operand of group g of chunk c for NV blocks: block m's vectors start at
+// a_base + m * a_mstep (wave-uniform, so the address stays scalar and each
+// lane adds only its own offset), 8-antenna groups 3 x 64 vectors apart.
+template <class C, int NV>
+__device__ __forceinline__ void load_a16(AFrag16<NV>& a, const BB_GLOBAL f32x2* a_base, int64_t a_mstep, int c,
+                                         int g, int lane) {
+#pragma unroll
+  for (int m = 0; m < NV; ++m) {
+    const BB_GLOBAL f32x2* const blk = a_base + (m * a_mstep + (int64_t)(c * C::NG + g) * 3 * 64);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) a.v[q][m] = blk[lane + q * 64];
+  }
+}
+
+template <class C, int MR, int NP, int NV>
+__device__ __forceinline__ void mma_group16(f32x4 (&acc)[3][MR][NP], const AFrag16<NV>& a,
+                                            const f32x2* __restrict__ buf, int g, int pb0, int lane) {
+  f32x2 b[3][NP];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int n = 0; n < NP; ++n) b[q][n] = buf[((g * 3 + q) * C::NPB + pb0 + n) * 64 + lane];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int m = 0; m < NV; ++m)
+#pragma unroll
+      for (int n = 0; n < NP; ++n)
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          acc[q][m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[q][m][s], b[q][n][s], acc[q][m][n], 0, 0, 0);
+}
+
+template <int MR, int NP, int WK, int WN>
+__global__ __launch_bounds__(64 * WK * WN) void synth_fwd16_kernel(const FwdParams P) {
+  using C = Tile16<MR, NP, WK, WN>;
+  __shared__ f32x2 s_buf[2][C::CHUNK_VEC];
+  __shared__ float s_part[WK][kMaxLevels][C::NT];
+  __shared__ __align__(16) double s_xs[4 * kMaxAnt];
+  const BB_LDS double* const xs = (const BB_LDS double*)s_xs;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wk = __builtin_amdgcn_readfirstlane(wave / WN);
+  const int pb0 = __builtin_amdgcn_readfirstlane((wave % WN) * NP);
+  const int n_levels = P.n_levels;
+
+  // persistent grid over pixel tiles; groups and instances in the same order
+  // in every workgroup; one writer per image tile (as synth_fwd_kernel)
+  for (int grp = 0; grp < P.n_groups; ++grp) {
+    const int slot = __builtin_amdgcn_readfirstlane(P.group_slot[grp]);
+    for (int ii = P.group_begin[grp]; ii < P.group_begin[grp + 1]; ++ii) {
+      const int inst = __builtin_amdgcn_readfirstlane(P.inst_list[ii]);
+      const InstDesc& Dg = P.descs[inst];
+      const void* const apack = Dg.apack;
+      const BB_GLOBAL double* const xs_g = as_global<double>(Dg.xs);
+      const BB_GLOBAL float* const wts = as_global<float>(Dg.wts);
+      const BB_GLOBAL int* const levs = as_global<int>(Dg.levs);
+      const int K_alloc = __builtin_amdgcn_readfirstlane(Dg.K_alloc);
+      const BB_GLOBAL int* const kbr16 = as_global<int>(Dg.kbr) + 2 * (K_alloc / 32);
+      const int nb16 = __builtin_amdgcn_readfirstlane((P.dyn[inst].K_eff + 15) / 16);
+      const int L_pad = __builtin_amdgcn_readfirstlane(Dg.L_pad);
+      const int n_chunks = L_pad / C::LCH;
+      const int n_pass = (nb16 * 16 + C::KC - 1) / C::KC;
+      const int64_t a_blk_vec = (int64_t)(L_pad / 8) * 3 * 64;  // float2 vectors per 16-block
+      if (blockIdx.x < P.n_tiles) {
+        __syncthreads();
+        for (int i = tid; i < 2 * L_pad; i += C::THREADS) ((f64x2*)s_xs)[i] = ((const BB_GLOBAL f64x2*)xs_g)[i];
+        __syncthreads();
+      }
+      for (int64_t tile = blockIdx.x; tile < P.n_tiles; tile += gridDim.x) {
+        const int64_t p0 = tile * C::NT;
+        for (int i = tid; i < WK * kMaxLevels * C::NT; i += C::THREADS) (&s_part[0][0][0])[i] = 0.0f;
+        int64_t pg = p0 + (tid % C::NT);
+        if (pg >= P.n_pix) pg = P.n_pix - 1;
+        const double px = P.pix[pg], py = P.pix[pg + P.pix_ld], pz = P.pix[pg + 2 * P.pix_ld];
+        for (int pass = 0; pass < n_pass; ++pass) {
+          const int b0 = pass * MR * WK + wk;  // this wave's first block; block m is b0 + m WK
+          int nv = nb16 > b0 ? (nb16 - b0 + WK - 1) / WK : 0;
+          nv = __builtin_amdgcn_readfirstlane(nv < MR ? nv : MR);
+          f32x4 acc[3][MR][NP];
+#pragma unroll
+          for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int m = 0; m < MR; ++m)
+#pragma unroll
+              for (int n = 0; n < NP; ++n) acc[q][m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+          // the chunk loop for NV existing blocks of this wave (NV = 0: phases only)
+          auto chunks = [&](auto nv_c) {
+            constexpr int NV = decltype(nv_c)::value;
+            const BB_GLOBAL f32x2* const a_base = as_global<f32x2>(apack) + (int64_t)b0 * a_blk_vec;
+            const int64_t a_mstep = (int64_t)WK * a_blk_vec;
+            AFrag16<NV> a_cur;
+            if constexpr (NV > 0) load_a16<C, NV>(a_cur, a_base, a_mstep, 0, 0, lane);
+            __syncthreads();  // previous users of s_buf are done
+            {
+              float cr[4 * C::JT], ci[4 * C::JT];
+              gen_pairs16<C>(cr, ci, xs, px, py, pz, tid, 0, 4 * C::JT);
+              gen_store16<C>(s_buf[0], cr, ci, tid);
+            }
+            __syncthreads();
+            for (int c = 0; c < n_chunks; ++c) {
+              const int c_next = min(c + 1, n_chunks - 1);
+              const BB_LDS double* const xs_next = xs + 4 * c_next * C::LCH;
+              float cr[4 * C::JT], ci[4 * C::JT];
+              if constexpr (NV > 0) {
+                // waves of odd k-groups multiply at a higher priority, which
+                // staggers the phase slices of the waves sharing a SIMD
+                if (wk & 1) __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+                for (int g = 0; g < C::NG; ++g) {
+                  AFrag16<NV> a_nxt;
+                  load_a16<C, NV>(a_nxt, a_base, a_mstep, g + 1 < C::NG ? c : c_next, g + 1 < C::NG ? g + 1 : 0,
+                                  lane);
+                  gen_pairs16<C>(cr, ci, xs_next, px, py, pz, tid, g * C::PPG, C::PPG);
+                  mma_group16<C, MR, NP, NV>(acc, a_cur, s_buf[c & 1], g, pb0, lane);
+                  a_cur = a_nxt;
+                  __builtin_amdgcn_sched_barrier(0);
+                }
+                if (wk & 1) __builtin_amdgcn_s_setprio(0);
+              } else {
+                gen_pairs16<C>(cr, ci, xs_next, px, py, pz, tid, 0, 4 * C::JT);
+              }
+              gen_store16<C>(s_buf[(c + 1) & 1], cr, ci, tid);
+              __syncthreads();
+            }
+          };
+          if (nv == MR)
+            chunks(std::integral_constant<int, MR>{});
+          else if (MR > 3 && nv == 3)
+            chunks(std::integral_constant<int, (MR > 3 ? 3 : 1)>{});
+          else if (MR > 2 && nv == 2)
+            chunks(std::integral_constant<int, (MR > 2 ? 2 : 1)>{});
+          else if (MR > 1 && nv == 1)
+            chunks(std::integral_constant<int, 1>{});
+          else
+            chunks(std::integral_constant<int, 0>{});
+
+          // epilogue: weighted |E|^2 of each existing block into per-level sums
+#pragma unroll
+          for (int m = 0; m < MR; ++m) {
+            if (m >= nv) continue;
+            const int b = b0 + m * WK;
+            const int lev_lo = kbr16[2 * b], lev_hi = kbr16[2 * b + 1];
+            if (lev_lo > lev_hi) continue;
+            float w[4];
+            int lv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int k = b * 16 + 4 * (lane >> 4) + r;
+              w[r] = wts[k];
+              lv[r] = levs[k];
+            }
+#pragma unroll
+            for (int n = 0; n < NP; ++n) {
+              float e2[4];
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const float er = acc[0][m][n][r] - acc[2][m][n][r];
+                const float ei = acc[0][m][n][r] + acc[1][m][n][r];
+                e2[r] = w[r] * fmaf(er, er, ei * ei);
+              }
+              for (int l = lev_lo; l <= lev_hi; ++l) {
+                float sum = 0.0f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sum += (lv[r] == l) ? e2[r] : 0.0f;
+                sum += __shfl_xor(sum, 16);
+                sum += __shfl_xor(sum, 32);
+                if (lane < 16) s_part[wk][l][(pb0 + n) * 16 + lane] += sum;
+              }
+            }
+          }
+        }
+        __syncthreads();
+        for (int i = tid; i < n_levels * C::NT; i += C::THREADS) {
+          const int l = i / C::NT, pl = i % C::NT;
+          const int64_t p = p0 + pl;
+          if (p < P.n_pix) {
+            float sum = 0.0f;
+#pragma unroll
+            for (int q = 0; q < WK; ++q) sum += s_part[q][l][pl];
+            float* dst = P.img + ((int64_t)slot * n_levels + l) * P.img_ld + p;
+            *dst += sum;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
 // Resident workgroups of a kernel on the current device (persistent grid size).
 template <class K>
 static int resident_blocks(K kernel, int threads) {
@@ -798,6 +1103,24 @@ static hipError_t launch_cfg(const FwdParams& p, hipStream_t s) {
 template <int PREC, int MODE, int MB, int NB, int WK, int WN>
 static hipError_t launch_tc(const FwdParams& p, TileCfg<MB, NB, WK, WN>, hipStream_t s) {
   return launch_cfg<MB, NB, WK, WN, PREC, MODE>(p, s);
+}
+
+// 16-row tiles: the three-product FP32 form's level images only.
+template <int PREC, int MODE, int MR, int NP, int WK, int WN>
+static hipError_t launch_tc(const FwdParams& p, Tile16<MR, NP, WK, WN>, hipStream_t s) {
+  using C = Tile16<MR, NP, WK, WN>;
+  if constexpr (PREC != 2 || MODE != 0) {
+    return hipErrorInvalidValue;
+  } else {
+    if (p.n_tiles <= 0 || p.n_groups <= 0) return hipSuccess;
+    auto kern = synth_fwd16_kernel<MR, NP, WK, WN>;
+    static int resident = 0;  // per instantiation; one device type per process
+    if (resident <= 0) resident = resident_blocks(kern, C::THREADS);
+    int64_t grid = resident > 0 ? resident : 1024;
+    if (grid > p.n_tiles) grid = p.n_tiles;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(C::THREADS), 0, s, p);
+    return hipGetLastError();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -834,15 +1157,21 @@ struct Cands<1> {  // BF16 x3, 4 products: the shapes of the FP32 form, and narr
   static constexpr int dflt[4] = {3, 2, 1, 0};
 };
 template <>
-struct Cands<2> {  // 3 products: k1/k2/k3 accumulators, 48 regs per output block
-  using L = TileList<TileCfg<1, 2, 8, 1>,   // 0: 256 x 64
-                     TileCfg<1, 1, 4, 4>,   // 1: 128 x 128, 16 waves: 3 active k-blocks (K <= 96) still
-                                            //    spread evenly over the four SIMDs
-                     TileCfg<1, 2, 2, 4>,   // 2: 64 x 256
-                     TileCfg<1, 1, 1, 8>,   // 3: 32 x 256, one pixel block per wave, two waves per SIMD
-                     TileCfg<1, 2, 4, 2>,   // 4: 128 x 128
-                     TileCfg<1, 1, 2, 8>>;  // 5: 64 x 256, 16 waves
-  static constexpr int dflt[4] = {3, 2, 1, 0};
+struct Cands<2> {  // 3 products: k1/k2/k3 accumulators, 48 regs per 32x32 output block
+  using L = TileList<TileCfg<1, 2, 8, 1>,    // 0: 256 x 64
+                     TileCfg<1, 1, 4, 4>,    // 1: 128 x 128, 16 waves: 3 active k-blocks (K <= 96) still
+                                             //    spread evenly over the four SIMDs
+                     TileCfg<1, 2, 2, 4>,    // 2: 64 x 256
+                     TileCfg<1, 1, 1, 8>,    // 3: 32 x 256, one pixel block per wave, two waves per SIMD
+                     TileCfg<1, 2, 4, 2>,    // 4: 128 x 128
+                     TileCfg<1, 1, 2, 8>,    // 5: 64 x 256, 16 waves
+                     Tile16<4, 2, 2, 4>,     // 6: 128 x 128 in 16-row blocks, 8 waves
+                     Tile16<2, 2, 2, 4>,     // 7: 64 x 128 in 16-row blocks
+                     Tile16<1, 2, 2, 4>,     // 8: 32 x 128 in 16-row blocks
+                     Tile16<4, 1, 2, 4>,     // 9: 128 x 64 in 16-row blocks
+                     Tile16<1, 2, 4, 4>,     // 10: 64 x 128 in 16-row blocks, 16 waves
+                     Tile16<2, 2, 4, 4>>;    // 11: 128 x 128 in 16-row blocks, 16 waves
+  static constexpr int dflt[4] = {3, 10, 11, 0};
 };
 template <>
 struct Cands<3> {  // BF16 three products: in 16 waves its operand fragments would spill
@@ -914,6 +1243,15 @@ bool synth_tile_info(int precision, int id, int* kc, int* nt, int* waves) {
   if (nt) *nt = b;
   if (waves) *waves = c;
   return true;
+}
+
+int synth_tile_rows(int precision, int id) {
+  int rows = 32;
+  (void)with_tile(precision, id, [&](auto cfg) {
+    rows = decltype(cfg)::ROWS;
+    return hipSuccess;
+  });
+  return rows;
 }
 
 bool synth_tile_allowed(int precision, int id, int k_class) {
