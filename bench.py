@@ -271,7 +271,10 @@ def measure_c4(args, torch, ctx):
     batch = Batch(items, ctx.device)
     s = StandardSynthesis(ctx, w.pix, 4, 64, 512, 128, args.precision)
     tune = None
-    if not args.no_autotune:
+    if args.c4_tiles:
+        s.tiles = [int(v) for v in args.c4_tiles.split(",")]
+        log(f"C4: tiles {s.tiles} as given")
+    elif not args.no_autotune:
         t0 = time.perf_counter()
         table = s.autotune_batched(batch, reps=1)
         tune = {"tiles": s.tiles, "ms_per_launch_by_class_and_tile": table, "seconds": time.perf_counter() - t0}
@@ -286,12 +289,14 @@ def measure_c4(args, torch, ctx):
         torch.cuda.synchronize()
         ms.append((time.perf_counter() - t0) * 1000.0)
     kern = s.timings()[2]
+    s_tiles = s.tiles
     s.close()
     prods = batch.products * w.n_pix
     log(f"C4 batched: {np.mean(ms):.1f} ms/call, synthesis {kern:.1f} ms, {prods / (np.mean(ms) / 1e3):.3e} products/s")
     return {"workload": "2048 uneven instances (64 channels x 32 epochs, L 200..512, K 16..128, 4 levels), "
                         "512x512 pixels, one batched call", "contraction": args.precision,
             "products": prods, "ms_per_call": float(np.mean(ms)), "synthesis_kernels_ms": kern, "autotune": tune,
+            "tiles": s_tiles,
             "value": prods / (np.mean(ms) / 1e3), "unit": "products/s",
             "algorithmic_fp32_rate_over_peak": ALG_FLOP * prods / (np.mean(ms) / 1e3) / (FP32_PEAK_TFLOPS * 1e12),
             "mfma_fraction_of_own_peak": EXEC_FLOP[args.precision] * prods / (kern / 1e3) / (PEAK[args.precision] * 1e12)}
@@ -603,6 +608,11 @@ def main():
                     help="uvw-domain partitions per axis of the NUFFT comparison")
     ap.add_argument("--only-nufft", action="store_true",
                     help="print only the NUFFT-vs-standard measurement (for profiling it alone)")
+    ap.add_argument("--only-c4", action="store_true",
+                    help="print only the batched uneven-instance measurement (for profiling it alone)")
+    ap.add_argument("--c4-tiles", default=None,
+                    help="tile ids per K class for the batched uneven-instance measurement, comma-separated "
+                         "(-1 keeps a class's default); implies no autotuning there")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default tile shapes instead of timing the candidates before the timed steps")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
@@ -630,6 +640,10 @@ def main():
     if args.only_nufft:
         from paper_2310_09200_amd import Context
         print(json.dumps({"nufft_vs_standard": measure_nufft(args, torch, Context(0))}), flush=True)
+        return
+    if args.only_c4:
+        from paper_2310_09200_amd import Context
+        print(json.dumps({"batched_c4": measure_c4(args, torch, Context(0))}), flush=True)
         return
     ctx, w, intervals, items, insts, pre_ms = build_inputs(args, torch, dev)
     n_levels = intervals.shape[0]

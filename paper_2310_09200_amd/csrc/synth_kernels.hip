@@ -1167,11 +1167,11 @@ struct Cands<2> {  // 3 products: k1/k2/k3 accumulators, 48 regs per 32x32 outpu
                      TileCfg<1, 1, 2, 8>,    // 5: 64 x 256, 16 waves
                      Tile16<4, 2, 2, 4>,     // 6: 128 x 128 in 16-row blocks, 8 waves
                      Tile16<2, 2, 2, 4>,     // 7: 64 x 128 in 16-row blocks
-                     Tile16<1, 2, 2, 4>,     // 8: 32 x 128 in 16-row blocks
-                     Tile16<4, 1, 2, 4>,     // 9: 128 x 64 in 16-row blocks
+                     Tile16<1, 1, 2, 8>,     // 8: 32 x 128 in 16-row blocks, 16 waves
+                     Tile16<2, 1, 2, 8>,     // 9: 64 x 128 in 16-row blocks, 16 waves
                      Tile16<1, 2, 4, 4>,     // 10: 64 x 128 in 16-row blocks, 16 waves
                      Tile16<2, 2, 4, 4>>;    // 11: 128 x 128 in 16-row blocks, 16 waves
-  static constexpr int dflt[4] = {3, 10, 11, 0};
+  static constexpr int dflt[4] = {3, 9, 11, 0};
 };
 template <>
 struct Cands<3> {  // BF16 three products: in 16 waves its operand fragments would spill

@@ -373,7 +373,7 @@ def test_autotune_keeps_images_and_picks_candidates(ctx, tile_case):
     with pytest.raises(BluebildError):
         s.tiles = [0, 0, 0, 0]        # a 256-eigenpair tile is not a candidate for K <= 32
     s.tiles = [-1, -1, -1, -1]        # defaults
-    assert s.tiles == [3, 10, 11, 0]
+    assert s.tiles == [3, 9, 11, 0]
     s.close()
 
 
