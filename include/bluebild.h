@@ -326,11 +326,26 @@ bb_status bb_synth_collect_eig_noalloc(bb_context ctx, int32_t precision, int32_
  *   scratch_images (device, float32 n_slots x n_levels x n_pix, overwritten;
  *   the handle's images are not touched) and ms_out (host, BB_K_CLASSES x
  *   BB_MAX_TILES doubles, row per class: mean milliseconds per launch, -1 where
- *   not timed).  Waits for the device. */
+ *   not timed).  Waits for the device.
+ * Autotune cache: with the environment variable BB_TUNE_CACHE naming a file,
+ *   bb_synth_autotune_batched records the tile it kept for each K class it
+ *   timed, keyed by (device architecture, precision, K class,
+ *   floor(log2(n_pix))), one JSON object per line (the file is replaced
+ *   whole through a temporary file beside it; lines in another form are
+ *   kept), and bb_synth_create starts a handle from the cached tiles of its
+ *   key (a cached tile its class may not use is ignored).  A cache that
+ *   cannot be written makes the autotune call return BB_ERR_STATE; the
+ *   handle keeps the tuned tiles.
+ * bb_tune_cache_lookup: the tiles a new handle of device architecture `arch`
+ *   (e.g. "gfx950"), `precision` and `n_pix` pixels would take from the
+ *   cache: tiles (host, BB_K_CLASSES ints) gets each class's cached tile, or
+ *   -1 where there is none (or BB_TUNE_CACHE is unset).  Host only: touches
+ *   no device. */
 #define BB_K_CLASSES 4
 #define BB_MAX_TILES 12
 bb_status bb_tile_info(int32_t precision, int32_t tile, int32_t* eig_per_pass, int32_t* pix_per_tile, int32_t* waves,
                        int32_t* class_mask);
+bb_status bb_tune_cache_lookup(const char* arch, int32_t precision, int64_t n_pix, int32_t* tiles);
 bb_status bb_synth_get_tiles(bb_synth h, int32_t* tiles);
 bb_status bb_synth_set_tiles(bb_synth h, const int32_t* tiles);
 bb_status bb_synth_autotune_batched(bb_synth h, int32_t n_inst, const bb_instance* inst, int64_t n_ant_rows,

@@ -66,6 +66,7 @@ PROTOS = {
                                                c_int32, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
     "bb_tile_info": (c_int32, [c_int32, c_int32, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
                                POINTER(c_int32)]),
+    "bb_tune_cache_lookup": (c_int32, [c_char_p, c_int32, c_int64, POINTER(c_int32)]),
     "bb_synth_get_tiles": (c_int32, [c_void_p, POINTER(c_int32)]),
     "bb_synth_set_tiles": (c_int32, [c_void_p, POINTER(c_int32)]),
     "bb_synth_autotune_batched": (c_int32, [c_void_p, c_int32, POINTER(bb_instance), c_int64, c_int64, c_int64,

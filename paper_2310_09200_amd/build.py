@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbluebild.so")
 
 SOURCES = ["api.cpp", "synth_kernels.hip", "prestep.hip", "synth_bwd.hip", "levels_weighting.hip", "nufft.hip", "nufft_fft.hip", "nufft_gather.hip",
-           "nufft_api.cpp", "noalloc.hip"]
+           "nufft_api.cpp", "noalloc.hip", "tune_cache.cpp"]
 ARCH = "gfx950"
 
 

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "api_common.h"
+#include "tune_cache.h"
 #include "bb_internal.h"
 #include "bluebild.h"
 
@@ -246,6 +247,7 @@ bb_status run_single(bb_synth h, const InstDesc& d) {
 // Fixed scratch of the no-allocation entry point: metadata, error word, staging.
 static_assert(BB_NOALLOC_SCRATCH_BYTES == bb::kNoallocScratchBytes, "header and library agree on the scratch size");
 static_assert(BB_K_CLASSES == bb::kKClasses, "header and library agree on the K classes");
+static_assert(bb_host::kTuneClasses == bb::kKClasses, "the tune cache keys the K classes");
 constexpr size_t kNoallocMeta = 0;
 constexpr size_t kNoallocErr = (sizeof(SingleMeta) + kAlign - 1) / kAlign * kAlign;
 constexpr size_t kNoallocStage = kNoallocErr + kAlign;
@@ -301,6 +303,12 @@ bb_status bb_context_create(int device, void* hip_stream, bb_context* out) {
     return BB_ERR_DEVICE;
   }
   rocblas_set_stream(c->rb, c->stream);
+  hipDeviceProp_t prop{};
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    c->arch = prop.gcnArchName;
+    const size_t colon = c->arch.find(':');
+    if (colon != std::string::npos) c->arch.resize(colon);
+  }
   bb_status st = noalloc_lookup(c, device, &c->noalloc_scratch);
   if (st != BB_OK) {
     rocblas_destroy_handle(c->rb);
@@ -362,7 +370,12 @@ bb_status bb_synth_create(bb_context ctx, const bb_options* opt, int64_t n_pix, 
   h->ws = static_cast<char*>(workspace);
   h->ws_bytes = ws_bytes;
   h->lay = lay;
-  for (int c = 0; c < bb::kKClasses; ++c) h->tiles[c] = bb::synth_default_tile(opt->precision, c);
+  int cached[bb::kKClasses];
+  bb_host::tune_cache_lookup(ctx->arch, opt->precision, n_pix, cached);
+  for (int c = 0; c < bb::kKClasses; ++c)
+    h->tiles[c] = (cached[c] >= 0 && bb::synth_tile_allowed(opt->precision, cached[c], c))
+                      ? cached[c]
+                      : bb::synth_default_tile(opt->precision, c);
   for (auto& e : h->ev)
     if (hipEventCreate(&e) != hipSuccess) {
       delete h;
@@ -1107,6 +1120,16 @@ bb_status bb_tile_info(int32_t precision, int32_t tile, int32_t* eig_per_pass, i
   return BB_OK;
 }
 
+bb_status bb_tune_cache_lookup(const char* arch, int32_t precision, int64_t n_pix, int32_t* tiles) {
+  if (!arch || !tiles || n_pix < 1 || precision < BB_PREC_FP32 || precision > BB_PREC_BF16X3_3M)
+    return BB_ERR_INVALID_ARG;
+  int cached[bb::kKClasses];
+  bb_host::tune_cache_lookup(arch, precision, n_pix, cached);
+  for (int c = 0; c < bb::kKClasses; ++c)
+    tiles[c] = (cached[c] >= 0 && bb::synth_tile_allowed(precision, cached[c], c)) ? cached[c] : -1;
+  return BB_OK;
+}
+
 bb_status bb_synth_get_tiles(bb_synth h, int32_t* tiles) {
   if (!h || !tiles) return BB_ERR_INVALID_ARG;
   for (int c = 0; c < bb::kKClasses; ++c) tiles[c] = h->tiles[c];
@@ -1208,6 +1231,11 @@ bb_status bb_synth_autotune_batched(bb_synth h, int32_t n_inst, const bb_instanc
   }
   for (int c = 0; c < bb::kKClasses; ++c) h->tiles[c] = best[c];
   h->timed = false;
+  double best_ms[bb::kKClasses];
+  for (int c = 0; c < bb::kKClasses; ++c) best_ms[c] = present[c] ? ms_out[c * BB_MAX_TILES + best[c]] : 0.0;
+  std::string cache_err;
+  if (!bb_host::tune_cache_store(ctx->arch, h->opt.precision, h->n_pix, best, best_ms, present, cache_err))
+    return fail(ctx, BB_ERR_STATE, "%s (the handle keeps the tuned tiles)", cache_err.c_str());
   return BB_OK;
 }
 

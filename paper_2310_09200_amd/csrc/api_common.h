@@ -22,6 +22,9 @@ struct bb_context_ {
   // device address of the library's fixed scratch on this device (looked up
   // when the context is created; used by bb_synth_collect_eig_noalloc)
   void* noalloc_scratch = nullptr;
+  // device architecture name without feature suffixes ("gfx950"): the key of
+  // the autotune cache entries
+  std::string arch;
 };
 
 namespace bb_host {

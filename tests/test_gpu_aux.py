@@ -215,3 +215,58 @@ def test_debug_fill_leaves_every_result_unchanged(ctx, monkeypatch):
         same = np.array_equal(plain[k], poisoned[k])
         say(f"{k}: {'bitwise equal' if same else 'DIFFERS'}")
         assert same, k
+
+
+def test_tune_cache_written_by_autotune_and_read_by_create(ctx, tmp_path, monkeypatch):
+    """BB_TUNE_CACHE: a handle starts from the cached tiles of its key; autotuning
+    replaces the entries of the classes it timed (other lines kept) and a new
+    handle then starts from the tuned tiles; an unwritable cache fails the
+    autotune call with BB_ERR_STATE while the handle keeps its tuned tiles."""
+    import json
+
+    from paper_2310_09200_amd import Batch, BluebildError, StandardSynthesis, _lib, tile_shapes
+    say("case autotune cache")
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    g = np.random.default_rng(12)
+    pix = sims.pixel_grid(40, 6.0, 60.0)          # 1600 pixels: pix_log2 = 10
+    wl = sims.wavelength_m(150e6)
+    items = []
+    for i, (L, K) in enumerate([(60, 20), (70, 50), (80, 100)]):
+        x = sims.disk_layout(L, 3000.0, g, z_sigma_m=2.0)
+        items.append((0, x, wl, sims.random_eigvecs(L, K, g).astype(np.complex64),
+                      g.normal(0, 1, K).astype(np.float32), g.integers(0, 2, K).astype(np.int32)))
+    path = tmp_path / "tune.jsonl"
+    other = '{"arch": "%s", "precision": 2, "k_class": 2, "pix_log2": 11, "tile": 1, "ms": 1.0}' % arch
+    path.write_text('{"arch": "%s", "precision": 2, "k_class": 2, "pix_log2": 10, "tile": 6, "ms": 5.0}\n'
+                    'kept as it is\n%s\n' % (arch, other))
+    monkeypatch.setenv("BB_TUNE_CACHE", str(path))
+    s = StandardSynthesis(ctx, pix, 2, 1, 80, 100, "fp32_3m")
+    assert s.tiles == [3, 9, 6, 0]                # class 2 from the cache, the rest defaults
+    ms = s.autotune_batched(Batch(items, ctx.device), reps=1)
+    s.sync()
+    tuned = s.tiles
+    s.close()
+    lines = path.read_text().splitlines()
+    assert "kept as it is" in lines and other in lines
+    entries = [json.loads(ln) for ln in lines if ln.startswith("{") and ln != other]
+    assert sorted(e["k_class"] for e in entries) == sorted(ms)
+    for e in entries:
+        assert (e["arch"], e["precision"], e["pix_log2"]) == (arch, 2, 10)
+        assert e["tile"] == tuned[e["k_class"]] and e["ms"] == pytest.approx(ms[e["k_class"]][e["tile"]], abs=1e-3)
+    s2 = StandardSynthesis(ctx, pix, 2, 1, 80, 100, "fp32_3m")
+    assert s2.tiles == tuned
+    s2.close()
+    s3 = StandardSynthesis(ctx, pix[:1000], 2, 1, 80, 100, "fp32_3m")   # another pixel key: defaults
+    assert s3.tiles == [3, 9, 11, 0]
+    s3.close()
+    monkeypatch.setenv("BB_TUNE_CACHE", str(tmp_path / "no_such_dir" / "tune.jsonl"))
+    s4 = StandardSynthesis(ctx, pix, 2, 1, 80, 100, "fp32_3m")
+    s4.tiles = [3, 2, 1, 0]
+    with pytest.raises(BluebildError) as e:
+        s4.autotune_batched(Batch(items, ctx.device), reps=1)
+    assert e.value.status == _lib.BB_ERR_STATE
+    shapes = tile_shapes("fp32_3m")
+    for c in range(3):                            # tuned: a candidate of each timed class
+        assert c in next(cl for t, *_, cl in shapes if t == s4.tiles[c])
+    assert s4.tiles[3] == 0                       # class 3 was not in the batch
+    s4.close()
