@@ -58,8 +58,10 @@ def test_c1_against_oracle(ctx, precision):
     assert np.all(err[:, 0] <= TOL[precision]), err
 
 
-CASES = [  # (L, K, n_side): ragged antenna / eigenpair / pixel counts covering every tile shape
-    (7, 5, 23), (50, 37, 37), (64, 64, 40), (129, 100, 41), (300, 200, 29), (333, 300, 19), (512, 512, 17),
+CASES = [  # (L, K, n_side): ragged antenna / eigenpair / pixel counts covering every tile shape,
+    # and the K class edges (16 and 17 rows: one and two 16-row blocks; 64 / 65: classes 1 / 2)
+    (7, 5, 23), (40, 16, 19), (33, 17, 21), (50, 37, 37), (64, 64, 40), (100, 65, 27), (129, 100, 41),
+    (300, 200, 29), (333, 300, 19), (512, 512, 17),
 ]
 
 
