@@ -281,19 +281,23 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
 //     accumulated over the split (A = phases, rows l; B = M, columns k);
 //   the H block of pixels 32 (w / 2) .. + 31 of the chunk, part w % 2
 //     (A = conj(W), rows l; B = M, columns p).
-// H goes through LDS to the threads that own (antenna t / 8, pixels t % 8 + 8 j),
+// H goes through LDS to the threads that own (antenna t % 32, pixels t / 32 + 8 j),
 // which form Im(H B) p with the staged phases.  The next chunk's M and pixel
 // coordinates are loaded into registers while the current chunk is processed.
 __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
   __shared__ float2 sW[32][65];   // conj(W) [32 l][64 k], staged once (+1 pad: column reads)
-  __shared__ float2 sM[64][65];   // M [64 k][64 p] (+1 pad: column reads); then H re / im [2][32][64] floats
+  __shared__ float2 sM[64][65];   // M [64 k][64 p] (+1 pad: column reads); then H re / im [2][64 p][33] floats
   __shared__ float2 sB[64][32];   // phases [64 p][32 l]
   __shared__ double sP[3][64];    // the chunk's pixel coordinates
+  __shared__ double sX[32][4];    // the tile's scaled antenna positions, staged once
   __shared__ double sh[3][256];
   const InstDesc& D = *P.desc;
   const int l0 = blockIdx.x * 32, s = blockIdx.y;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int tl = t >> 3, tp = (t & 7);
+  // Im(H B) p: consecutive lanes take consecutive antennas, so the reads of
+  // the phases and of H (stored pixel-major, rows padded to 33) are free of
+  // bank conflicts
+  const int tl = t & 31, tp = t >> 5;
   const int l = l0 + tl;
   const int blk = wave >> 1, part = wave & 1;
   const bool dw_active = 32 * blk < P.K_alloc;  // wave-uniform: this wave's dW block exists
@@ -304,7 +308,8 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
   const float* Er = P.E;
   const float* Ei = P.E + (int64_t)P.K_alloc * P.n_pix;
   const float* Wf = (const float*)P.W;
-  float* const sH = reinterpret_cast<float*>(&sM[0][0]);  // [2 parts][32 l][64 p]
+  float* const sH = reinterpret_cast<float*>(&sM[0][0]);  // [2 parts][64 p][33]
+  if (t < 128) (&sX[0][0])[t] = D.xs[4 * l0 + t];            // rows l0 .. l0 + 31 < L_pad
   for (int i = t; i < 32 * 64; i += 256) {
     const int ll = i >> 6, kk = i & 63;
     float2 wv = make_float2(0.0f, 0.0f);
@@ -344,10 +349,12 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
     if (t < 192) sP[t >> 6][t & 63] = pnext;
     __syncthreads();
     if (pc + 64 < p1) load_chunk(pc + 64);  // workgroup-uniform
-    for (int i = t; i < 64 * 32; i += 256) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = t + 256 * j;
       const int pp = i >> 5, ll = i & 31;
       float c = 0.0f, sn = 0.0f;
-      if (pc + pp < p1) phase_b(D.xs + 4 * (l0 + ll), sP[0][pp], sP[1][pp], sP[2][pp], c, sn);
+      if (pc + pp < p1) phase_b(&sX[ll][0], sP[0][pp], sP[1][pp], sP[2][pp], c, sn);
       sB[pp][ll] = make_float2(c, sn);
     }
     __syncthreads();
@@ -388,7 +395,7 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int ll = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      sH[(part * 32 + ll) * 64 + 32 * blk + (lane & 31)] = h[r];
+      sH[(part * 64 + 32 * blk + (lane & 31)) * 33 + ll] = h[r];
     }
     __syncthreads();
     if (l < P.L) {
@@ -397,7 +404,7 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
         const int pp = tp + 8 * j;
         if (pc + pp < p1) {
           const float2 b = sB[pp][tl];
-          const float hr = sH[tl * 64 + pp], hi = sH[(32 + tl) * 64 + pp];
+          const float hr = sH[pp * 33 + tl], hi = sH[(64 + pp) * 33 + tl];
           const double v = (double)fmaf(hr, b.y, hi * b.x);  // Im(H B)
           gx += v * sP[0][pp];
           gy += v * sP[1][pp];
@@ -421,9 +428,9 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
   if (tp == 0 && l < P.L_pad) {
     double a = 0, b = 0, c = 0;
     for (int j = 0; j < 8; ++j) {
-      a += sh[0][t + j];
-      b += sh[1][t + j];
-      c += sh[2][t + j];
+      a += sh[0][t + 32 * j];
+      b += sh[1][t + 32 * j];
+      c += sh[2][t + 32 * j];
     }
     double* o = P.dx_part + ((int64_t)s * P.L_pad + l) * 3;
     o[0] = a;
