@@ -92,9 +92,12 @@ typedef float bwd_f32x16 __attribute__((ext_vector_type(16)));
 __global__ __launch_bounds__(256) void bwd_dw_kernel(const BwdParams P) {
   __shared__ float2 sB[64][32];
   __shared__ float2 sM[64][32];
+  __shared__ double sX[32][4];  // the tile's scaled antenna positions
   const InstDesc& D = *P.desc;
   const int l0 = blockIdx.x * 32, k0 = blockIdx.y * 32, s = blockIdx.z;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  if (t < 128) (&sX[0][0])[t] = D.xs[4 * l0 + t];  // rows l0 .. l0 + 31 < L_pad
+  __syncthreads();
   const int64_t p0 = (int64_t)s * P.split_len;
   int64_t p1 = p0 + P.split_len;
   if (p1 > P.n_pix) p1 = P.n_pix;
@@ -105,13 +108,13 @@ __global__ __launch_bounds__(256) void bwd_dw_kernel(const BwdParams P) {
   const float* Ei = P.E + (int64_t)P.K_alloc * P.n_pix;
   for (int64_t pc = p0; pc < p1; pc += 64) {
     // phases: 32 antennas x 64 pixels, 8 per thread (zero past the split)
-    for (int i = t; i < 64 * 32; i += 256) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = t + 256 * j;
       const int pp = i >> 5, ll = i & 31;
       const int64_t p = pc + pp;
       float c = 0.0f, sn = 0.0f;
-      if (p < p1) {
-        phase_b(D.xs + 4 * (l0 + ll), P.pix[p], P.pix[p + P.pix_ld], P.pix[p + 2 * P.pix_ld], c, sn);
-      }
+      if (p < p1) phase_b(&sX[ll][0], P.pix[p], P.pix[p + P.pix_ld], P.pix[p + 2 * P.pix_ld], c, sn);
       sB[pp][ll] = make_float2(c, sn);
     }
     for (int i = t; i < 64 * 32; i += 256) {
@@ -164,17 +167,20 @@ __global__ __launch_bounds__(256) void bwd_dw_kernel(const BwdParams P) {
 // 64-pixel chunk and 64-eigenpair slice, conj(W) [32 l][64 k] and M [64 k][64 p]
 // are staged in LDS; wave w computes one real 32 x 32 block of H: pixel half
 // w / 2, real part (w even: Wr Mr - Wi' Mi with W' = conj W) or imaginary part
-// (w odd: Wr' Mi + Wi' Mr).  The blocks go through LDS to the threads that
-// own (antenna t / 8, pixels t % 8 + 8 j), which evaluate the phases.
+// (w odd: Wr' Mi + Wi' Mr).  The blocks go through LDS (pixel-major, rows
+// padded to 33) to the threads that own (antenna t % 32, pixels t / 32 + 8 j),
+// which evaluate the phases.
 __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
   __shared__ float2 sW[32][65];   // conj(W) for 32 antennas x 64 eigenpairs (+1 pad: column reads)
-  __shared__ float2 sM[64][65];   // M for 64 eigenpairs x 64 pixels; then H re / im [2][32][64] floats
+  __shared__ float2 sM[64][65];   // M for 64 eigenpairs x 64 pixels; then H re / im [2][64 p][33] floats
+  __shared__ double sX[32][4];    // the tile's scaled antenna positions
   __shared__ double sh[3][256];
   const InstDesc& D = *P.desc;
   const int l0 = blockIdx.x * 32, s = blockIdx.y;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int tl = t >> 3, tp = (t & 7);
+  const int tl = t & 31, tp = t >> 5;
   const int l = l0 + tl;
+  if (t < 128) (&sX[0][0])[t] = D.xs[4 * l0 + t];  // rows l0 .. l0 + 31 < L_pad
   const int blk = wave >> 1, part = wave & 1;  // this wave's H block: pixel half, re / im
   const int64_t p0 = (int64_t)s * P.split_len;
   int64_t p1 = p0 + P.split_len;
@@ -183,7 +189,7 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
   const float* Er = P.E;
   const float* Ei = P.E + (int64_t)P.K_alloc * P.n_pix;
   const float* Wf = (const float*)P.W;
-  float* const sH = reinterpret_cast<float*>(&sM[0][0]);  // [2 parts][32 l][64 p]
+  float* const sH = reinterpret_cast<float*>(&sM[0][0]);  // [2 parts][64 p][33]
   double gx = 0.0, gy = 0.0, gz = 0.0;
   for (int64_t pc = p0; pc < p1; pc += 64) {
     bwd_f32x16 acc;
@@ -233,7 +239,7 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int ll = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-      sH[(part * 32 + ll) * 64 + 32 * blk + (lane & 31)] = acc[r];
+      sH[(part * 64 + 32 * blk + (lane & 31)) * 33 + ll] = acc[r];
     }
     __syncthreads();
     if (l < P.L) {
@@ -244,8 +250,8 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
         if (p < p1) {
           const double px = P.pix[p], py = P.pix[p + P.pix_ld], pz = P.pix[p + 2 * P.pix_ld];
           float c, sn;
-          phase_b(D.xs + 4 * l, px, py, pz, c, sn);
-          const float hr = sH[tl * 64 + pp], hi = sH[(32 + tl) * 64 + pp];
+          phase_b(&sX[tl][0], px, py, pz, c, sn);
+          const float hr = sH[pp * 33 + tl], hi = sH[(64 + pp) * 33 + tl];
           const double v = (double)fmaf(hr, sn, hi * c);  // Im(H B)
           gx += v * px;
           gy += v * py;
@@ -262,9 +268,9 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
   if (tp == 0 && l < P.L_pad) {
     double a = 0, b = 0, c = 0;
     for (int j = 0; j < 8; ++j) {
-      a += sh[0][t + j];
-      b += sh[1][t + j];
-      c += sh[2][t + j];
+      a += sh[0][t + 32 * j];
+      b += sh[1][t + 32 * j];
+      c += sh[2][t + 32 * j];
     }
     double* o = P.dx_part + ((int64_t)s * P.L_pad + l) * 3;
     o[0] = a;
