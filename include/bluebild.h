@@ -406,7 +406,10 @@ bb_status bb_synth_eig_backward(bb_synth h, int32_t n_ant, int32_t n_eig, double
  * points are added with FP32 atomics (the busiest parts of the uv plane, and
  * grids thicker than 32 points along p0) the last bits of a result vary
  * between runs.  Memory: n_levels N0 N1 N2 complex64 grid cells plus two stage
- * buffers of about N0 M1 M2 / 2 cells each (bb_nufft_workspace_size). */
+ * buffers of about N0 M1 M2 / 2 cells each (bb_nufft_workspace_size).
+ * Allocation: the plan and its calls use only the caller's workspace, except
+ * on the rocFFT transform, whose plans (made at bb_nufft_create, released at
+ * bb_nufft_destroy) keep device tables that rocFFT allocates itself. */
 typedef struct bb_nufft_* bb_nufft;
 typedef struct {
   int32_t n_levels;   /* images, 1..16 */
