@@ -86,14 +86,38 @@ def test_ragged_random_eigpairs(ctx, L, K, n_side, precision):
     assert np.all(err[:, 0] <= TOL[precision]), err
 
 
-def test_all_levels_dropped_leaves_images_zero(ctx):
-    say("case all level ids -1")
+@pytest.mark.parametrize("K,precision", [(20, "fp32"), (50, "fp32_3m"), (100, "fp32_3m"), (100, "bf16x3_3m")])
+def test_all_levels_dropped_leaves_images_zero(ctx, K, precision):
+    """Every level id -1: no kept eigenpair, so no pass runs and the images stay zero
+    (32-row and 16-row tiles)."""
+    say(f"case all level ids -1, K={K} precision={precision}")
     g = np.random.default_rng(5)
     x = sims.disk_layout(40, 1000.0, g)
     pix = sims.pixel_grid(16, 5.0, 90.0)
-    W = sims.random_eigvecs(40, 20, g)
-    got = run_eig(ctx, pix, 2, x, 2.0, W, np.ones(20), -np.ones(20, np.int32))
+    W = sims.random_eigvecs(40, K, g)
+    got = run_eig(ctx, pix, 2, x, 2.0, W, np.ones(K), -np.ones(K, np.int32), precision)
     assert np.all(got == 0)
+
+
+@pytest.mark.parametrize("precision", ["fp32_3m", "bf16x3_3m"])
+def test_sixteen_levels(ctx, precision):
+    """The largest level count (16) with K in the K <= 128 class: level ranges of
+    16-row and 32-row blocks that span many levels, against the oracle."""
+    say(f"case 16 levels precision={precision}")
+    g = np.random.default_rng(16)
+    L, K = 90, 100
+    x = sims.disk_layout(L, 3000.0, g, z_sigma_m=2.0)
+    wl = sims.wavelength_m(150e6)
+    pix = sims.pixel_grid(30, 6.0, 60.0)
+    W = sims.random_eigvecs(L, K, g)
+    d = g.normal(0, 1, K)
+    lev = g.integers(-1, 16, K).astype(np.int32)
+    d32 = d.astype(np.float32).astype(np.float64)
+    want = oracle_images(W.astype(np.complex64).astype(np.complex128), d32, lev, x, wl, pix, 16)
+    got = run_eig(ctx, pix, 16, x, wl, W, d, lev, precision)
+    err = level_errors(got, want)
+    say("16 levels", precision, "max err", err[:, 0].max())
+    assert np.all(err[:, 0] <= TOL[precision]), err
 
 
 def test_accumulation_and_determinism(ctx):
