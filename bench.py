@@ -31,22 +31,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2310_09200_amd", "csrc", "synth_kernels.hip")
 # Counter summary of the synthesis kernel on this workload (rocprofv3 --pmc
 # FETCH_SIZE / WRITE_SIZE, calibrated by a device copy of known size; MFMA busy;
-# transcendental instructions).  It names the sha256 of the kernel source the
-# counters were taken on; its figures are used only while that source is the
-# current one, and reported as null otherwise.
+# transcendental instructions).  It names the sha256 of the kernel code the
+# counters were taken on (the source without its // comments and blank lines,
+# so that a comment edit keeps the figures and any code edit drops them); its
+# figures are used only while that code is the current one, and reported as
+# null otherwise.
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "synth_fwd_c2_counters.md")
 
 
-def kernel_source_sha256():
+def kernel_code_sha256(path=KERNEL_SOURCE):
     import hashlib
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    code = []
+    with open(path) as f:
+        for ln in f.read().splitlines():
+            i = ln.find("//")
+            if i >= 0:
+                ln = ln[:i]
+            ln = ln.rstrip()
+            if ln.strip():
+                code.append(ln)
+    return hashlib.sha256("\n".join(code).encode()).hexdigest()
 
 
 def counter_figures(mode):
     """{name: value} for ``mode`` from the counter summary, or None when it is absent or stale.
 
-    The summary carries lines ``kernel_source_sha256: <hex>`` and
+    The summary carries lines ``kernel_code_sha256: <hex>`` and
     ``<mode>.<name>: <value>`` (bytes per launch, MFMA busy fraction,
     transcendental wave instructions per launch, ...).
     """
@@ -58,7 +68,7 @@ def counter_figures(mode):
     sha, out = None, {}
     for ln in lines:
         ln = ln.strip().strip("`")
-        if ln.startswith("kernel_source_sha256:"):
+        if ln.startswith("kernel_code_sha256:"):
             sha = ln.split(":", 1)[1].strip()
         elif ln.startswith(mode + ".") and ":" in ln:
             k, v = ln[len(mode) + 1:].split(":", 1)
@@ -66,7 +76,7 @@ def counter_figures(mode):
                 out[k.strip()] = float(v)
             except ValueError:
                 pass
-    if sha is None or sha != kernel_source_sha256() or not out:
+    if sha is None or sha != kernel_code_sha256() or not out:
         return None
     return out
 

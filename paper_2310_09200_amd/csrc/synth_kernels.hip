@@ -21,6 +21,8 @@
 //   end of the tile: sum over waves in a fixed order, one read-modify-write of
 //     the images (one writer per pixel and launch: deterministic, no atomics).
 // Neither B (L x N_pix) nor E (K x N_pix) is ever written to HBM.
+// synth_fwd16_kernel is the same structure for the three-product FP32 form on
+// 16-row eigenpair blocks (16x16x4 MFMAs), for instances with few eigenpairs.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -817,7 +819,8 @@ __global__ __launch_bounds__(64 * WK * WN) void synth_fwd_kernel(const FwdParams
 // step, B lane l = pixel l % 16 of antenna l / 16; result register r of lane l
 // = row 4 (l / 16) + r, pixel l % 16.  Operand vectors are float2 (two steps,
 // 8 antennas): a group of MFMAs covers 8 antennas, which keeps the A operand
-// and its prefetch within the register budget of two waves per SIMD.
+// and its prefetch within the register budget (256 VGPRs at two waves per
+// SIMD, 128 at four).
 template <int MR, int NP, int WK, int WN>
 struct Tile16 {
   static constexpr int ROWS = 16;

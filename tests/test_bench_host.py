@@ -18,12 +18,12 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert r.stdout.strip() == ""
 
 
-def test_counter_figures_are_keyed_to_the_kernel_source(tmp_path, monkeypatch):
-    """Counter figures are read only while the summary names the current kernel source's hash."""
+def test_counter_figures_are_keyed_to_the_kernel_code(tmp_path, monkeypatch):
+    """Counter figures are read only while the summary names the current kernel code's hash."""
     import bench
-    sha = bench.kernel_source_sha256()
+    sha = bench.kernel_code_sha256()
     f = tmp_path / "c.md"
-    f.write_text(f"# x\n\n`kernel_source_sha256: {sha}`\n`fp32_3m.fetch_bytes: 1.5e10`\n"
+    f.write_text(f"# x\n\n`kernel_code_sha256: {sha}`\n`fp32_3m.fetch_bytes: 1.5e10`\n"
                  "`fp32_3m.write_bytes: 2e9`\n`fp32_3m.mfma_busy: 0.85`\nfp32.mfma_busy: 0.9\n")
     monkeypatch.setattr(bench, "COUNTER_SUMMARY", str(f))
     got = bench.counter_figures("fp32_3m")
@@ -31,9 +31,22 @@ def test_counter_figures_are_keyed_to_the_kernel_source(tmp_path, monkeypatch):
     assert bench.counter_figures("fp32") == {"mfma_busy": 0.9}
     assert bench.counter_figures("bf16x3") is None
     f.write_text(f.read_text().replace(sha, "0" * 64))
-    assert bench.counter_figures("fp32_3m") is None          # stale: another kernel source
+    assert bench.counter_figures("fp32_3m") is None          # stale: another kernel
     monkeypatch.setattr(bench, "COUNTER_SUMMARY", str(tmp_path / "missing.md"))
     assert bench.counter_figures("fp32_3m") is None
+
+
+def test_kernel_code_hash_ignores_comments_only(tmp_path):
+    """The key changes with the code and not with comments or blank lines."""
+    import bench
+    a = tmp_path / "a.hip"
+    a.write_text("int f(int x) {  // doubled\n  return 2 * x;\n}\n")
+    b = tmp_path / "b.hip"
+    b.write_text("// a note\nint f(int x) {   // twice x\n\n  return 2 * x;\n}\n")
+    c = tmp_path / "c.hip"
+    c.write_text("int f(int x) {\n  return 3 * x;\n}\n")
+    assert bench.kernel_code_sha256(str(a)) == bench.kernel_code_sha256(str(b))
+    assert bench.kernel_code_sha256(str(a)) != bench.kernel_code_sha256(str(c))
 
 
 def test_level_errors_definition():
