@@ -431,7 +431,7 @@ def measure_nufft(args, torch, ctx):
             "nufft_emit_ms": float(np.mean(emit_ms)), "speedup_nufft_over_standard": float(np.mean(std_ms) / np.mean(nu_ms)),
             "products": prods, "standard_products_per_s": prods / (np.mean(std_ms) / 1e3),
             "partitions": args.nufft_partitions, "uvw_partitions": args.nufft_uvw_partitions,
-            "transform": {"auto": "pruned, own LDS line FFTs where every axis fits, else rocFFT",
+            "transform": {"auto": "pruned, own LDS line FFTs where every axis fits (a direct DFT on MFMA for axes of at most 64 points), else rocFFT",
                           "rocfft": "pruned, rocFFT"}[args.nufft_transform],
             "max_level_diff_nufft_vs_standard": max(errs)}
 

@@ -207,6 +207,7 @@ hipError_t launch_nufft_interp(const NufftGeom& g, const InterpLayout& lay, cons
                                float* image, hipStream_t s);
 // Line FFTs of the pruned transform (nufft_fft.hip).
 constexpr int kLineFftMax = 16384;  // longest line held in LDS (128 KB)
+constexpr int kLineDftMax = 64;     // lines up to this length may be a direct pruned DFT instead
 struct LineFft {
   int L;                 // transform length (M of the axis)
   int n_in;              // stored inputs per line (N of the axis)
@@ -216,6 +217,7 @@ struct LineFft {
   int64_t n_lines, in_stride, out_stride;
   int64_t t_inner;       // out_mode 1: line = outer * t_inner + inner, stored at [outer][w][inner]
   int out_mode;          // 0: out[line * out_stride + w]
+  int direct;            // 1: a direct pruned DFT per line (L <= kLineDftMax) from a table
 };
 // Fills L, n_pass, radix_codes and nl; -1 if L is not 2,3,5-smooth or exceeds kLineFftMax.
 int line_fft_plan(int L, LineFft& p);
@@ -228,6 +230,13 @@ void line_fft_twiddles(const LineFft& p, float* tw);
 hipError_t launch_line_fft(const LineFft& p, const void* in, const float* inv_psi, const int* perm, const float2* tw,
                            void* out, hipStream_t s);
 hipError_t launch_transpose_c64(const void* in, int64_t rows, int64_t cols, void* out, hipStream_t s);
+// Table of the direct pruned DFT of a line of p.L points from p.n_in stored
+// inputs to the p.win_len kept outputs (complex64 [n_in][win_len], host):
+// exp(+2 pi i f m / L) times inv_psi[i], f the input's frequency, m the output position.
+void line_dft_table(const LineFft& p, const float* inv_psi, float* tab);
+// Whether a planned line (with n_in and the window set) fits the direct DFT kernel.
+bool line_dft_fits(const LineFft& p);
+hipError_t launch_line_dft(const LineFft& p, const void* in, const float2* tab, void* out, hipStream_t s);
 hipError_t launch_nufft_corr(const NufftGeom& g, const double* pix, int64_t pix_ld, int64_t n_pix, const double* quad_t,
                              const double* quad_wphi, int n_quad, double* corr, hipStream_t s);
 hipError_t launch_fill_zero_f64(double* p, int n, hipStream_t s);

@@ -13,7 +13,8 @@
 //   2. deconvolve and zero-pad: each level's grid, divided by the type-2
 //      kernel's transform, placed in an M = 2N grid;
 //   3. inverse FFT (unnormalised, e^{+i}), pruned to the lines that hold data
-//      and the outputs the pixels reach (nufft_fft.hip; rocFFT for long lines);
+//      and the outputs the pixels reach (nufft_fft.hip: LDS line FFTs, a
+//      direct DFT on MFMA for lines of at most 64 points; rocFFT for long lines);
 //   4. interpolate at each pixel's rescaled position with the same kernel,
 //      divide by the spreading kernel's transform there, and add
 //      2 Re(.) + the diagonal term into the image.

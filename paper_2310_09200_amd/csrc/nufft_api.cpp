@@ -36,6 +36,7 @@ struct NufftLayout {
   size_t grid, stage_ac, stage_b, work, work_bytes, t_total;  // from the transient base
   size_t perm[3];  // line FFTs: digit-reversed load position per input index (int32, M_d)
   size_t tw[3];    // line FFTs: the passes' twiddles (complex64, M_d - 1)
+  size_t dft[3];   // lines of at most kLineDftMax points: direct DFT table (complex64, N_d x window_d)
   size_t psi0, psi1, psi2, corr, quad_t, quad_wphi, diag, err, p_total;  // from the persistent base
   size_t total;    // t_total + p_total
 };
@@ -278,6 +279,8 @@ NufftLayout nufft_layout(const bb::NufftGeom& g, int n_levels, int64_t n_pix, si
       p += align_up(4 * (size_t)g.M[d]);
       l.tw[d] = p;
       p += align_up(8 * (size_t)g.M[d]);
+      l.dft[d] = p;
+      if (g.M[d] <= bb::kLineDftMax) p += align_up(8 * (size_t)g.N[d] * g.win_len[d]);
     }
   l.psi0 = p;
   p += align_up(4 * (size_t)g.N[0]);
@@ -577,6 +580,7 @@ bb_status create_one(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix,
       p.n_in = g.N[d];
       p.win_lo = g.win_lo[d];
       p.win_len = g.win_len[d];
+      p.direct = bb::line_dft_fits(p) ? 1 : 0;
     }
     h->lf[0].n_lines = (int64_t)g.N[0] * g.N[1];  // grid lines along axis 2 -> A'[i0][w2][i1]
     h->lf[0].in_stride = g.N[2];
@@ -626,13 +630,17 @@ bb_status create_one(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix,
     }
   }
   std::vector<int> perm[3];
-  std::vector<float> tw[3];
+  std::vector<float> tw[3], dft[3];
   if (line_fft)
     for (int d = 0; d < 3; ++d) {
       perm[d].resize(g.M[d]);
       bb::line_fft_perm(h->lf[2 - d], perm[d].data());
       tw[d].assign(2 * (size_t)g.M[d], 0.0f);
       bb::line_fft_twiddles(h->lf[2 - d], tw[d].data());
+      if (h->lf[2 - d].direct) {
+        dft[d].assign(2 * (size_t)g.N[d] * g.win_len[d], 0.0f);
+        bb::line_dft_table(h->lf[2 - d], psi[d].data(), dft[d].data());
+      }
     }
   hipStream_t s = ctx->stream;
   if (bb_host::debug_fill() && (bb::launch_fill_poison(h->tws, lay.t_total, s) != hipSuccess ||
@@ -641,7 +649,9 @@ bb_status create_one(bb_context ctx, const bb_nufft_options* opt, int64_t n_pix,
   for (int d = 0; d < 3 && line_fft; ++d)
     if (hipMemcpyAsync(pnat<int>(h, lay.perm[d]), perm[d].data(), 4 * perm[d].size(), hipMemcpyHostToDevice, s) !=
             hipSuccess ||
-        hipMemcpyAsync(pnat<float>(h, lay.tw[d]), tw[d].data(), 4 * tw[d].size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        hipMemcpyAsync(pnat<float>(h, lay.tw[d]), tw[d].data(), 4 * tw[d].size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        (!dft[d].empty() && hipMemcpyAsync(pnat<float>(h, lay.dft[d]), dft[d].data(), 4 * dft[d].size(),
+                                           hipMemcpyHostToDevice, s) != hipSuccess))
       return bail("table upload failed");
   // pageable sources: each copy is staged before the call returns
   if (hipMemcpyAsync(pnat<float>(h, lay.psi0), psi[0].data(), 4 * psi[0].size(), hipMemcpyHostToDevice, s) != hipSuccess ||
@@ -949,13 +959,17 @@ bb_status bb_nufft_emit(bb_nufft h) {
     if (h->line_fft) {
       // axis 2: grid -> A'; axis 1: A' -> B; B -> B' (transpose); axis 0: B' -> C
       const int64_t w1 = g.win_len[1], w2 = g.win_len[2];
-      BB_HIP(ctx, bb::launch_line_fft(h->lf[0], level_grid, psi[2], pnat<int>(h, h->lay.perm[2]),
-                                      pnat<float2>(h, h->lay.tw[2]), ac, s));
-      BB_HIP(ctx, bb::launch_line_fft(h->lf[1], ac, psi[1], pnat<int>(h, h->lay.perm[1]), pnat<float2>(h, h->lay.tw[1]),
-                                      b, s));
+      auto line = [&](int st, const void* in, void* out) {
+        const int d = 2 - st;
+        return h->lf[st].direct
+                   ? bb::launch_line_dft(h->lf[st], in, pnat<float2>(h, h->lay.dft[d]), out, s)
+                   : bb::launch_line_fft(h->lf[st], in, psi[d], pnat<int>(h, h->lay.perm[d]),
+                                         pnat<float2>(h, h->lay.tw[d]), out, s);
+      };
+      BB_HIP(ctx, line(0, level_grid, ac));
+      BB_HIP(ctx, line(1, ac, b));
       BB_HIP(ctx, bb::launch_transpose_c64(b, g.N[0], w2 * w1, ac, s));
-      BB_HIP(ctx, bb::launch_line_fft(h->lf[2], ac, psi[0], pnat<int>(h, h->lay.perm[0]), pnat<float2>(h, h->lay.tw[0]),
-                                      b, s));
+      BB_HIP(ctx, line(2, ac, b));
       il = {(int64_t)g.win_len[0], w1 * g.win_len[0], g.win_lo[0], g.win_len[0]};
       u = b;
     } else {

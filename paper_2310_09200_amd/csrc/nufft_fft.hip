@@ -1,4 +1,6 @@
-// Line FFTs of the NUFFT's pruned type-2 transform (gfx950).
+// Line FFTs of the NUFFT's pruned type-2 transform (gfx950).  Lines of at
+// most 64 points (the thin axis of a grid) are instead a direct pruned DFT on
+// MFMA (line_dft_kernel, at the end of this file).
 //
 // Each workgroup transforms one or more lines of L = M points held in LDS
 // (L 2,3,5-smooth, at most 16384).  A line's N stored inputs are placed at
@@ -228,7 +230,153 @@ __global__ __launch_bounds__(256) void transpose_c64_kernel(const float2* __rest
   }
 }
 
+// Lines of at most kLineDftMax points as a direct pruned DFT on MFMA: the
+// kept outputs of a block of 16 lines are one small dense product,
+//   D[n][line] = sum_k A[n][k] B[k][line],
+// B the lines' stored inputs as floats (k <-> float f of the line: re / im of
+// input f / 2), A the real form of the table T (complex64, n_in x win_len,
+// exp(+2 pi i f_i m_w / L) / psi_i): row n = 2 w + c gives the real (c = 0) or
+// imaginary (c = 1) part of output w, A[2w][2i] = Re T, A[2w][2i+1] = -Im T,
+// A[2w+1][2i] = Im T, A[2w+1][2i+1] = Re T.  One wave per 16-line block on
+// v_mfma_f32_16x16x4f32 (A lane l = row l % 16 of k = 4 s + l / 16; B lane l
+// = line l % 16; D register r of lane l = row 4 (l / 16) + r); K index
+// k = 4 s + q is float q STEPS + s of the line, so lane (line, q) reads STEPS
+// consecutive floats of its line and the table fragments stay in registers
+// for the whole kernel.  D registers r, r + 1 are the real and imaginary part
+// of one output: each lane stores whole complex values, 16 consecutive lines
+// at a time.  STEPS = 2 n_in / 4; at most 8 blocks of 16 output rows.
+template <int STEPS, int NBMAX>
+__global__ __launch_bounds__(256) void line_dft_kernel(LineFft p, const float2* __restrict__ in,
+                                                       const float2* __restrict__ tab, float2* __restrict__ out) {
+  typedef float f32x4_t __attribute__((ext_vector_type(4)));
+  // blocks of 16 lines per wave and step: all their inputs are requested
+  // before the first product, so that a wave keeps G x 2 KB of reads in flight
+  constexpr int G = 4;
+  const int lane = threadIdx.x & 63, q = lane >> 4, r16 = lane & 15;
+  const int wl = p.win_len, n_in = p.n_in;
+  const int nb = (2 * wl + 15) / 16;  // blocks of 16 output rows (wave-uniform, <= NBMAX)
+  float a[NBMAX][STEPS];
+#pragma unroll
+  for (int b = 0; b < NBMAX; ++b)
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) {
+      const int n = 16 * b + r16, w = n >> 1, cn = n & 1;
+      const int f = q * STEPS + s, i = f >> 1, cf = f & 1;
+      float v = 0.0f;
+      if (b < nb && w < wl && i < n_in) {
+        const float2 t = tab[i * wl + w];
+        v = cn == 0 ? (cf == 0 ? t.x : -t.y) : (cf == 0 ? t.y : t.x);
+      }
+      a[b][s] = v;
+    }
+  const int64_t n_blocks = (p.n_lines + 15) / 16;
+  const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t blk0 = wave0 * G; blk0 < n_blocks; blk0 += n_waves * G) {
+    float x[G][STEPS];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int64_t line = (blk0 + g) * 16 + r16;
+      const bool live = line < p.n_lines;
+      const float* const src = reinterpret_cast<const float*>(in + (live ? line : 0) * p.in_stride) + q * STEPS;
+      if constexpr (STEPS % 4 == 0) {  // 16-byte aligned runs: vector loads
+#pragma unroll
+        for (int s = 0; s < STEPS; s += 4) {
+          const float4 v = live ? *reinterpret_cast<const float4*>(src + s) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+          x[g][s] = v.x;
+          x[g][s + 1] = v.y;
+          x[g][s + 2] = v.z;
+          x[g][s + 3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) x[g][s] = live ? src[s] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int64_t line = (blk0 + g) * 16 + r16;
+      f32x4_t d[NBMAX];
+#pragma unroll
+      for (int b = 0; b < NBMAX; ++b) {
+        d[b] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+        if (b < nb)
+#pragma unroll
+          for (int s = 0; s < STEPS; ++s)
+            d[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[b][s], x[g][s], d[b], 0, 0, 0);
+      }
+      if (line >= p.n_lines) continue;
+      float2* dst;
+      int64_t wstride;
+      if (p.out_mode == 0) {
+        dst = out + line * p.out_stride;
+        wstride = 1;
+      } else {  // line = outer * t_inner + inner, stored at [outer][w][inner]
+        const int64_t outer = line / p.t_inner, inner = line - outer * p.t_inner;
+        dst = out + outer * wl * p.t_inner + inner;
+        wstride = p.t_inner;
+      }
+#pragma unroll
+      for (int b = 0; b < NBMAX; ++b)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {  // registers 2 h, 2 h + 1: output w = 8 b + 2 q + h
+          const int w = 8 * b + 2 * q + h;
+          if (b < nb && w < wl) dst[w * wstride] = make_float2(d[b][2 * h], d[b][2 * h + 1]);
+        }
+    }
+  }
+}
+
 }  // namespace
+
+void line_dft_table(const LineFft& p, const float* inv_psi, float* tab) {
+  const int half = p.n_in / 2;
+  for (int i = 0; i < p.n_in; ++i) {
+    const int f = i < half ? i : i - p.n_in;
+    for (int w = 0; w < p.win_len; ++w) {
+      const int m = (p.win_lo + w) % p.L;
+      // the angle's numerator reduced mod L first: exact in integers
+      const int64_t fm = (((int64_t)f * m) % p.L + p.L) % p.L;
+      const double a = 2.0 * M_PI * (double)fm / p.L;
+      tab[2 * ((size_t)i * p.win_len + w)] = (float)(std::cos(a) * inv_psi[i]);
+      tab[2 * ((size_t)i * p.win_len + w) + 1] = (float)(std::sin(a) * inv_psi[i]);
+    }
+  }
+}
+
+bool line_dft_fits(const LineFft& p) {
+  // 2 n_in floats per line in 4 lane groups (2 <= STEPS <= 16), at most 8 blocks of 16 output rows
+  return p.L <= kLineDftMax && p.n_in % 2 == 0 && p.n_in >= 4 && p.n_in <= 32 && p.win_len >= 1 &&
+         2 * p.win_len <= 128;
+}
+
+hipError_t launch_line_dft(const LineFft& p, const void* in, const float2* tab, void* out, hipStream_t s) {
+  if (p.n_lines <= 0) return hipSuccess;
+  if (!line_dft_fits(p)) return hipErrorInvalidValue;
+  // the vector loads of runs of 4 floats need 16-byte aligned lines
+  if ((p.n_in / 2) % 4 == 0 && ((p.in_stride * 8) % 16 != 0 || reinterpret_cast<uintptr_t>(in) % 16 != 0))
+    return hipErrorInvalidValue;
+  const int64_t waves = (p.n_lines + 63) / 64;  // four 16-line blocks per wave and step
+  const unsigned grid = (unsigned)std::min<int64_t>((waves + 3) / 4, 1 << 16);
+  const float2* const x = static_cast<const float2*>(in);
+  float2* const y = static_cast<float2*>(out);
+  const bool narrow = 2 * p.win_len <= 64;  // at most 4 blocks of 16 output rows
+#define BB_DFT_CASE(S)                                                                                  \
+  case S:                                                                                               \
+    if (narrow)                                                                                         \
+      hipLaunchKernelGGL((line_dft_kernel<S, 4>), dim3(grid), dim3(256), 0, s, p, x, tab, y);           \
+    else                                                                                                \
+      hipLaunchKernelGGL((line_dft_kernel<S, 8>), dim3(grid), dim3(256), 0, s, p, x, tab, y);           \
+    break;
+  switch (p.n_in / 2) {
+    BB_DFT_CASE(2) BB_DFT_CASE(3) BB_DFT_CASE(4) BB_DFT_CASE(5) BB_DFT_CASE(6) BB_DFT_CASE(7) BB_DFT_CASE(8)
+    BB_DFT_CASE(9) BB_DFT_CASE(10) BB_DFT_CASE(11) BB_DFT_CASE(12) BB_DFT_CASE(13) BB_DFT_CASE(14)
+    BB_DFT_CASE(15) BB_DFT_CASE(16)
+    default: return hipErrorInvalidValue;
+  }
+#undef BB_DFT_CASE
+  return hipGetLastError();
+}
 
 int line_fft_plan(int L, LineFft& p) {
   if (L < 2 || L > kLineFftMax) return -1;
