@@ -86,43 +86,106 @@ __global__ __launch_bounds__(256) void bwd_m_kernel(const BwdParams P) {
 // w contracts pixels 16 w .. 16 w + 15 of it as 8 steps of 32x32x2 MFMAs
 // (A = B phases, rows l; B = M, columns k):
 //   Re += Br Mr - Bi Mi,  Im += Br Mi + Bi Mr.
-// The four waves' partial tiles are summed in a fixed order at the end.
+// The next chunk's M and pixel coordinates are loaded into registers while
+// the current chunk is processed.  The four waves' partial tiles are summed
+// in a fixed order at the end.
 typedef float bwd_f32x16 __attribute__((ext_vector_type(16)));
+
+// One chunk's H block of a wave: H[l][p] += sum over 64 eigenpairs of
+// conj(W)[l][k] M[k][p] for pixels 32 blk .. 32 blk + 31, real part (PART 0:
+// Wr' Mr - Wi' Mi) or imaginary part (PART 1: Wr' Mi + Wi' Mr), W' = conj W.
+// PART is a template argument and the loop is unrolled whole, so that it holds
+// no branch: its LDS reads then run ahead of the MFMAs instead of each step
+// waiting for its own.
+template <int PART>
+__device__ __forceinline__ void h_chunk(bwd_f32x16& h, const float2 (*sW)[65], const float2 (*sM)[65], int blk,
+                                        int lane) {
+#pragma unroll
+  for (int st = 0; st < 32; ++st) {
+    const int kk = 2 * st + (lane >> 5);              // this lane's contraction row (eigenpair)
+    const float2 w = sW[lane & 31][kk];               // A operand: row l = lane % 32
+    const float2 m = sM[kk][32 * blk + (lane & 31)];  // B operand: column p = lane % 32 of the half
+    if (PART == 0) {
+      h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.x, m.x, h, 0, 0, 0);
+      h = __builtin_amdgcn_mfma_f32_32x32x2f32(-w.y, m.y, h, 0, 0, 0);
+    } else {
+      h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.x, m.y, h, 0, 0, 0);
+      h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.y, m.x, h, 0, 0, 0);
+    }
+  }
+}
+
+// One chunk's dW block of a wave: dW[l][k] += sum over the chunk's 64 pixels
+// of B[p][l] M[k][p] for eigenpairs 32 blk .. 32 blk + 31, real part (PART 0:
+// Br Mr - Bi Mi) or imaginary part (PART 1: Br Mi + Bi Mr).
+template <int PART>
+__device__ __forceinline__ void dw_chunk(bwd_f32x16& dw, const float2 (*sB)[32], const float2 (*sM)[65], int blk,
+                                         int lane) {
+#pragma unroll
+  for (int st = 0; st < 32; ++st) {
+    const int pp = 2 * st + (lane >> 5);
+    const float2 b = sB[pp][lane & 31];
+    const float2 m = sM[32 * blk + (lane & 31)][pp];
+    if (PART == 0) {
+      dw = __builtin_amdgcn_mfma_f32_32x32x2f32(b.x, m.x, dw, 0, 0, 0);
+      dw = __builtin_amdgcn_mfma_f32_32x32x2f32(-b.y, m.y, dw, 0, 0, 0);
+    } else {
+      dw = __builtin_amdgcn_mfma_f32_32x32x2f32(b.x, m.y, dw, 0, 0, 0);
+      dw = __builtin_amdgcn_mfma_f32_32x32x2f32(b.y, m.x, dw, 0, 0, 0);
+    }
+  }
+}
 
 __global__ __launch_bounds__(256) void bwd_dw_kernel(const BwdParams P) {
   __shared__ float2 sB[64][32];
-  __shared__ float2 sM[64][32];
-  __shared__ double sX[32][4];  // the tile's scaled antenna positions
+  __shared__ float2 sM[64][33];  // [pixel][eigenpair] (+1 pad: the staging writes run along pixels)
+  __shared__ double sP[3][64];   // the chunk's pixel coordinates
+  __shared__ double sX[32][4];   // the tile's scaled antenna positions
   const InstDesc& D = *P.desc;
   const int l0 = blockIdx.x * 32, k0 = blockIdx.y * 32, s = blockIdx.z;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   if (t < 128) (&sX[0][0])[t] = D.xs[4 * l0 + t];  // rows l0 .. l0 + 31 < L_pad
-  __syncthreads();
   const int64_t p0 = (int64_t)s * P.split_len;
   int64_t p1 = p0 + P.split_len;
   if (p1 > P.n_pix) p1 = P.n_pix;
+  const float* Er = P.E;
+  const float* Ei = P.E + (int64_t)P.K_alloc * P.n_pix;
+  // the next chunk's M (8 values per thread: eigenpair k0 + 4 j + t / 64,
+  // pixel t % 64; rows up to K_alloc hold M or zeros) and pixel coordinates
+  // (threads < 192: axis t / 64); lanes past the split load the split's last
+  // pixel and keep zeros
+  float2 mnext[8];
+  double pnext = 0.0;
+  auto load_chunk = [&](int64_t pc) {
+    const int64_t p = pc + (t & 63);
+    const bool p_ok = p < p1;
+    const int64_t pq = p_ok ? p : p1 - 1;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t e = (int64_t)(k0 + 4 * j + (t >> 6)) * P.n_pix + pq;
+      const float er = Er[e], ei = Ei[e];
+      mnext[j] = p_ok ? make_float2(er, ei) : make_float2(0.0f, 0.0f);
+    }
+    if (t < 192) pnext = p_ok ? P.pix[pq + (t >> 6) * P.pix_ld] : 0.0;
+  };
+  load_chunk(p0);
   bwd_f32x16 are, aim;
 #pragma unroll
   for (int r = 0; r < 16; ++r) are[r] = aim[r] = 0.0f;
-  const float* Er = P.E;
-  const float* Ei = P.E + (int64_t)P.K_alloc * P.n_pix;
   for (int64_t pc = p0; pc < p1; pc += 64) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sM[t & 63][4 * j + (t >> 6)] = mnext[j];
+    if (t < 192) sP[t >> 6][t & 63] = pnext;
+    __syncthreads();
+    if (pc + 64 < p1) load_chunk(pc + 64);  // workgroup-uniform
     // phases: 32 antennas x 64 pixels, 8 per thread (zero past the split)
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int i = t + 256 * j;
       const int pp = i >> 5, ll = i & 31;
-      const int64_t p = pc + pp;
-      float c = 0.0f, sn = 0.0f;
-      if (p < p1) phase_b(&sX[ll][0], P.pix[p], P.pix[p + P.pix_ld], P.pix[p + 2 * P.pix_ld], c, sn);
-      sB[pp][ll] = make_float2(c, sn);
-    }
-    for (int i = t; i < 64 * 32; i += 256) {
-      const int kk = i >> 6, pp = i & 63;
-      const int64_t p = pc + pp;
-      float2 m = make_float2(0.0f, 0.0f);
-      if (p < p1) m = make_float2(Er[(int64_t)(k0 + kk) * P.n_pix + p], Ei[(int64_t)(k0 + kk) * P.n_pix + p]);
-      sM[pp][kk] = m;
+      float c, sn;
+      phase_b(&sX[ll][0], sP[0][pp], sP[1][pp], sP[2][pp], c, sn);
+      sB[pp][ll] = pc + pp < p1 ? make_float2(c, sn) : make_float2(0.0f, 0.0f);
     }
     __syncthreads();
 #pragma unroll
@@ -163,16 +226,18 @@ __global__ __launch_bounds__(256) void bwd_dw_kernel(const BwdParams P) {
 }
 
 // dx partial: H_lp = sum_k conj(W_lk) M_kp on MFMA, then Im(H_lp B_lp) p
-// summed over the split's pixels.  grid (L_pad/32, n_split), 256 threads.  Per
-// 64-pixel chunk and 64-eigenpair slice, conj(W) [32 l][64 k] and M [64 k][64 p]
-// are staged in LDS; wave w computes one real 32 x 32 block of H: pixel half
+// summed over the split's pixels.  grid (L_pad/32, n_split), 256 threads.  The
+// work runs in steps (64-pixel chunk, 64-eigenpair slice); each step stages
+// conj(W) [32 l][64 k] and M [64 k][64 p] in LDS from registers loaded during
+// the step before.  Wave w computes one real 32 x 32 block of H: pixel half
 // w / 2, real part (w even: Wr Mr - Wi' Mi with W' = conj W) or imaginary part
-// (w odd: Wr' Mi + Wi' Mr).  The blocks go through LDS (pixel-major, rows
-// padded to 33) to the threads that own (antenna t % 32, pixels t / 32 + 8 j),
-// which evaluate the phases.
+// (w odd: Wr' Mi + Wi' Mr).  After a chunk's last slice the blocks go through
+// LDS (pixel-major, rows padded to 33) to the threads that own (antenna t % 32,
+// pixels t / 32 + 8 j), which evaluate the phases.
 __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
   __shared__ float2 sW[32][65];   // conj(W) for 32 antennas x 64 eigenpairs (+1 pad: column reads)
   __shared__ float2 sM[64][65];   // M for 64 eigenpairs x 64 pixels; then H re / im [2][64 p][33] floats
+  __shared__ double sP[3][64];    // the chunk's pixel coordinates
   __shared__ double sX[32][4];    // the tile's scaled antenna positions
   __shared__ double sh[3][256];
   const InstDesc& D = *P.desc;
@@ -181,58 +246,68 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
   const int tl = t & 31, tp = t >> 5;
   const int l = l0 + tl;
   if (t < 128) (&sX[0][0])[t] = D.xs[4 * l0 + t];  // rows l0 .. l0 + 31 < L_pad
-  const int blk = wave >> 1, part = wave & 1;  // this wave's H block: pixel half, re / im
+  // this wave's H block: pixel half, re / im (wave-uniform, held in scalar registers)
+  const int blk = __builtin_amdgcn_readfirstlane(wave >> 1), part = __builtin_amdgcn_readfirstlane(wave & 1);
   const int64_t p0 = (int64_t)s * P.split_len;
   int64_t p1 = p0 + P.split_len;
   if (p1 > P.n_pix) p1 = P.n_pix;
   const int K_pad = P.dyn->K_pad;
+  const int n_kc = K_pad > 64 ? (K_pad + 63) / 64 : 1;  // slices per chunk (one of zeros if K_pad = 0)
   const float* Er = P.E;
   const float* Ei = P.E + (int64_t)P.K_alloc * P.n_pix;
   const float* Wf = (const float*)P.W;
   float* const sH = reinterpret_cast<float*>(&sM[0][0]);  // [2 parts][64 p][33]
+  // The next step's M (16 values per thread: eigenpair 4 j + t / 64 of the
+  // slice, pixel t % 64), conj(W) (8 per thread: antenna t % 32, eigenpair
+  // t / 32 + 8 j of the slice, so that a wave reads 32 consecutive antennas
+  // of a column of W) and, for a new chunk, pixel coordinates.  Lanes outside
+  // the split, K_pad or the antennas load a valid address and keep zeros.
+  float2 mnext[16], wnext[8];
+  double pnext = 0.0;
+  auto load_step = [&](int64_t pc, int kc) {
+    const int64_t p = pc + (t & 63);
+    const bool p_ok = p < p1;
+    const int64_t pq = p_ok ? p : p1 - 1;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int k = kc + 4 * j + (t >> 6);
+      const int64_t e = (int64_t)(k < K_pad ? k : 0) * P.n_pix + pq;
+      const float er = Er[e], ei = Ei[e];
+      mnext[j] = (p_ok && k < K_pad) ? make_float2(er, ei) : make_float2(0.0f, 0.0f);
+    }
+    const bool l_ok = l0 + tl < P.L;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = kc + tp + 8 * j;
+      const int src = k < K_pad ? D.perm[k] : -1;
+      const bool ok = l_ok && src >= 0;
+      const float* w = Wf + 2 * ((int64_t)(ok ? src : 0) * P.L + (l_ok ? l0 + tl : 0));
+      const float wr = w[0], wi = w[1];
+      wnext[j] = ok ? make_float2(wr, -wi) : make_float2(0.0f, 0.0f);
+    }
+    if (kc == 0 && t < 192) pnext = p_ok ? P.pix[pq + (t >> 6) * P.pix_ld] : 0.0;
+  };
+  load_step(p0, 0);
   double gx = 0.0, gy = 0.0, gz = 0.0;
   for (int64_t pc = p0; pc < p1; pc += 64) {
     bwd_f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-    for (int kc = 0; kc < K_pad; kc += 64) {
-      // conj(W) does not depend on the pixels: with a single eigenpair slice it
-      // is staged by the first chunk only (no later pass writes sW)
-      for (int i = t; i < 32 * 64 && (K_pad > 64 || pc == p0); i += 256) {
-        const int ll = i >> 6, kk = i & 63;
-        const int k = kc + kk;
-        float2 wv = make_float2(0.0f, 0.0f);
-        if (l0 + ll < P.L && k < K_pad) {
-          const int src = D.perm[k];
-          if (src >= 0) {
-            const float* w = Wf + 2 * ((int64_t)src * P.L + l0 + ll);
-            wv = make_float2(w[0], -w[1]);
-          }
-        }
-        sW[ll][kk] = wv;
-      }
-      for (int i = t; i < 64 * 64; i += 256) {
-        const int kk = i >> 6, pp = i & 63;
-        const int k = kc + kk;
-        const int64_t p = pc + pp;
-        float2 m = make_float2(0.0f, 0.0f);
-        if (p < p1 && k < K_pad) m = make_float2(Er[(int64_t)k * P.n_pix + p], Ei[(int64_t)k * P.n_pix + p]);
-        sM[kk][pp] = m;
-      }
+    for (int kq = 0; kq < n_kc; ++kq) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) sM[4 * j + (t >> 6)][t & 63] = mnext[j];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sW[tl][tp + 8 * j] = wnext[j];
+      if (kq == 0 && t < 192) sP[t >> 6][t & 63] = pnext;
       __syncthreads();
-#pragma unroll 8
-      for (int st = 0; st < 32; ++st) {
-        const int kk = 2 * st + (lane >> 5);             // this lane's contraction row (eigenpair)
-        const float2 w = sW[lane & 31][kk];              // A operand: row l = lane % 32
-        const float2 m = sM[kk][32 * blk + (lane & 31)];  // B operand: column p = lane % 32 of the half
-        if (part == 0) {
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(w.x, m.x, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(-w.y, m.y, acc, 0, 0, 0);
-        } else {
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(w.x, m.y, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(w.y, m.x, acc, 0, 0, 0);
-        }
-      }
+      // the next step: the chunk's next slice, else the next chunk's first
+      const bool last = kq + 1 == n_kc;
+      const int64_t npc = last ? pc + 64 : pc;
+      if (npc < p1) load_step(npc, last ? 0 : 64 * (kq + 1));  // workgroup-uniform
+      if (part == 0)
+        h_chunk<0>(acc, sW, sM, blk, lane);
+      else
+        h_chunk<1>(acc, sW, sM, blk, lane);
       __syncthreads();
     }
     // register r of lane q holds H at (l, p) = (8 (r / 4) + 4 (q / 32) + r % 4, 32 blk + q % 32)
@@ -245,21 +320,20 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
     if (l < P.L) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
+        // pixels past the split add exact zeros (their M and hence H, and
+        // coordinates are 0)
         const int pp = tp + 8 * j;
-        const int64_t p = pc + pp;
-        if (p < p1) {
-          const double px = P.pix[p], py = P.pix[p + P.pix_ld], pz = P.pix[p + 2 * P.pix_ld];
-          float c, sn;
-          phase_b(&sX[tl][0], px, py, pz, c, sn);
-          const float hr = sH[pp * 33 + tl], hi = sH[(64 + pp) * 33 + tl];
-          const double v = (double)fmaf(hr, sn, hi * c);  // Im(H B)
-          gx += v * px;
-          gy += v * py;
-          gz += v * pz;
-        }
+        const double px = sP[0][pp], py = sP[1][pp], pz = sP[2][pp];
+        float c, sn;
+        phase_b(&sX[tl][0], px, py, pz, c, sn);
+        const float hr = sH[pp * 33 + tl], hi = sH[(64 + pp) * 33 + tl];
+        const double v = (double)fmaf(hr, sn, hi * c);  // Im(H B)
+        gx += v * px;
+        gy += v * py;
+        gz += v * pz;
       }
     }
-    __syncthreads();  // sH (in sM) is restaged by the next chunk
+    __syncthreads();  // sH (in sM) and sP are restaged by the next chunk
   }
   sh[0][t] = gx;
   sh[1][t] = gy;
@@ -305,8 +379,8 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
   // bank conflicts
   const int tl = t & 31, tp = t >> 5;
   const int l = l0 + tl;
-  const int blk = wave >> 1, part = wave & 1;
-  const bool dw_active = 32 * blk < P.K_alloc;  // wave-uniform: this wave's dW block exists
+  const int blk = __builtin_amdgcn_readfirstlane(wave >> 1), part = __builtin_amdgcn_readfirstlane(wave & 1);
+  const bool dw_active = 32 * blk < P.K_alloc;  // this wave's dW block exists
   const int64_t p0 = (int64_t)s * P.split_len;
   int64_t p1 = p0 + P.split_len;
   if (p1 > P.n_pix) p1 = P.n_pix;
@@ -317,7 +391,7 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
   float* const sH = reinterpret_cast<float*>(&sM[0][0]);  // [2 parts][64 p][33]
   if (t < 128) (&sX[0][0])[t] = D.xs[4 * l0 + t];            // rows l0 .. l0 + 31 < L_pad
   for (int i = t; i < 32 * 64; i += 256) {
-    const int ll = i >> 6, kk = i & 63;
+    const int ll = i & 31, kk = i >> 5;  // a wave reads 32 consecutive antennas of two columns of W
     float2 wv = make_float2(0.0f, 0.0f);
     if (l0 + ll < P.L && kk < K_pad) {
       const int src = D.perm[kk];
@@ -333,16 +407,22 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
   // are loaded into registers while the current chunk is processed
   float2 mnext[16];
   double pnext = 0.0;
+  // Every lane loads (pixels past the split and eigenpairs past K_pad from
+  // row 0 and the split's last pixel) and then zeroes what lies outside, so
+  // the loads carry no branches.
   auto load_chunk = [&](int64_t pc) {
     const int pp = t & 63;
     const int64_t p = pc + pp;
+    const bool p_ok = p < p1;
+    const int64_t pq = p_ok ? p : p1 - 1;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int kk = 4 * j + (t >> 6);
-      mnext[j] = (p < p1 && kk < K_pad) ? make_float2(Er[(int64_t)kk * P.n_pix + p], Ei[(int64_t)kk * P.n_pix + p])
-                                        : make_float2(0.0f, 0.0f);
+      const int64_t e = (int64_t)(kk < K_pad ? kk : 0) * P.n_pix + pq;
+      const float er = Er[e], ei = Ei[e];
+      mnext[j] = (p_ok && kk < K_pad) ? make_float2(er, ei) : make_float2(0.0f, 0.0f);
     }
-    if (t < 192) pnext = p < p1 ? P.pix[p + (t >> 6) * P.pix_ld] : 0.0;
+    if (t < 192) pnext = p_ok ? P.pix[pq + (t >> 6) * P.pix_ld] : 0.0;
   };
   load_chunk(p0);
   bwd_f32x16 dw;
@@ -359,43 +439,22 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
     for (int j = 0; j < 8; ++j) {
       const int i = t + 256 * j;
       const int pp = i >> 5, ll = i & 31;
-      float c = 0.0f, sn = 0.0f;
-      if (pc + pp < p1) phase_b(&sX[ll][0], sP[0][pp], sP[1][pp], sP[2][pp], c, sn);
-      sB[pp][ll] = make_float2(c, sn);
+      float c, sn;  // pixels past the split have coordinates 0 and get phases 0
+      phase_b(&sX[ll][0], sP[0][pp], sP[1][pp], sP[2][pp], c, sn);
+      sB[pp][ll] = pc + pp < p1 ? make_float2(c, sn) : make_float2(0.0f, 0.0f);
     }
     __syncthreads();
-    if (dw_active) {
-      // dW += B M^T over the chunk's pixels: Re = Br Mr - Bi Mi, Im = Br Mi + Bi Mr
-#pragma unroll 8
-      for (int st = 0; st < 32; ++st) {
-        const int pp = 2 * st + (lane >> 5);
-        const float2 b = sB[pp][lane & 31];
-        const float2 m = sM[32 * blk + (lane & 31)][pp];
-        if (part == 0) {
-          dw = __builtin_amdgcn_mfma_f32_32x32x2f32(b.x, m.x, dw, 0, 0, 0);
-          dw = __builtin_amdgcn_mfma_f32_32x32x2f32(-b.y, m.y, dw, 0, 0, 0);
-        } else {
-          dw = __builtin_amdgcn_mfma_f32_32x32x2f32(b.x, m.y, dw, 0, 0, 0);
-          dw = __builtin_amdgcn_mfma_f32_32x32x2f32(b.y, m.x, dw, 0, 0, 0);
-        }
-      }
-    }
-    // H = conj(W) M for this wave's pixel half
+    // dW += B M^T over the chunk's pixels, then H = conj(W) M for this wave's
+    // pixel half
     bwd_f32x16 h;
 #pragma unroll
     for (int r = 0; r < 16; ++r) h[r] = 0.0f;
-#pragma unroll 8
-    for (int st = 0; st < 32; ++st) {
-      const int kk = 2 * st + (lane >> 5);
-      const float2 w = sW[lane & 31][kk];
-      const float2 m = sM[kk][32 * blk + (lane & 31)];
-      if (part == 0) {
-        h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.x, m.x, h, 0, 0, 0);
-        h = __builtin_amdgcn_mfma_f32_32x32x2f32(-w.y, m.y, h, 0, 0, 0);
-      } else {
-        h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.x, m.y, h, 0, 0, 0);
-        h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.y, m.x, h, 0, 0, 0);
-      }
+    if (part == 0) {
+      if (dw_active) dw_chunk<0>(dw, sB, sM, blk, lane);
+      h_chunk<0>(h, sW, sM, blk, lane);
+    } else {
+      if (dw_active) dw_chunk<1>(dw, sB, sM, blk, lane);
+      h_chunk<1>(h, sW, sM, blk, lane);
     }
     __syncthreads();  // every wave is done with sM
 #pragma unroll
@@ -407,15 +466,15 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
     if (l < P.L) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
+        // pixels past the split add exact zeros (their phases, M and hence
+        // H, and coordinates are all 0)
         const int pp = tp + 8 * j;
-        if (pc + pp < p1) {
-          const float2 b = sB[pp][tl];
-          const float hr = sH[pp * 33 + tl], hi = sH[(64 + pp) * 33 + tl];
-          const double v = (double)fmaf(hr, b.y, hi * b.x);  // Im(H B)
-          gx += v * sP[0][pp];
-          gy += v * sP[1][pp];
-          gz += v * sP[2][pp];
-        }
+        const float2 b = sB[pp][tl];
+        const float hr = sH[pp * 33 + tl], hi = sH[(64 + pp) * 33 + tl];
+        const double v = (double)fmaf(hr, b.y, hi * b.x);  // Im(H B)
+        gx += v * sP[0][pp];
+        gy += v * sP[1][pp];
+        gz += v * sP[2][pp];
       }
     }
     __syncthreads();  // sB, sP and sM (holding H) are restaged by the next chunk

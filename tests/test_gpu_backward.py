@@ -62,6 +62,26 @@ def test_backward_matches_oracle_gradient(ctx, L, K, n_side):
     _compare(ctx, x, wl, pix, W, d, lev, wts, 3, 2e-4)
 
 
+@pytest.mark.parametrize("L,K,n_side,drop", [(130, 150, 37, False), (256, 128, 48, True), (64, 96, 21, False)])
+def test_backward_several_slices(ctx, L, K, n_side, drop):
+    """More than 64 kept eigenpairs: the two-kernel path with 2-3 eigenpair slices per chunk, ragged L and pixels."""
+    say(f"case backward slices L={L} K={K} n_side={n_side} drop={drop}")
+    x, wl, pix, W, d, lev, wts = _case(L, K, n_side, 11 + L, drop=drop)
+    _compare(ctx, x, wl, pix, W, d, lev, wts, 3, 2e-4)
+
+
+def test_backward_nothing_kept(ctx):
+    """Every eigenpair outside every level (K_alloc > 64): all gradients are exactly zero."""
+    from paper_2310_09200_amd import StandardSynthesis
+    say("case backward nothing kept")
+    x, wl, pix, W, d, lev, wts = _case(40, 80, 20, 3)
+    lev[:] = -1
+    s = StandardSynthesis(ctx, pix, 3, 1, 40, 80)
+    dW, dd, dx = (t.cpu().numpy() for t in s.eig_backward(x, wl, W, d, lev, wts))
+    s.close()
+    assert np.all(dW == 0) and np.all(dd == 0) and np.all(dx == 0)
+
+
 def test_backward_c5_full_size(ctx):
     """C5: L=256, K=64 top eigenpairs, 512^2 pixels, 4 levels, loss weights w ~ N(0,1)."""
     say("case backward C5 full size")
