@@ -341,9 +341,10 @@ def measure_c5_backward(args, torch, ctx):
     log(f"C5: forward {f_ms:.3f} ms, backward {b_ms:.3f} ms")
     return {"workload": "L=256, K=64, 512x512 pixels, 4 levels, loss weights N(0,1) per level and pixel",
             "forward_ms": f_ms, "backward_ms": b_ms, "products": prods,
-            "backward_note": "E recompute (FP32 MFMA) + dd/M, dW = 2 B M^T and H = conj(W) M on FP32 MFMA (one fused "
-                             "kernel at K <= 64) -> dx; about 3x the forward's complex MACs",
-            "backward_fp32_mfma_fraction": 3 * 8.0 * prods / (b_ms / 1e3) / (FP32_PEAK_TFLOPS * 1e12)}
+            "backward_note": "E recompute (FP32 MFMA, three products) + dd/M, dW = 2 B M^T and H = conj(W) M on FP32 "
+                             "MFMA (one fused kernel at K <= 64) -> dx; three times the forward's complex MACs, "
+                             "executed as 6 + 8 + 8 = 22 flop per product",
+            "backward_fp32_mfma_fraction": 22.0 * prods / (b_ms / 1e3) / (FP32_PEAK_TFLOPS * 1e12)}
 
 
 def measure_nufft(args, torch, ctx):

@@ -1314,7 +1314,8 @@ bb_status bb_synth_eig_backward(bb_synth h, int32_t n_ant, int32_t n_eig, double
   BB_HIP(ctx, hipEventRecord(h->ev[1], s));
   hipLaunchKernelGGL(write_meta_kernel, dim3(1), dim3(1), 0, s, meta, dsc, 0);
   BB_HIP(ctx, hipGetLastError());
-  BB_HIP(ctx, bb::launch_stage(&meta->desc, &meta->dyn, 1, dsc.K_alloc, dsc.L_pad, h->opt.n_levels, 0,
+  // three planes: the recompute of E runs the three-product FP32 form
+  BB_HIP(ctx, bb::launch_stage(&meta->desc, &meta->dyn, 1, dsc.K_alloc, dsc.L_pad, h->opt.n_levels, 2,
                                at<int>(h, h->lay.err), s));
   BB_HIP(ctx, hipEventRecord(h->ev[2], s));
   bb::FwdParams p{};

@@ -274,7 +274,8 @@ hipError_t launch_nufft_spread_tiles(const NufftGeom& g, const NufftInst* insts,
                                      int* nch, int* choff, float* grid, int64_t n_cell, hipStream_t s);
 
 // Backward.
-// E recompute (FP32 MFMA, one instance) into two planes [2][K_alloc][n_pix].
+// E recompute (FP32 MFMA, three-product form, one instance staged as three
+// planes) into two planes [2][K_alloc][n_pix].
 hipError_t launch_fields(const FwdParams& p, int K_alloc, hipStream_t s);
 int fields_tile_pixels(int K_alloc);
 

@@ -8,7 +8,7 @@
 //   dW_lk = 2 sum_p B_lp M_kp            (d/dRe W + j d/dIm W)
 //   H_lp  = sum_k conj(W_lk) M_kp
 //   dx_l  = -(4 pi / lambda_w) sum_p Im(H_lp B_lp) p
-// E is recomputed by the forward MFMA kernel (FP32) into HBM; the
+// E is recomputed by the forward MFMA kernel (FP32, three products) into HBM; the
 // contractions dW and H run on FP32 MFMA (32x32x2), in one kernel sharing its
 // staged phases and M when every eigenpair fits one 64-wide slice, in two
 // otherwise.  The kernels work in level-sorted eigenpair order (the staging

@@ -1290,15 +1290,21 @@ hipError_t launch_synth(const FwdParams& p, int max_K_alloc, int precision, int 
   return launch_synth_tile(p, precision, synth_default_tile(precision, synth_k_class(max_K_alloc)), s);
 }
 
-int fields_tile_pixels(int K_alloc) { return synth_tile_pixels(K_alloc, 0); }
+// FP32 recompute of E for the backward pass, in the three-product form
+// whatever the handle's precision (the instance is staged as three planes), on
+// 32-row tiles (the 16-row kernel writes no E), one per K class so that no
+// k-block wave idles: K <= 32: 32 x 256, <= 64: 64 x 256, <= 128: 128 x 128,
+// above: 256 x 64.
+using FieldsL = TileList<TileCfg<1, 1, 1, 8>, TileCfg<1, 2, 2, 4>, TileCfg<1, 2, 4, 2>, TileCfg<1, 2, 8, 1>>;
+
+int fields_tile_pixels(int K_alloc) {
+  int nt = 0;
+  tile_at<0>(synth_k_class(K_alloc), [&](auto cfg) { nt = decltype(cfg)::NT; return hipSuccess; }, FieldsL{});
+  return nt;
+}
 
 hipError_t launch_fields(const FwdParams& p, int K_alloc, hipStream_t s) {
-  // FP32 recompute of E for the backward pass (the handle's precision does not
-  // apply), in the forward's default tile shape for this K: no idle k-block waves
-  using FieldsL = TileList<TileCfg<1, 4, 8, 1>, TileCfg<1, 4, 4, 2>, TileCfg<1, 2, 2, 4>, TileCfg<1, 2, 1, 4>>;
-  static_assert(Cands<0>::dflt[0] == 3 && Cands<0>::dflt[3] == 0, "the defaults of 4-product tiles lead the list");
-  return tile_at<0>(synth_default_tile(0, synth_k_class(K_alloc)), [&](auto cfg) { return launch_tc<0, 1>(p, cfg, s); },
-                    FieldsL{});
+  return tile_at<0>(synth_k_class(K_alloc), [&](auto cfg) { return launch_tc<2, 1>(p, cfg, s); }, FieldsL{});
 }
 
 // Phase-generation throughput probe (measurement only): every thread takes one
