@@ -1252,8 +1252,10 @@ BwdPlan plan_backward(int64_t n_pix, int n_ant, int n_eig) {
   BwdPlan b{};
   b.L_pad = bb::round_up(n_ant, bb::kAntChunk);
   b.K_alloc = bb::round_up(n_eig, 32);
-  const int64_t tiles = (int64_t)(b.L_pad / 32) * (b.K_alloc / 32);
-  int64_t want = (1024 + tiles - 1) / tiles;
+  // pixel splits: the fused and dx kernels run (L_pad / 32) x n_split
+  // workgroups, two of which fit a CU; 512 of them fill the 256 CUs
+  const int64_t lblocks = b.L_pad / 32;
+  int64_t want = (512 + lblocks - 1) / lblocks;
   const int64_t max_split = (n_pix + 63) / 64;
   if (want > max_split) want = max_split;
   if (want < 1) want = 1;

@@ -80,15 +80,18 @@ __global__ __launch_bounds__(256) void bwd_m_kernel(const BwdParams P) {
   if (threadIdx.x == 0) P.dd_part[(int64_t)k * P.n_split + s] = t;
 }
 
-// dW partial: sum over the split's pixels of B_lp M_kp for a 32 x 32 (l, k)
-// tile, on MFMA.  grid (L_pad/32, K_alloc/32, n_split), 256 threads.  Each
-// 64-pixel chunk stages phases [64 px][32 l] and M [64 px][32 k] in LDS; wave
-// w contracts pixels 16 w .. 16 w + 15 of it as 8 steps of 32x32x2 MFMAs
-// (A = B phases, rows l; B = M, columns k):
+// dW partial: sum over the split's pixels of B_lp M_kp for a 32 x 64 (l, k)
+// tile of two 32-eigenpair blocks, on MFMA.  grid (L_pad/32,
+// ceil(K_alloc/64), n_split), 256 threads.  Each 64-pixel chunk stages
+// phases [64 px][32 l] and M [64 px][64 k] in LDS; wave w contracts pixels
+// 16 w .. 16 w + 15 of it as 8 steps of 32x32x2 MFMAs per block (A = B
+// phases, rows l; B = M, columns k):
 //   Re += Br Mr - Bi Mi,  Im += Br Mi + Bi Mr.
-// The next chunk's M and pixel coordinates are loaded into registers while
-// the current chunk is processed.  The four waves' partial tiles are summed
-// in a fixed order at the end.
+// Two blocks per workgroup share each phase evaluation; the second is absent
+// (workgroup-uniform) when K_alloc is an odd multiple of 32.  The next
+// chunk's M and pixel coordinates are loaded into registers while the
+// current chunk is processed.  The four waves' partial tiles are summed in a
+// fixed order at the end.
 typedef float bwd_f32x16 __attribute__((ext_vector_type(16)));
 
 // One chunk's H block of a wave: H[l][p] += sum over 64 eigenpairs of
@@ -136,13 +139,32 @@ __device__ __forceinline__ void dw_chunk(bwd_f32x16& dw, const float2 (*sB)[32],
   }
 }
 
+// One chunk's dW steps of a wave for both eigenpair blocks.
+__device__ __forceinline__ void dw2_chunk(bwd_f32x16 (&are)[2], bwd_f32x16 (&aim)[2], const float2 (*sB)[32],
+                                          const float2 (*sM)[65], int wave, int lane) {
+#pragma unroll
+  for (int st = 0; st < 8; ++st) {
+    const int pp = 16 * wave + 2 * st + (lane >> 5);  // this lane's contraction row (pixel)
+    const float2 b = sB[pp][lane & 31];               // A operand: row l = lane % 32
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const float2 m = sM[pp][32 * q + (lane & 31)];  // B operand: column k = lane % 32 of block q
+      are[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(b.x, m.x, are[q], 0, 0, 0);
+      are[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(-b.y, m.y, are[q], 0, 0, 0);
+      aim[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(b.x, m.y, aim[q], 0, 0, 0);
+      aim[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(b.y, m.x, aim[q], 0, 0, 0);
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void bwd_dw_kernel(const BwdParams P) {
   __shared__ float2 sB[64][32];
-  __shared__ float2 sM[64][33];  // [pixel][eigenpair] (+1 pad: the staging writes run along pixels)
+  __shared__ float2 sM[64][65];  // [pixel][eigenpair] (+1 pad: the staging writes run along pixels)
   __shared__ double sP[3][64];   // the chunk's pixel coordinates
   __shared__ double sX[32][4];   // the tile's scaled antenna positions
   const InstDesc& D = *P.desc;
-  const int l0 = blockIdx.x * 32, k0 = blockIdx.y * 32, s = blockIdx.z;
+  const int l0 = blockIdx.x * 32, k0 = blockIdx.y * 64, s = blockIdx.z;
+  const bool two = k0 + 32 < P.K_alloc;  // the second eigenpair block exists
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   if (t < 128) (&sX[0][0])[t] = D.xs[4 * l0 + t];  // rows l0 .. l0 + 31 < L_pad
   const int64_t p0 = (int64_t)s * P.split_len;
@@ -150,31 +172,34 @@ __global__ __launch_bounds__(256) void bwd_dw_kernel(const BwdParams P) {
   if (p1 > P.n_pix) p1 = P.n_pix;
   const float* Er = P.E;
   const float* Ei = P.E + (int64_t)P.K_alloc * P.n_pix;
-  // the next chunk's M (8 values per thread: eigenpair k0 + 4 j + t / 64,
-  // pixel t % 64; rows up to K_alloc hold M or zeros) and pixel coordinates
-  // (threads < 192: axis t / 64); lanes past the split load the split's last
-  // pixel and keep zeros
-  float2 mnext[8];
+  // the next chunk's M (16 values per thread: eigenpair k0 + 4 j + t / 64,
+  // pixel t % 64; rows up to K_alloc hold M or zeros, an absent second block
+  // reads row k0 and keeps zeros) and pixel coordinates (threads < 192: axis
+  // t / 64); lanes past the split load the split's last pixel and keep zeros
+  float2 mnext[16];
   double pnext = 0.0;
   auto load_chunk = [&](int64_t pc) {
     const int64_t p = pc + (t & 63);
     const bool p_ok = p < p1;
     const int64_t pq = p_ok ? p : p1 - 1;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int64_t e = (int64_t)(k0 + 4 * j + (t >> 6)) * P.n_pix + pq;
+    for (int j = 0; j < 16; ++j) {
+      const bool k_ok = j < 8 || two;
+      const int64_t e = (int64_t)(k0 + (k_ok ? 4 * j + (t >> 6) : 0)) * P.n_pix + pq;
       const float er = Er[e], ei = Ei[e];
-      mnext[j] = p_ok ? make_float2(er, ei) : make_float2(0.0f, 0.0f);
+      mnext[j] = (p_ok && k_ok) ? make_float2(er, ei) : make_float2(0.0f, 0.0f);
     }
     if (t < 192) pnext = p_ok ? P.pix[pq + (t >> 6) * P.pix_ld] : 0.0;
   };
   load_chunk(p0);
-  bwd_f32x16 are, aim;
+  bwd_f32x16 are[2], aim[2];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) are[r] = aim[r] = 0.0f;
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) are[q][r] = aim[q][r] = 0.0f;
   for (int64_t pc = p0; pc < p1; pc += 64) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) sM[t & 63][4 * j + (t >> 6)] = mnext[j];
+    for (int j = 0; j < 16; ++j) sM[t & 63][4 * j + (t >> 6)] = mnext[j];
     if (t < 192) sP[t >> 6][t & 63] = pnext;
     __syncthreads();
     if (pc + 64 < p1) load_chunk(pc + 64);  // workgroup-uniform
@@ -188,40 +213,36 @@ __global__ __launch_bounds__(256) void bwd_dw_kernel(const BwdParams P) {
       sB[pp][ll] = pc + pp < p1 ? make_float2(c, sn) : make_float2(0.0f, 0.0f);
     }
     __syncthreads();
-#pragma unroll
-    for (int st = 0; st < 8; ++st) {
-      const int pp = 16 * wave + 2 * st + (lane >> 5);  // this lane's contraction row (pixel)
-      const float2 b = sB[pp][lane & 31];               // A operand: row l = lane % 32
-      const float2 m = sM[pp][lane & 31];               // B operand: column k = lane % 32
-      are = __builtin_amdgcn_mfma_f32_32x32x2f32(b.x, m.x, are, 0, 0, 0);
-      are = __builtin_amdgcn_mfma_f32_32x32x2f32(-b.y, m.y, are, 0, 0, 0);
-      aim = __builtin_amdgcn_mfma_f32_32x32x2f32(b.x, m.y, aim, 0, 0, 0);
-      aim = __builtin_amdgcn_mfma_f32_32x32x2f32(b.y, m.x, aim, 0, 0, 0);
-    }
+    dw2_chunk(are, aim, sB, sM, wave, lane);  // an absent second block multiplies zeros
     __syncthreads();
   }
-  // fixed-order sum of the four waves' tiles: wave w's register r of lane q
-  // holds (l, k) = (8 (r / 4) + 4 (q / 32) + r % 4, q % 32)
+  // fixed-order sum of the four waves' tiles, one block at a time: wave w's
+  // register r of lane q holds (l, k) = (8 (r / 4) + 4 (q / 32) + r % 4, q % 32)
   float* const red = reinterpret_cast<float*>(&sB[0][0]);  // [4 waves][16 regs][64 lanes] re, then im in sM
   float* const redi = reinterpret_cast<float*>(&sM[0][0]);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    red[(wave * 16 + r) * 64 + lane] = are[r];
-    redi[(wave * 16 + r) * 64 + lane] = aim[r];
-  }
-  __syncthreads();
-  for (int i = t; i < 16 * 64; i += 256) {
-    const int r = i >> 6, q = i & 63;
-    double re = 0.0, im = 0.0;
+  for (int b = 0; b < 2; ++b) {
+    if (b == 1 && !two) break;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      re += red[(w * 16 + r) * 64 + q];
-      im += redi[(w * 16 + r) * 64 + q];
+    for (int r = 0; r < 16; ++r) {
+      red[(wave * 16 + r) * 64 + lane] = are[b][r];
+      redi[(wave * 16 + r) * 64 + lane] = aim[b][r];
     }
-    const int l = 8 * (r >> 2) + 4 * (q >> 5) + (r & 3), k = q & 31;
-    double* out = P.dW_part + (((int64_t)s * P.L_pad + (l0 + l)) * P.K_alloc + k0 + k) * 2;
-    out[0] = re;
-    out[1] = im;
+    __syncthreads();
+    for (int i = t; i < 16 * 64; i += 256) {
+      const int r = i >> 6, q = i & 63;
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        re += red[(w * 16 + r) * 64 + q];
+        im += redi[(w * 16 + r) * 64 + q];
+      }
+      const int l = 8 * (r >> 2) + 4 * (q >> 5) + (r & 3), k = 32 * b + (q & 31);
+      double* out = P.dW_part + (((int64_t)s * P.L_pad + (l0 + l)) * P.K_alloc + k0 + k) * 2;
+      out[0] = re;
+      out[1] = im;
+    }
+    __syncthreads();
   }
 }
 
@@ -240,6 +261,7 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
   __shared__ double sP[3][64];    // the chunk's pixel coordinates
   __shared__ double sX[32][4];    // the tile's scaled antenna positions
   __shared__ double sh[3][256];
+  __shared__ int sPerm[kMaxEig];  // staged eigenpair -> the caller's column of W
   const InstDesc& D = *P.desc;
   const int l0 = blockIdx.x * 32, s = blockIdx.y;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -279,7 +301,7 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int k = kc + tp + 8 * j;
-      const int src = k < K_pad ? D.perm[k] : -1;
+      const int src = k < K_pad ? sPerm[k] : -1;
       const bool ok = l_ok && src >= 0;
       const float* w = Wf + 2 * ((int64_t)(ok ? src : 0) * P.L + (l_ok ? l0 + tl : 0));
       const float wr = w[0], wi = w[1];
@@ -287,6 +309,8 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
     }
     if (kc == 0 && t < 192) pnext = p_ok ? P.pix[pq + (t >> 6) * P.pix_ld] : 0.0;
   };
+  for (int k = t; k < K_pad; k += 256) sPerm[k] = D.perm[k];
+  __syncthreads();
   load_step(p0, 0);
   double gx = 0.0, gy = 0.0, gz = 0.0;
   for (int64_t pc = p0; pc < p1; pc += 64) {
@@ -556,7 +580,7 @@ hipError_t launch_backward(const BwdParams& p, hipStream_t s) {
     hipLaunchKernelGGL(bwd_fused_kernel, dim3(p.L_pad / 32, p.n_split), dim3(256), 0, s, p);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(bwd_dw_kernel, dim3(p.L_pad / 32, p.K_alloc / 32, p.n_split), dim3(256), 0, s, p);
+  hipLaunchKernelGGL(bwd_dw_kernel, dim3(p.L_pad / 32, (p.K_alloc + 63) / 64, p.n_split), dim3(256), 0, s, p);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(bwd_dx_kernel, dim3(p.L_pad / 32, p.n_split), dim3(256), 0, s, p);
