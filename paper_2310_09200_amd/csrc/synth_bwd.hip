@@ -118,12 +118,33 @@ __device__ __forceinline__ void h_chunk(bwd_f32x16& h, const float2 (*sW)[65], c
   }
 }
 
+// h_chunk for a W that stays the same over the chunks: the real part takes
+// -Wi' from registers (wny[st] for this lane's row of step st), loaded once.
+template <int PART>
+__device__ __forceinline__ void h_chunk_w(bwd_f32x16& h, const float2 (*sW)[65], const float (&wny)[32],
+                                          const float2 (*sM)[65], int blk, int lane) {
+#pragma unroll
+  for (int st = 0; st < 32; ++st) {
+    const int kk = 2 * st + (lane >> 5);
+    const float2 m = sM[kk][32 * blk + (lane & 31)];
+    if (PART == 0) {
+      h = __builtin_amdgcn_mfma_f32_32x32x2f32(sW[lane & 31][kk].x, m.x, h, 0, 0, 0);
+      h = __builtin_amdgcn_mfma_f32_32x32x2f32(wny[st], m.y, h, 0, 0, 0);
+    } else {
+      const float2 w = sW[lane & 31][kk];
+      h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.x, m.y, h, 0, 0, 0);
+      h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.y, m.x, h, 0, 0, 0);
+    }
+  }
+}
+
 // One chunk's dW block of a wave: dW[l][k] += sum over the chunk's 64 pixels
 // of B[p][l] M[k][p] for eigenpairs 32 blk .. 32 blk + 31, real part (PART 0:
 // Br Mr - Bi Mi) or imaginary part (PART 1: Br Mi + Bi Mr).
+// The real part takes -Bi from the staged plane sBn (no negation per step).
 template <int PART>
-__device__ __forceinline__ void dw_chunk(bwd_f32x16& dw, const float2 (*sB)[32], const float2 (*sM)[65], int blk,
-                                         int lane) {
+__device__ __forceinline__ void dw_chunk(bwd_f32x16& dw, const float2 (*sB)[32], const float (*sBn)[32],
+                                         const float2 (*sM)[65], int blk, int lane) {
 #pragma unroll
   for (int st = 0; st < 32; ++st) {
     const int pp = 2 * st + (lane >> 5);
@@ -131,7 +152,7 @@ __device__ __forceinline__ void dw_chunk(bwd_f32x16& dw, const float2 (*sB)[32],
     const float2 m = sM[32 * blk + (lane & 31)][pp];
     if (PART == 0) {
       dw = __builtin_amdgcn_mfma_f32_32x32x2f32(b.x, m.x, dw, 0, 0, 0);
-      dw = __builtin_amdgcn_mfma_f32_32x32x2f32(-b.y, m.y, dw, 0, 0, 0);
+      dw = __builtin_amdgcn_mfma_f32_32x32x2f32(sBn[pp][lane & 31], m.y, dw, 0, 0, 0);
     } else {
       dw = __builtin_amdgcn_mfma_f32_32x32x2f32(b.x, m.y, dw, 0, 0, 0);
       dw = __builtin_amdgcn_mfma_f32_32x32x2f32(b.y, m.x, dw, 0, 0, 0);
@@ -392,9 +413,9 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
   __shared__ float2 sW[32][65];   // conj(W) [32 l][64 k], staged once (+1 pad: column reads)
   __shared__ float2 sM[64][65];   // M [64 k][64 p] (+1 pad: column reads); then H re / im [2][64 p][33] floats
   __shared__ float2 sB[64][32];   // phases [64 p][32 l]
+  __shared__ float sBn[64][32];   // their negated sines
   __shared__ double sP[3][64];    // the chunk's pixel coordinates
   __shared__ double sX[32][4];    // the tile's scaled antenna positions, staged once
-  __shared__ double sh[3][256];
   const InstDesc& D = *P.desc;
   const int l0 = blockIdx.x * 32, s = blockIdx.y;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -449,6 +470,12 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
     if (t < 192) pnext = p_ok ? P.pix[pq + (t >> 6) * P.pix_ld] : 0.0;
   };
   load_chunk(p0);
+  // -Im conj(W) of this lane's rows, for the real part of H (waves of part 0)
+  float wny[32];
+  __syncthreads();  // conj(W) is staged
+  if (part == 0)
+#pragma unroll
+    for (int st = 0; st < 32; ++st) wny[st] = -sW[lane & 31][2 * st + (lane >> 5)].y;
   bwd_f32x16 dw;
 #pragma unroll
   for (int r = 0; r < 16; ++r) dw[r] = 0.0f;
@@ -465,7 +492,9 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
       const int pp = i >> 5, ll = i & 31;
       float c, sn;  // pixels past the split have coordinates 0 and get phases 0
       phase_b(&sX[ll][0], sP[0][pp], sP[1][pp], sP[2][pp], c, sn);
-      sB[pp][ll] = pc + pp < p1 ? make_float2(c, sn) : make_float2(0.0f, 0.0f);
+      const bool ok = pc + pp < p1;
+      sB[pp][ll] = ok ? make_float2(c, sn) : make_float2(0.0f, 0.0f);
+      sBn[pp][ll] = ok ? -sn : 0.0f;
     }
     __syncthreads();
     // dW += B M^T over the chunk's pixels, then H = conj(W) M for this wave's
@@ -474,11 +503,11 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) h[r] = 0.0f;
     if (part == 0) {
-      if (dw_active) dw_chunk<0>(dw, sB, sM, blk, lane);
-      h_chunk<0>(h, sW, sM, blk, lane);
+      if (dw_active) dw_chunk<0>(dw, sB, sBn, sM, blk, lane);
+      h_chunk_w<0>(h, sW, wny, sM, blk, lane);
     } else {
-      if (dw_active) dw_chunk<1>(dw, sB, sM, blk, lane);
-      h_chunk<1>(h, sW, sM, blk, lane);
+      if (dw_active) dw_chunk<1>(dw, sB, sBn, sM, blk, lane);
+      h_chunk_w<1>(h, sW, wny, sM, blk, lane);
     }
     __syncthreads();  // every wave is done with sM
 #pragma unroll
@@ -510,16 +539,17 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
       P.dW_part[(((int64_t)s * P.L_pad + (l0 + ll)) * P.K_alloc + k) * 2 + part] = dw[r];
     }
   }
-  sh[0][t] = gx;
-  sh[1][t] = gy;
-  sh[2][t] = gz;
+  double* const sh = reinterpret_cast<double*>(&sM[0][0]);  // [3][256]; sM is free after the loop
+  sh[t] = gx;
+  sh[256 + t] = gy;
+  sh[512 + t] = gz;
   __syncthreads();
   if (tp == 0 && l < P.L_pad) {
     double a = 0, b = 0, c = 0;
     for (int j = 0; j < 8; ++j) {
-      a += sh[0][t + 32 * j];
-      b += sh[1][t + 32 * j];
-      c += sh[2][t + 32 * j];
+      a += sh[t + 32 * j];
+      b += sh[256 + t + 32 * j];
+      c += sh[512 + t + 32 * j];
     }
     double* o = P.dx_part + ((int64_t)s * P.L_pad + l) * 3;
     o[0] = a;
