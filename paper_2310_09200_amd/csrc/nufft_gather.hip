@@ -77,22 +77,23 @@ __device__ __forceinline__ float row_bcast(int v) {
 
 // acc[L] += wgt * level value L, whose real and imaginary words are words
 // 2L and 2L + 1 of the row's level data (c0: words 0..15, c1: words 16..31);
-// levels past the plan's count carry zeros.
-template <int L>
-__device__ __forceinline__ void add_level(float2 (&acc)[kMaxLevels], float wgt, int c0, int c1) {
-  if constexpr (2 * L < 16) {
-    acc[L].x += wgt * row_bcast<2 * L>(c0);
-    acc[L].y += wgt * row_bcast<2 * L + 1>(c0);
-  } else {
-    acc[L].x += wgt * row_bcast<2 * L - 16>(c1);
-    acc[L].y += wgt * row_bcast<2 * L - 15>(c1);
-  }
+// levels past the plan's count carry zeros.  All words are broadcast first,
+// each into a register of its own, and then multiplied in: a broadcast into
+// the register a multiply-add has just read costs wait states.
+template <int W>
+__device__ __forceinline__ float level_word(int c0, int c1) {
+  if constexpr (W < 16)
+    return row_bcast<W>(c0);
+  else
+    return row_bcast<W - 16>(c1);
 }
 
 template <size_t... L>
 __device__ __forceinline__ void add_levels(float2 (&acc)[kMaxLevels], float wgt, int c0, int c1,
                                            std::index_sequence<L...>) {
-  (add_level<(int)L>(acc, wgt, c0, c1), ...);
+  const float vr[] = {level_word<2 * (int)L>(c0, c1)...};
+  const float vi[] = {level_word<2 * (int)L + 1>(c0, c1)...};
+  ((acc[L].x += wgt * vr[L], acc[L].y += wgt * vi[L]), ...);
 }
 
 template <int W>
