@@ -16,9 +16,10 @@
 //      w x w bins (x - a, y - c), a, c < w, and for such a baseline the kernel
 //      weight of point (x, y, z) is k0[a] k1[c] k2[(z - f2) mod N2].
 //      A column's points sit in rows of 16 lanes: each lane of a row loads
-//      one 32-bit word of the baseline's data and the row shares them with
-//      DPP row broadcasts (and one permute for k2), so every word crosses the
-//      texture path once per row instead of once per lane.
+//      one word of the baseline's record and the value pair of one level,
+//      and the row shares them with DPP row broadcasts (and one permute for
+//      k2), so every word crosses the texture path once per row instead of
+//      once per lane.
 // Columns near the centre of the uv plane see up to ~1e5 baselines, so a
 // block is split into up to w^2 parts (each a range of the (a, c) offsets)
 // sized from its busiest column; a block of one part writes its points with
@@ -28,6 +29,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 
 #include "bb_internal.h"
@@ -40,6 +42,15 @@ namespace {
 constexpr int kPartLoad = 4096;  // target baselines per column and part
 constexpr int kXcds = 8;         // XCDs of the device (workgroups are dealt to them round-robin)
 constexpr int kRun = 64;         // consecutive parts an XCD takes at a time
+
+// f(integral_constant<int, I>) for I = B .. E - 1
+template <int B, int E, class F>
+void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 
 struct SrcRec {  // one sorted baseline (128 bytes); k2 and f2 share the first 48
   float k2[8];
@@ -75,24 +86,15 @@ __device__ __forceinline__ float row_bcast(int v) {
   return __builtin_bit_cast(float, r);
 }
 
-// acc[L] += wgt * level value L, whose real and imaginary words are words
-// 2L and 2L + 1 of the row's level data (c0: words 0..15, c1: words 16..31);
-// levels past the plan's count carry zeros.  All words are broadcast first,
-// each into a register of its own, and then multiplied in: a broadcast into
-// the register a multiply-add has just read costs wait states.
-template <int W>
-__device__ __forceinline__ float level_word(int c0, int c1) {
-  if constexpr (W < 16)
-    return row_bcast<W>(c0);
-  else
-    return row_bcast<W - 16>(c1);
-}
-
+// acc[L] += wgt * level value L, held (re, im) by lane L of the row (levels
+// past the plan's count carry zeros).  All values are broadcast first, each
+// into a register of its own, and then multiplied in: a broadcast into the
+// register a multiply-add has just read costs wait states.
 template <size_t... L>
-__device__ __forceinline__ void add_levels(float2 (&acc)[kMaxLevels], float wgt, int c0, int c1,
+__device__ __forceinline__ void add_levels(float2 (&acc)[kMaxLevels], float wgt, int cr, int ci,
                                            std::index_sequence<L...>) {
-  const float vr[] = {level_word<2 * (int)L>(c0, c1)...};
-  const float vi[] = {level_word<2 * (int)L + 1>(c0, c1)...};
+  const float vr[] = {row_bcast<(int)L>(cr)...};
+  const float vi[] = {row_bcast<(int)L>(ci)...};
   ((acc[L].x += wgt * vr[L], acc[L].y += wgt * vi[L]), ...);
 }
 
@@ -169,7 +171,7 @@ __global__ __launch_bounds__(256) void nufft_block_parts_kernel(NufftGeom g, con
 
 // Persistent over the parts of every column block (part k of block b for
 // part_off[b] <= k < part_off[b + 1]); see the file comment.  LV: the level
-// count rounded up to even.
+// count.
 template <int Z, int LV>
 __global__ __launch_bounds__(256) void nufft_gather_spread_kernel(NufftGeom g, const int* __restrict__ offset,
                                                                   const SrcRec* __restrict__ rec,
@@ -220,12 +222,11 @@ __global__ __launch_bounds__(256) void nufft_gather_spread_kernel(NufftGeom g, c
         const int beg = offset[bin], end = offset[bin + 1];
         // record word of this lane: k2[0..7] (lanes 0-7), f2 (8), k0[a] (9), k1[c] (10)
         const int rw = row_lane < 9 ? row_lane : row_lane == 9 ? 12 + a : row_lane == 10 ? 20 + c : 0;
-        const bool lv0 = row_lane < 2 * n_levels, lv1 = 16 + row_lane < 2 * n_levels;
+        const bool lv_ok = row_lane < n_levels;  // this lane holds level row_lane's value
         for (int p = beg; p < end; ++p) {
           const int m = reinterpret_cast<const int*>(rec + p)[rw];
-          const int* C = reinterpret_cast<const int*>(cv + (int64_t)p * cv_stride);
-          const int c0 = lv0 ? C[row_lane] : 0;
-          const int c1 = LV > 8 && lv1 ? C[16 + row_lane] : 0;
+          const float2 c = lv_ok ? cv[(int64_t)p * cv_stride + row_lane] : make_float2(0.0f, 0.0f);
+          const int cr = __builtin_bit_cast(int, c.x), ci = __builtin_bit_cast(int, c.y);
           const int f2 = __builtin_bit_cast(int, row_bcast<8>(m));
           const float k01 = row_bcast<9>(m) * row_bcast<10>(m);
           int d = z - f2;
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(256) void nufft_gather_spread_kernel(NufftGeom g, c
           const float k2d =
               __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute((row_base + (in ? d : 0)) * 4, m));
           const float wgt = in ? k01 * k2d : 0.0f;
-          add_levels(acc, wgt, c0, c1, std::make_index_sequence<LV>{});
+          add_levels(acc, wgt, cr, ci, std::make_index_sequence<LV>{});
         }
       }
       if (z < N2) {
@@ -310,16 +311,11 @@ hipError_t launch_nufft_spread_gather(const NufftGeom& g, const NufftInst* insts
     return hipGetLastError();
   };
   auto by_levels = [&](auto zc) -> hipError_t {
-    switch ((n_levels + 1) / 2) {
-      case 1: return run(zc, std::integral_constant<int, 2>{});
-      case 2: return run(zc, std::integral_constant<int, 4>{});
-      case 3: return run(zc, std::integral_constant<int, 6>{});
-      case 4: return run(zc, std::integral_constant<int, 8>{});
-      case 5: return run(zc, std::integral_constant<int, 10>{});
-      case 6: return run(zc, std::integral_constant<int, 12>{});
-      case 7: return run(zc, std::integral_constant<int, 14>{});
-      default: return run(zc, std::integral_constant<int, 16>{});
-    }
+    hipError_t r = hipErrorInvalidValue;
+    static_for<1, kMaxLevels + 1>([&](auto lc) {
+      if (decltype(lc)::value == n_levels) r = run(zc, lc);
+    });
+    return r;
   };
   if (Zc == 16) return by_levels(std::integral_constant<int, 16>{});
   if (Zc == 32) return by_levels(std::integral_constant<int, 32>{});
