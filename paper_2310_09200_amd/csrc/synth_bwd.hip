@@ -100,9 +100,10 @@ typedef float bwd_f32x16 __attribute__((ext_vector_type(16)));
 // PART is a template argument and the loop is unrolled whole, so that it holds
 // no branch: its LDS reads then run ahead of the MFMAs instead of each step
 // waiting for its own.
+// The real part takes -Wi' from the staged plane sWn (no negation per step).
 template <int PART>
-__device__ __forceinline__ void h_chunk(bwd_f32x16& h, const float2 (*sW)[65], const float2 (*sM)[65], int blk,
-                                        int lane) {
+__device__ __forceinline__ void h_chunk(bwd_f32x16& h, const float2 (*sW)[65], const float (*sWn)[65],
+                                        const float2 (*sM)[65], int blk, int lane) {
 #pragma unroll
   for (int st = 0; st < 32; ++st) {
     const int kk = 2 * st + (lane >> 5);              // this lane's contraction row (eigenpair)
@@ -110,7 +111,7 @@ __device__ __forceinline__ void h_chunk(bwd_f32x16& h, const float2 (*sW)[65], c
     const float2 m = sM[kk][32 * blk + (lane & 31)];  // B operand: column p = lane % 32 of the half
     if (PART == 0) {
       h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.x, m.x, h, 0, 0, 0);
-      h = __builtin_amdgcn_mfma_f32_32x32x2f32(-w.y, m.y, h, 0, 0, 0);
+      h = __builtin_amdgcn_mfma_f32_32x32x2f32(sWn[lane & 31][kk], m.y, h, 0, 0, 0);
     } else {
       h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.x, m.y, h, 0, 0, 0);
       h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.y, m.x, h, 0, 0, 0);
@@ -278,6 +279,7 @@ __global__ __launch_bounds__(256) void bwd_dw_kernel(const BwdParams P) {
 // pixels t / 32 + 8 j), which evaluate the phases.
 __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
   __shared__ float2 sW[32][65];   // conj(W) for 32 antennas x 64 eigenpairs (+1 pad: column reads)
+  __shared__ float sWn[32][65];   // its negated imaginary parts
   __shared__ float2 sM[64][65];   // M for 64 eigenpairs x 64 pixels; then H re / im [2][64 p][33] floats
   __shared__ double sP[3][64];    // the chunk's pixel coordinates
   __shared__ double sX[32][4];    // the tile's scaled antenna positions
@@ -342,7 +344,10 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) sM[4 * j + (t >> 6)][t & 63] = mnext[j];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) sW[tl][tp + 8 * j] = wnext[j];
+      for (int j = 0; j < 8; ++j) {
+        sW[tl][tp + 8 * j] = wnext[j];
+        sWn[tl][tp + 8 * j] = -wnext[j].y;
+      }
       if (kq == 0 && t < 192) sP[t >> 6][t & 63] = pnext;
       __syncthreads();
       // the next step: the chunk's next slice, else the next chunk's first
@@ -350,9 +355,9 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
       const int64_t npc = last ? pc + 64 : pc;
       if (npc < p1) load_step(npc, last ? 0 : 64 * (kq + 1));  // workgroup-uniform
       if (part == 0)
-        h_chunk<0>(acc, sW, sM, blk, lane);
+        h_chunk<0>(acc, sW, sWn, sM, blk, lane);
       else
-        h_chunk<1>(acc, sW, sM, blk, lane);
+        h_chunk<1>(acc, sW, sWn, sM, blk, lane);
       __syncthreads();
     }
     // register r of lane q holds H at (l, p) = (8 (r / 4) + 4 (q / 32) + r % 4, 32 blk + q % 32)
