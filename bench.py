@@ -530,6 +530,7 @@ def measure_c1(args, torch, ctx, modes, workers):
     _, items, pre_ms = gpu_eigenpairs(torch, ctx, w, [inst], 64, 4)
     _, x, wl, W, d, lev = items[0]
     ref_img, dt, oprods = oracle_leg(items, w.pix, 5, workers)
+    x = torch.as_tensor(x).to(ctx.device)  # inputs resident on the device, as in the timed batched launches
     prods = float(x.shape[0]) * int((lev >= 0).sum().item()) * w.n_pix
     out = {}
     for m in modes:
