@@ -204,10 +204,11 @@ __global__ __launch_bounds__(256) void bwd_dw_kernel(const BwdParams P) {
     const int64_t p = pc + (t & 63);
     const bool p_ok = p < p1;
     const int64_t pq = p_ok ? p : p1 - 1;
+    const int64_t r0 = (int64_t)(k0 + (t >> 6)) * P.n_pix + pq, st4 = 4 * P.n_pix;  // rows advance by 4 per j
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const bool k_ok = j < 8 || two;
-      const int64_t e = (int64_t)(k0 + (k_ok ? 4 * j + (t >> 6) : 0)) * P.n_pix + pq;
+      const int64_t e = k_ok ? r0 + j * st4 : pq;
       const float er = Er[e], ei = Ei[e];
       mnext[j] = (p_ok && k_ok) ? make_float2(er, ei) : make_float2(0.0f, 0.0f);
     }
@@ -284,7 +285,7 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
   __shared__ double sP[3][64];    // the chunk's pixel coordinates
   __shared__ double sX[32][4];    // the tile's scaled antenna positions
   __shared__ double sh[3][256];
-  __shared__ int sPerm[kMaxEig];  // staged eigenpair -> the caller's column of W
+  __shared__ int sOff[kMaxEig];   // staged eigenpair -> offset of its column of W (src * L), -1 if none
   const InstDesc& D = *P.desc;
   const int l0 = blockIdx.x * 32, s = blockIdx.y;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -313,10 +314,11 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
     const int64_t p = pc + (t & 63);
     const bool p_ok = p < p1;
     const int64_t pq = p_ok ? p : p1 - 1;
+    const int64_t r0 = (int64_t)(kc + (t >> 6)) * P.n_pix + pq, st4 = 4 * P.n_pix;  // rows advance by 4 per j
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int k = kc + 4 * j + (t >> 6);
-      const int64_t e = (int64_t)(k < K_pad ? k : 0) * P.n_pix + pq;
+      const int64_t e = k < K_pad ? r0 + j * st4 : pq;
       const float er = Er[e], ei = Ei[e];
       mnext[j] = (p_ok && k < K_pad) ? make_float2(er, ei) : make_float2(0.0f, 0.0f);
     }
@@ -324,15 +326,21 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int k = kc + tp + 8 * j;
-      const int src = k < K_pad ? sPerm[k] : -1;
-      const bool ok = l_ok && src >= 0;
-      const float* w = Wf + 2 * ((int64_t)(ok ? src : 0) * P.L + (l_ok ? l0 + tl : 0));
-      const float wr = w[0], wi = w[1];
+      const int off = sOff[k];
+      const bool ok = l_ok && off >= 0;
+      const float* w = Wf + 2 * ((int64_t)(ok ? off : 0) + (l_ok ? l0 + tl : 0));
+      float wr = w[0], wi = w[1];
+      // keep the loads unconditional (a load the compiler moves under `ok`
+      // becomes a branch per element)
+      asm volatile("" : "+v"(wr), "+v"(wi));
       wnext[j] = ok ? make_float2(wr, -wi) : make_float2(0.0f, 0.0f);
     }
     if (kc == 0 && t < 192) pnext = p_ok ? P.pix[pq + (t >> 6) * P.pix_ld] : 0.0;
   };
-  for (int k = t; k < K_pad; k += 256) sPerm[k] = D.perm[k];
+  for (int k = t; k < 64 * n_kc; k += 256) {  // 64 n_kc <= kMaxEig
+    const int src = k < K_pad ? D.perm[k] : -1;
+    sOff[k] = src >= 0 ? src * P.L : -1;
+  }
   __syncthreads();
   load_step(p0, 0);
   double gx = 0.0, gy = 0.0, gz = 0.0;
@@ -465,10 +473,11 @@ __global__ __launch_bounds__(256) void bwd_fused_kernel(const BwdParams P) {
     const int64_t p = pc + pp;
     const bool p_ok = p < p1;
     const int64_t pq = p_ok ? p : p1 - 1;
+    const int64_t r0 = (int64_t)(t >> 6) * P.n_pix + pq, st4 = 4 * P.n_pix;  // rows advance by 4 per j
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int kk = 4 * j + (t >> 6);
-      const int64_t e = (int64_t)(kk < K_pad ? kk : 0) * P.n_pix + pq;
+      const int64_t e = kk < K_pad ? r0 + j * st4 : pq;
       const float er = Er[e], ei = Ei[e];
       mnext[j] = (p_ok && kk < K_pad) ? make_float2(er, ei) : make_float2(0.0f, 0.0f);
     }
