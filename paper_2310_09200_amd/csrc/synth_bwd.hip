@@ -139,6 +139,27 @@ __device__ __forceinline__ void h_chunk_w(bwd_f32x16& h, const float2 (*sW)[65],
   }
 }
 
+// h_chunk over conj(W) staged once for every eigenpair of the instance (rows
+// of WS, this slice's columns kc .. kc + 63); the real part negates Wi' per
+// step.
+template <int PART, int WS>
+__device__ __forceinline__ void h_chunk_all(bwd_f32x16& h, const float2 (*sW)[WS], int kc, const float2 (*sM)[65],
+                                            int blk, int lane) {
+#pragma unroll
+  for (int st = 0; st < 32; ++st) {
+    const int kk = 2 * st + (lane >> 5);
+    const float2 w = sW[lane & 31][kc + kk];
+    const float2 m = sM[kk][32 * blk + (lane & 31)];
+    if (PART == 0) {
+      h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.x, m.x, h, 0, 0, 0);
+      h = __builtin_amdgcn_mfma_f32_32x32x2f32(-w.y, m.y, h, 0, 0, 0);
+    } else {
+      h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.x, m.y, h, 0, 0, 0);
+      h = __builtin_amdgcn_mfma_f32_32x32x2f32(w.y, m.x, h, 0, 0, 0);
+    }
+  }
+}
+
 // One chunk's dW block of a wave: dW[l][k] += sum over the chunk's 64 pixels
 // of B[p][l] M[k][p] for eigenpairs 32 blk .. 32 blk + 31, real part (PART 0:
 // Br Mr - Bi Mi) or imaginary part (PART 1: Br Mi + Bi Mr).
@@ -277,7 +298,10 @@ __global__ __launch_bounds__(256) void bwd_dw_kernel(const BwdParams P) {
 // w / 2, real part (w even: Wr Mr - Wi' Mi with W' = conj W) or imaginary part
 // (w odd: Wr' Mi + Wi' Mr).  After a chunk's last slice the blocks go through
 // LDS (pixel-major, rows padded to 33) to the threads that own (antenna t % 32,
-// pixels t / 32 + 8 j), which evaluate the phases.
+// pixels t / 32 + 8 j), which evaluate the phases.  WONCE (K_alloc <= 128):
+// conj(W) of all the instance's eigenpairs is staged once, and the steps
+// stage only M.
+template <bool WONCE>
 __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
   __shared__ float2 sW[32][65];   // conj(W) for 32 antennas x 64 eigenpairs (+1 pad: column reads)
   __shared__ float sWn[32][65];   // its negated imaginary parts
@@ -286,6 +310,7 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
   __shared__ double sX[32][4];    // the tile's scaled antenna positions
   __shared__ double sh[3][256];
   __shared__ int sOff[kMaxEig];   // staged eigenpair -> offset of its column of W (src * L), -1 if none
+  __shared__ float2 sWall[32][129];  // WONCE: conj(W) for 32 antennas x 128 eigenpairs (+1 pad)
   const InstDesc& D = *P.desc;
   const int l0 = blockIdx.x * 32, s = blockIdx.y;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -324,7 +349,7 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
     }
     const bool l_ok = l0 + tl < P.L;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < 8 && !WONCE; ++j) {
       const int k = kc + tp + 8 * j;
       const int off = sOff[k];
       const bool ok = l_ok && off >= 0;
@@ -337,9 +362,22 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
     }
     if (kc == 0 && t < 192) pnext = p_ok ? P.pix[pq + (t >> 6) * P.pix_ld] : 0.0;
   };
-  for (int k = t; k < 64 * n_kc; k += 256) {  // 64 n_kc <= kMaxEig
-    const int src = k < K_pad ? D.perm[k] : -1;
-    sOff[k] = src >= 0 ? src * P.L : -1;
+  if constexpr (WONCE) {
+    for (int i = t; i < 32 * 128; i += 256) {
+      const int ll = i & 31, kk = i >> 5;  // a wave reads 32 consecutive antennas of two columns of W
+      const int src = kk < K_pad ? D.perm[kk] : -1;
+      float2 wv = make_float2(0.0f, 0.0f);
+      if (l0 + ll < P.L && src >= 0) {
+        const float* w = Wf + 2 * ((int64_t)src * P.L + l0 + ll);
+        wv = make_float2(w[0], -w[1]);
+      }
+      sWall[ll][kk] = wv;
+    }
+  } else {
+    for (int k = t; k < 64 * n_kc; k += 256) {  // 64 n_kc <= kMaxEig
+      const int src = k < K_pad ? D.perm[k] : -1;
+      sOff[k] = src >= 0 ? src * P.L : -1;
+    }
   }
   __syncthreads();
   load_step(p0, 0);
@@ -351,10 +389,12 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
     for (int kq = 0; kq < n_kc; ++kq) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) sM[4 * j + (t >> 6)][t & 63] = mnext[j];
+      if constexpr (!WONCE) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        sW[tl][tp + 8 * j] = wnext[j];
-        sWn[tl][tp + 8 * j] = -wnext[j].y;
+        for (int j = 0; j < 8; ++j) {
+          sW[tl][tp + 8 * j] = wnext[j];
+          sWn[tl][tp + 8 * j] = -wnext[j].y;
+        }
       }
       if (kq == 0 && t < 192) sP[t >> 6][t & 63] = pnext;
       __syncthreads();
@@ -362,10 +402,17 @@ __global__ __launch_bounds__(256) void bwd_dx_kernel(const BwdParams P) {
       const bool last = kq + 1 == n_kc;
       const int64_t npc = last ? pc + 64 : pc;
       if (npc < p1) load_step(npc, last ? 0 : 64 * (kq + 1));  // workgroup-uniform
-      if (part == 0)
-        h_chunk<0>(acc, sW, sWn, sM, blk, lane);
-      else
-        h_chunk<1>(acc, sW, sWn, sM, blk, lane);
+      if constexpr (WONCE) {
+        if (part == 0)
+          h_chunk_all<0, 129>(acc, sWall, 64 * kq, sM, blk, lane);
+        else
+          h_chunk_all<1, 129>(acc, sWall, 64 * kq, sM, blk, lane);
+      } else {
+        if (part == 0)
+          h_chunk<0>(acc, sW, sWn, sM, blk, lane);
+        else
+          h_chunk<1>(acc, sW, sWn, sM, blk, lane);
+      }
       __syncthreads();
     }
     // register r of lane q holds H at (l, p) = (8 (r / 4) + 4 (q / 32) + r % 4, 32 blk + q % 32)
@@ -627,7 +674,10 @@ hipError_t launch_backward(const BwdParams& p, hipStream_t s) {
   hipLaunchKernelGGL(bwd_dw_kernel, dim3(p.L_pad / 32, (p.K_alloc + 63) / 64, p.n_split), dim3(256), 0, s, p);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(bwd_dx_kernel, dim3(p.L_pad / 32, p.n_split), dim3(256), 0, s, p);
+  if (p.K_alloc <= 128)
+    hipLaunchKernelGGL(bwd_dx_kernel<true>, dim3(p.L_pad / 32, p.n_split), dim3(256), 0, s, p);
+  else
+    hipLaunchKernelGGL(bwd_dx_kernel<false>, dim3(p.L_pad / 32, p.n_split), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 
