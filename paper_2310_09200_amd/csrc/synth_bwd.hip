@@ -637,7 +637,8 @@ __global__ __launch_bounds__(256) void bwd_reduce_kernel(const BwdParams P, floa
   const int K_pad = P.dyn->K_pad;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (int64_t)P.L * K_pad) {
-    const int l = (int)(idx % P.L), k = (int)(idx / P.L);
+    // consecutive threads take consecutive eigenpairs: their partials are adjacent
+    const int k = (int)(idx % K_pad), l = (int)(idx / K_pad);
     const int src = D.perm[k];
     if (src >= 0) {
       double re = 0.0, im = 0.0;
